@@ -1,0 +1,193 @@
+/*
+ * sbs.h - boundary-pixel SAD stereo disparity on AMD Instinct MI355X (gfx950).
+ *
+ * The operation (Mukherjee & Guddeti, arXiv 2001.07809, Sec. III "Disparity
+ * Measurement of Boundary Pixels", with the winner-takes-all rule of Sec. II
+ * and the O(N_b w^2 d) cost of the sequential complexity analysis):
+ * for a rectified stereo pair the match of a left pixel lies on the same row
+ * of the right image. Only the listed ("boundary") pixels are evaluated. For
+ * list entry k, with p = idx[k], x = p mod W, y = p div W, r = (block-1)/2:
+ *
+ *   cost(d) = sum_{j=-r..r} sum_{i=-r..r} sum_{c<C}
+ *             | L[cy(y+j)][cx(x+i)][c] - R[cy(y+j)][cx(x-d+i)][c] |
+ *
+ * for every d in 0..dmax, where cx and cy clamp to the image (replicate
+ * padding, each coordinate on its own). out_disp[k] is the smallest d with the
+ * least cost and out_cost[k] is that cost. Results are exact integers. They
+ * depend only on (images, x, y, block, dmax), never on the rest of the list,
+ * its order or batching.
+ *
+ * Conventions for every entry point:
+ *  - Images are 8-bit, interleaved HWC (C = 1 gray or C = 3 RGB), rows
+ *    pitch_bytes apart, pitch_bytes >= W*C. Image, list and output pointers
+ *    are DEVICE memory owned by the caller. The library never frees them and
+ *    keeps no pointer to them after the enqueued work completes.
+ *  - Calls are asynchronous and ordered on `stream` (a hipStream_t; NULL is
+ *    the null stream). A call returns once the work is enqueued. The caller
+ *    keeps buffers alive until the stream reaches that point.
+ *  - Arguments are checked on the host before any device work. The status is
+ *    returned, never thrown; sbs_last_error() gives the message for the last
+ *    non-OK status on the calling thread.
+ *  - Indices must be < W*H. The kernels never read out of bounds. An index
+ *    >= W*H yields out_disp 255 and out_cost 0xFFFFFFFF and sets a device
+ *    error word that sbs_check_indices() reports as SBS_ERR_INDEX_RANGE.
+ *  - Duplicated indices are allowed; n = 0 is a successful no-op.
+ */
+#ifndef SBS_H
+#define SBS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SBS_ABI_VERSION 1
+
+typedef enum {
+  SBS_OK = 0,
+  SBS_ERR_INVALID_ARG = 1, /* NULL pointer with n > 0, W or H < 1, C not 1 or 3,
+                              pitch < W*C, block even or < 1, dmax < 0 or > 255,
+                              n < 0, workspace too small for an explicit workspace */
+  SBS_ERR_UNSUPPORTED = 2, /* block > SBS_MAX_BLOCK, or no gfx950 device */
+  SBS_ERR_WORKSPACE = 3,   /* the library could not allocate its own workspace */
+  SBS_ERR_HIP = 4,         /* a HIP runtime call failed; see sbs_last_error() */
+  SBS_ERR_INDEX_RANGE = 5  /* an index >= W*H was seen (sbs_check_indices) */
+} sbs_status;
+
+/* Largest supported block (window side). The cost of a window must fit 24
+ * bits: block^2 * C * 255 < 2^24. */
+#define SBS_MAX_BLOCK 127
+
+/*
+ * Single frame. Computes out_disp[k] (and out_cost[k] unless out_cost is
+ * NULL) for the n listed pixels.
+ *   left, right    device, HWC u8, W x H x C, rows pitch_bytes apart
+ *   boundary_idx   device, n entries, raster index y*W + x (any order)
+ *   block          odd window side, 1..SBS_MAX_BLOCK
+ *   dmax           largest disparity searched, 0..255 (dmax+1 candidates)
+ *   out_disp       device, n bytes
+ *   out_cost       device, n u32, or NULL
+ *   workspace      device scratch of at least sbs_workspace_bytes() for this
+ *                  one frame, or NULL with workspace_bytes 0 for a workspace
+ *                  the library allocates, keeps and grows itself (that path
+ *                  may allocate and is not safe under stream capture)
+ *   stream         hipStream_t or NULL
+ */
+int sbs_sad_disparity(const uint8_t* left, const uint8_t* right, int32_t W, int32_t H, int32_t C,
+                      int64_t pitch_bytes, const uint32_t* boundary_idx, int64_t n, int32_t block,
+                      int32_t dmax, uint8_t* out_disp, uint32_t* out_cost, void* workspace,
+                      size_t workspace_bytes, void* stream);
+
+/* One frame of a batch. Field meanings as for sbs_sad_disparity. Host memory. */
+typedef struct {
+  const uint8_t* left;
+  const uint8_t* right;
+  int32_t W, H, C;
+  int64_t pitch_bytes;
+  const uint32_t* boundary_idx;
+  int64_t n;
+  int32_t block, dmax;
+  uint8_t* out_disp;
+  uint32_t* out_cost;
+} sbs_frame;
+
+/* Device workspace bytes needed by sbs_sad_disparity_batched for these
+ * frames (and by sbs_sad_disparity for a single frame). 0 on invalid frames. */
+size_t sbs_workspace_bytes(const sbs_frame* frames, int32_t nframes);
+
+/*
+ * Many frames in one pass: the per-frame work of every frame goes into one
+ * work queue that a single persistent kernel drains (uneven boundary counts
+ * and frame sizes balance across the GPU). Each frame's outputs equal what
+ * sbs_sad_disparity gives for it alone.
+ *   frames     host array of nframes descriptors (read during the call only;
+ *              the descriptors travel to the device inside kernel arguments)
+ *   workspace  device, >= sbs_workspace_bytes(frames, nframes), or NULL / 0
+ *              for a library-managed workspace (not capture safe)
+ * With an explicit workspace the call performs no allocation, no host
+ * synchronisation and no copy from host memory, so it can be captured into a
+ * hipGraph and replayed (replays recompute from the frames' current contents).
+ */
+int sbs_sad_disparity_batched(const sbs_frame* frames, int32_t nframes, void* workspace,
+                              size_t workspace_bytes, void* stream);
+
+/*
+ * Debug check: synchronises `stream`, reads the device error word of
+ * `workspace` (or of the library-managed workspace when NULL), clears it, and
+ * returns SBS_ERR_INDEX_RANGE if any call since the last check saw an index
+ * >= W*H, else SBS_OK. frames/nframes are accepted for symmetry and unused.
+ */
+int sbs_check_indices(const sbs_frame* frames, int32_t nframes, void* workspace, void* stream);
+
+/*
+ * Autotuner: times each tile plan (columns per lane, disparities per chunk,
+ * rows per tile, persistent grid size) on these frames, keeps the fastest, and
+ * stores it under the key (arch, W, H, C, block, dmax, density bucket) in a
+ * JSON cache at cache_path (created or updated; NULL: in memory only). Later
+ * calls with a matching key use the stored plan. Synchronous. Outputs of the
+ * frames are written as a side effect.
+ */
+int sbs_tune(const sbs_frame* frames, int32_t nframes, const char* cache_path);
+
+/* Loads a JSON tuning cache written by sbs_tune. Returns SBS_OK or SBS_ERR_INVALID_ARG. */
+int sbs_load_tuning(const char* cache_path);
+
+/* Message for the last non-OK status on the calling thread ("" if none). */
+const char* sbs_last_error(void);
+
+/* SBS_ABI_VERSION of the loaded library. */
+int sbs_abi_version(void);
+
+/*
+ * Reference path: the same operation by direct brute force (one wavefront
+ * per pixel, lanes over disparities, images read in place with clamped
+ * coordinates), sharing no kernel with the tiled path. For cross-checks and
+ * for parity tests; no workspace. Arguments as for sbs_sad_disparity.
+ */
+int sbs_sad_disparity_ref(const uint8_t* left, const uint8_t* right, int32_t W, int32_t H, int32_t C,
+                          int64_t pitch_bytes, const uint32_t* boundary_idx, int64_t n, int32_t block,
+                          int32_t dmax, uint8_t* out_disp, uint32_t* out_cost, void* stream);
+
+/*
+ * Per-frame launch path for the batching comparison: runs the frames one at a
+ * time, each as its own sequence of launches on `stream` (no shared queue).
+ * Same outputs as sbs_sad_disparity_batched. Workspace as for the batched call.
+ */
+int sbs_sad_disparity_per_frame(const sbs_frame* frames, int32_t nframes, void* workspace,
+                                size_t workspace_bytes, void* stream);
+
+/*
+ * Plan control (used by the tuner and the benchmark). A plan is
+ * (cols_per_lane, chunk, tile_rows, waves_per_cu); 0 in a field means
+ * "automatic". sbs_set_plan forces a plan for subsequent calls (all fields 0
+ * restores automatic choice); sbs_get_plan reports the plan the library would
+ * use for a frame. Valid cols_per_lane: 4; chunk: 8, 16; tile_rows: 8..64;
+ * waves_per_cu: 1..16.
+ */
+typedef struct {
+  int32_t cols_per_lane;
+  int32_t chunk;
+  int32_t tile_rows;
+  int32_t waves_per_cu;
+} sbs_plan;
+
+int sbs_set_plan(const sbs_plan* plan);
+int sbs_get_plan(const sbs_frame* frame, sbs_plan* plan);
+
+/*
+ * Kernel timing (for the benchmark). While enabled, every call records a pair
+ * of HIP events on its stream around each launch of the tile kernel (the
+ * dominant kernel). sbs_kernel_times waits for the recorded pairs, writes up
+ * to `cap` durations in milliseconds to `ms` (in launch order), releases them
+ * and returns how many pairs there were. Not for use under stream capture.
+ */
+int sbs_kernel_timing(int32_t enable);
+int32_t sbs_kernel_times(float* ms, int32_t cap);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SBS_H */

@@ -1,0 +1,597 @@
+// C-ABI of libsbs: argument checks, workspace layout, plan choice, launch
+// sequences and the autotuner. The operation is defined in include/sbs.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <mutex>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "../../include/sbs.h"
+#include "sbs_internal.h"
+
+namespace sbs {
+hipError_t launch_put_desc(FrameDev* table, const FrameDev* host, int nframes, hipStream_t s);
+hipError_t launch_prologue(const FrameDev* table, int f0, int nf, int max_rows, int max_rbjobs, WsHeader* hdr,
+                           hipStream_t s);
+hipError_t launch_finalize(const FrameDev* table, int f0, int nf, hipStream_t s);
+hipError_t launch_tile_grid(const FrameDev* table, int fi, int64_t nitems, int chunk, hipStream_t s);
+hipError_t launch_tile_persistent(const FrameDev* table, int nframes, int64_t total, int chunk, int grid,
+                                  WsHeader* hdr, hipStream_t s);
+hipError_t launch_ref(const uint8_t* L, const uint8_t* R, int W, int H, int C, int64_t pitch, const uint32_t* idx,
+                      int64_t n, int r, int dmax, uint8_t* od, uint32_t* oc, uint32_t* err, hipStream_t s);
+}  // namespace sbs
+
+using namespace sbs;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int status, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return status;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  return fail(SBS_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// ---------------------------------------------------------------- device info
+struct DevInfo {
+  bool checked = false;
+  bool ok = false;
+  int cus = 0;
+  std::string arch;
+};
+std::mutex g_mu;
+std::map<int, DevInfo> g_dev;
+
+int device_check(int* cus) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  std::lock_guard<std::mutex> lk(g_mu);
+  DevInfo& d = g_dev[dev];
+  if (!d.checked) {
+    hipDeviceProp_t p;
+    e = hipGetDeviceProperties(&p, dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+    d.arch = p.gcnArchName;
+    d.cus = p.multiProcessorCount;
+    d.ok = d.arch.rfind("gfx950", 0) == 0;
+    d.checked = true;
+  }
+  if (!d.ok) return fail(SBS_ERR_UNSUPPORTED, "device %d is %s, not gfx950", dev, d.arch.c_str());
+  if (cus) *cus = d.cus;
+  return SBS_OK;
+}
+
+// ---------------------------------------------------------------- plans
+struct Plan {
+  int cpl = 4, chunk = 16, ty = 32, wpc = 8;
+};
+bool g_forced = false;
+Plan g_forced_plan;
+std::map<std::string, Plan> g_tuned;
+
+int density_bucket(const sbs_frame& f) {
+  double rho = (double)f.n / ((double)f.W * f.H);
+  int b = (int)(rho * 20.0);  // 5% buckets
+  return b > 20 ? 20 : b;
+}
+
+std::string plan_key(const sbs_frame& f) {
+  std::ostringstream o;
+  o << "gfx950/" << f.W << "x" << f.H << "x" << f.C << "/b" << f.block << "/d" << f.dmax << "/rho"
+    << density_bucket(f);
+  return o.str();
+}
+
+Plan default_plan(const sbs_frame& f) {
+  Plan p;
+  p.chunk = (f.dmax + 1) <= 8 ? 8 : 16;
+  p.ty = 32;
+  p.wpc = 8;
+  return p;
+}
+
+Plan choose_plan(const sbs_frame& f) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (g_forced) {
+    Plan p = default_plan(f);
+    if (g_forced_plan.cpl) p.cpl = g_forced_plan.cpl;
+    if (g_forced_plan.chunk) p.chunk = g_forced_plan.chunk;
+    if (g_forced_plan.ty) p.ty = g_forced_plan.ty;
+    if (g_forced_plan.wpc) p.wpc = g_forced_plan.wpc;
+    return p;
+  }
+  auto it = g_tuned.find(plan_key(f));
+  if (it != g_tuned.end()) return it->second;
+  return default_plan(f);
+}
+
+// ---------------------------------------------------------------- validation + layout
+int validate(const sbs_frame& f, int i) {
+  if (f.n < 0) return fail(SBS_ERR_INVALID_ARG, "frame %d: n < 0", i);
+  if (f.n > INT32_MAX) return fail(SBS_ERR_INVALID_ARG, "frame %d: n > 2^31-1", i);
+  if (f.W < 1 || f.H < 1) return fail(SBS_ERR_INVALID_ARG, "frame %d: W and H must be >= 1", i);
+  if ((int64_t)f.W * f.H > INT32_MAX) return fail(SBS_ERR_INVALID_ARG, "frame %d: W*H >= 2^31", i);
+  if (f.C != 1 && f.C != 3) return fail(SBS_ERR_INVALID_ARG, "frame %d: C must be 1 or 3", i);
+  if (f.pitch_bytes < (int64_t)f.W * f.C) return fail(SBS_ERR_INVALID_ARG, "frame %d: pitch < W*C", i);
+  if (f.block < 1 || (f.block % 2) == 0) return fail(SBS_ERR_INVALID_ARG, "frame %d: block must be odd and >= 1", i);
+  if (f.dmax < 0 || f.dmax > 255) return fail(SBS_ERR_INVALID_ARG, "frame %d: dmax must be in [0, 255]", i);
+  if (f.n > 0 && (!f.left || !f.right || !f.boundary_idx || !f.out_disp))
+    return fail(SBS_ERR_INVALID_ARG, "frame %d: NULL pointer with n > 0", i);
+  if (f.block > SBS_MAX_BLOCK) return fail(SBS_ERR_UNSUPPORTED, "frame %d: block %d > %d", i, f.block, SBS_MAX_BLOCK);
+  return SBS_OK;
+}
+
+struct FrameLayout {
+  size_t map_off, keys_off, lp_off, rp_off, rb_off, end;
+  int lpw, rpw, ph, roff, rbw;
+};
+
+FrameLayout frame_layout(const sbs_frame& f, size_t base) {
+  FrameLayout L;
+  const int r = (f.block - 1) / 2;
+  int roff = f.dmax + kRSlack;
+  while ((roff & 3) != 3) ++roff;
+  L.roff = roff;
+  L.lpw = (int)align_up((size_t)f.W + kSpan, 64);
+  L.rpw = (int)align_up((size_t)f.W + kSpan + roff + 4, 64);
+  L.ph = f.H + 2 * r;
+  const int groups = (f.W + 63) / 64;
+  L.rbw = (groups + 63) / 64;
+  size_t o = align_up(base, 256);
+  L.map_off = o; o = align_up(o + (size_t)f.W * f.H * 4, 256);
+  L.keys_off = o; o = align_up(o + (size_t)std::max<int64_t>(f.n, 1) * 4, 256);
+  L.lp_off = o; o = align_up(o + (size_t)L.lpw * L.ph * 4, 256);
+  L.rp_off = o; o = align_up(o + (size_t)L.rpw * L.ph * 4, 256);
+  L.rb_off = o; o = align_up(o + (size_t)f.H * L.rbw * 8, 256);
+  L.end = o;
+  return L;
+}
+
+size_t table_bytes(int nframes) { return align_up(sizeof(FrameDev) * (size_t)std::max(nframes, 1), 256); }
+
+size_t total_bytes(const sbs_frame* frames, int nframes) {
+  size_t o = kHeaderBytes + table_bytes(nframes);
+  for (int i = 0; i < nframes; ++i) o = frame_layout(frames[i], o).end;
+  return o;
+}
+
+// ---------------------------------------------------------------- library-managed workspace
+struct OwnWs {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+};
+std::map<int, OwnWs> g_ws;
+
+int own_workspace(size_t need, void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  std::lock_guard<std::mutex> lk(g_mu);
+  OwnWs& w = g_ws[dev];
+  if (w.bytes < need) {
+    if (w.ptr) {
+      e = hipDeviceSynchronize();
+      if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+      hipFree(w.ptr);
+      w.ptr = nullptr;
+      w.bytes = 0;
+    }
+    size_t sz = std::max(need, (size_t)1 << 20);
+    e = hipMalloc(&w.ptr, sz);
+    if (e != hipSuccess) return fail(SBS_ERR_WORKSPACE, "hipMalloc(%zu): %s", sz, hipGetErrorString(e));
+    e = hipMemset(w.ptr, 0, kHeaderBytes);
+    if (e != hipSuccess) return hip_fail(e, "hipMemset");
+    w.bytes = sz;
+  }
+  *out = w.ptr;
+  return SBS_OK;
+}
+
+void* own_workspace_ptr() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto it = g_ws.find(dev);
+  return it == g_ws.end() ? nullptr : it->second.ptr;
+}
+
+// ---------------------------------------------------------------- kernel timing
+bool g_timing = false;
+std::vector<std::pair<hipEvent_t, hipEvent_t>> g_events;
+
+void timing_begin(hipStream_t s, hipEvent_t* a) {
+  *a = nullptr;
+  if (!g_timing) return;
+  if (hipEventCreate(a) != hipSuccess) { *a = nullptr; return; }
+  hipEventRecord(*a, s);
+}
+
+void timing_end(hipStream_t s, hipEvent_t a) {
+  if (!a) return;
+  hipEvent_t b;
+  if (hipEventCreate(&b) != hipSuccess) { hipEventDestroy(a); return; }
+  hipEventRecord(b, s);
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_events.emplace_back(a, b);
+}
+
+// ---------------------------------------------------------------- run
+enum Mode { kSingle = 0, kBatched = 1, kPerFrame = 2 };
+
+int run(const sbs_frame* frames, int nframes, void* workspace, size_t ws_bytes, hipStream_t s, Mode mode) {
+  if (nframes < 0 || (nframes > 0 && !frames)) return fail(SBS_ERR_INVALID_ARG, "bad frame array");
+  for (int i = 0; i < nframes; ++i) {
+    int st = validate(frames[i], i);
+    if (st != SBS_OK) return st;
+  }
+  int64_t live = 0;
+  for (int i = 0; i < nframes; ++i) live += frames[i].n;
+  if (live == 0) return SBS_OK;
+  int cus = 0;
+  int st = device_check(&cus);
+  if (st != SBS_OK) return st;
+  const size_t need = total_bytes(frames, nframes);
+  if (workspace) {
+    if (ws_bytes < need)
+      return fail(SBS_ERR_INVALID_ARG, "workspace of %zu bytes < %zu needed", ws_bytes, need);
+  } else {
+    if (ws_bytes != 0) return fail(SBS_ERR_INVALID_ARG, "workspace NULL with nonzero size");
+    st = own_workspace(need, &workspace);
+    if (st != SBS_OK) return st;
+  }
+  char* base = (char*)workspace;
+  WsHeader* hdr = (WsHeader*)base;
+  FrameDev* table = (FrameDev*)(base + kHeaderBytes);
+
+  // One plan per call (from the first frame with work): the persistent kernel is one instance.
+  int lead = 0;
+  while (lead < nframes && frames[lead].n == 0) ++lead;
+  const Plan plan = choose_plan(frames[lead]);
+
+  std::vector<FrameDev> host((size_t)nframes);
+  size_t off = kHeaderBytes + table_bytes(nframes);
+  int64_t items = 0;
+  int max_rows = 1, max_rbjobs = 1;
+  for (int i = 0; i < nframes; ++i) {
+    const sbs_frame& f = frames[i];
+    FrameLayout L = frame_layout(f, off);
+    off = L.end;
+    FrameDev& d = host[(size_t)i];
+    std::memset(&d, 0, sizeof d);
+    d.left = f.left;
+    d.right = f.right;
+    d.idx = f.boundary_idx;
+    d.out_disp = f.out_disp;
+    d.out_cost = f.out_cost;
+    d.map = (int32_t*)(base + L.map_off);
+    d.keys = (uint32_t*)(base + L.keys_off);
+    d.lp = (uint32_t*)(base + L.lp_off);
+    d.rp = (uint32_t*)(base + L.rp_off);
+    d.rowbits = (uint64_t*)(base + L.rb_off);
+    d.pitch = f.pitch_bytes;
+    d.n = f.n;
+    d.W = f.W; d.H = f.H; d.C = f.C;
+    d.r = (f.block - 1) / 2;
+    d.dmax = f.dmax;
+    d.lpw = L.lpw; d.rpw = L.rpw; d.ph = L.ph; d.roff = L.roff; d.rbw = L.rbw;
+    d.txo = (kSpan - 2 * d.r) & ~3;
+    d.ty = plan.ty;
+    d.ntx = (f.W + d.txo - 1) / d.txo;
+    d.nty = (f.H + d.ty - 1) / d.ty;
+    d.chunk = plan.chunk;
+    d.nch = (f.dmax + 1 + plan.chunk - 1) / plan.chunk;
+    d.item_base = items;
+    d.nitems = f.n > 0 ? (int64_t)d.ntx * d.nty * d.nch : 0;
+    items += d.nitems;
+    max_rows = std::max(max_rows, L.ph);
+    max_rbjobs = std::max(max_rbjobs, f.H * L.rbw);
+  }
+  hipError_t e = launch_put_desc(table, host.data(), nframes, s);
+  if (e != hipSuccess) return hip_fail(e, "descriptor upload");
+  if (mode == kPerFrame || mode == kSingle) {
+    for (int i = 0; i < nframes; ++i) {
+      if (frames[i].n == 0) continue;
+      e = launch_prologue(table, i, 1, host[(size_t)i].ph, frames[i].H * host[(size_t)i].rbw, hdr, s);
+      if (e != hipSuccess) return hip_fail(e, "prologue");
+      hipEvent_t ev;
+      timing_begin(s, &ev);
+      e = launch_tile_grid(table, i, host[(size_t)i].nitems, plan.chunk, s);
+      timing_end(s, ev);
+      if (e != hipSuccess) return hip_fail(e, "tile kernel");
+      e = launch_finalize(table, i, 1, s);
+      if (e != hipSuccess) return hip_fail(e, "finalize");
+    }
+  } else {
+    e = launch_prologue(table, 0, nframes, max_rows, max_rbjobs, hdr, s);
+    if (e != hipSuccess) return hip_fail(e, "prologue");
+    int64_t grid = (int64_t)cus * plan.wpc;
+    if (grid > items) grid = items;
+    hipEvent_t ev;
+    timing_begin(s, &ev);
+    e = launch_tile_persistent(table, nframes, items, plan.chunk, (int)std::max<int64_t>(grid, 1), hdr, s);
+    timing_end(s, ev);
+    if (e != hipSuccess) return hip_fail(e, "persistent tile kernel");
+    e = launch_finalize(table, 0, nframes, s);
+    if (e != hipSuccess) return hip_fail(e, "finalize");
+  }
+  return SBS_OK;
+}
+
+// ---------------------------------------------------------------- tuning cache (JSON)
+std::string plan_json(const Plan& p) {
+  std::ostringstream o;
+  o << "{\"cols_per_lane\": " << p.cpl << ", \"chunk\": " << p.chunk << ", \"tile_rows\": " << p.ty
+    << ", \"waves_per_cu\": " << p.wpc << "}";
+  return o.str();
+}
+
+bool parse_int_field(const std::string& s, const char* name, int* out) {
+  std::string pat = std::string("\"") + name + "\"";
+  size_t p = s.find(pat);
+  if (p == std::string::npos) return false;
+  p = s.find(':', p);
+  if (p == std::string::npos) return false;
+  *out = std::atoi(s.c_str() + p + 1);
+  return true;
+}
+
+int load_cache(const char* path) {
+  std::ifstream in(path);
+  if (!in) return fail(SBS_ERR_INVALID_ARG, "cannot open %s", path);
+  std::stringstream ss;
+  ss << in.rdbuf();
+  std::string s = ss.str();
+  size_t p = 0;
+  std::map<std::string, Plan> got;
+  while ((p = s.find('"', p)) != std::string::npos) {
+    size_t q = s.find('"', p + 1);
+    if (q == std::string::npos) break;
+    std::string key = s.substr(p + 1, q - p - 1);
+    size_t ob = s.find('{', q), cb = s.find('}', q);
+    if (ob == std::string::npos || cb == std::string::npos || key.rfind("gfx", 0) != 0) { p = q + 1; continue; }
+    std::string body = s.substr(ob, cb - ob + 1);
+    Plan pl;
+    if (parse_int_field(body, "cols_per_lane", &pl.cpl) && parse_int_field(body, "chunk", &pl.chunk) &&
+        parse_int_field(body, "tile_rows", &pl.ty) && parse_int_field(body, "waves_per_cu", &pl.wpc))
+      got[key] = pl;
+    p = cb + 1;
+  }
+  std::lock_guard<std::mutex> lk(g_mu);
+  for (auto& kv : got) g_tuned[kv.first] = kv.second;
+  return SBS_OK;
+}
+
+int save_cache(const char* path) {
+  std::map<std::string, Plan> all;
+  {
+    std::ifstream in(path);
+    if (in) { in.close(); load_cache(path); }
+    std::lock_guard<std::mutex> lk(g_mu);
+    all = g_tuned;
+  }
+  std::ofstream out(path);
+  if (!out) return fail(SBS_ERR_INVALID_ARG, "cannot write %s", path);
+  out << "{\n";
+  size_t i = 0;
+  for (auto& kv : all) {
+    out << "  \"" << kv.first << "\": " << plan_json(kv.second) << (++i < all.size() ? ",\n" : "\n");
+  }
+  out << "}\n";
+  return SBS_OK;
+}
+
+bool plan_valid(const Plan& p) {
+  return p.cpl == 4 && (p.chunk == 8 || p.chunk == 16) && p.ty >= 8 && p.ty <= 64 && p.wpc >= 1 && p.wpc <= 16;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sbs_abi_version(void) { return SBS_ABI_VERSION; }
+
+const char* sbs_last_error(void) { return g_err.c_str(); }
+
+size_t sbs_workspace_bytes(const sbs_frame* frames, int32_t nframes) {
+  if (nframes < 0 || (nframes > 0 && !frames)) return 0;
+  for (int i = 0; i < nframes; ++i)
+    if (validate(frames[i], i) != SBS_OK) return 0;
+  return total_bytes(frames, nframes);
+}
+
+int sbs_sad_disparity(const uint8_t* left, const uint8_t* right, int32_t W, int32_t H, int32_t C,
+                      int64_t pitch_bytes, const uint32_t* boundary_idx, int64_t n, int32_t block, int32_t dmax,
+                      uint8_t* out_disp, uint32_t* out_cost, void* workspace, size_t workspace_bytes,
+                      void* stream) {
+  sbs_frame f{left, right, W, H, C, pitch_bytes, boundary_idx, n, block, dmax, out_disp, out_cost};
+  return run(&f, 1, workspace, workspace_bytes, (hipStream_t)stream, kSingle);
+}
+
+int sbs_sad_disparity_batched(const sbs_frame* frames, int32_t nframes, void* workspace, size_t workspace_bytes,
+                              void* stream) {
+  return run(frames, nframes, workspace, workspace_bytes, (hipStream_t)stream, kBatched);
+}
+
+int sbs_sad_disparity_per_frame(const sbs_frame* frames, int32_t nframes, void* workspace, size_t workspace_bytes,
+                                void* stream) {
+  return run(frames, nframes, workspace, workspace_bytes, (hipStream_t)stream, kPerFrame);
+}
+
+int sbs_check_indices(const sbs_frame* frames, int32_t nframes, void* workspace, void* stream) {
+  (void)frames;
+  (void)nframes;
+  if (!workspace) workspace = own_workspace_ptr();
+  if (!workspace) return SBS_OK;
+  hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  uint32_t err = 0;
+  e = hipMemcpy(&err, workspace, sizeof err, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
+  const uint32_t zero = 0;
+  e = hipMemcpy(workspace, &zero, sizeof zero, hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
+  if (err) return fail(SBS_ERR_INDEX_RANGE, "an index >= W*H was seen");
+  return SBS_OK;
+}
+
+int sbs_sad_disparity_ref(const uint8_t* left, const uint8_t* right, int32_t W, int32_t H, int32_t C,
+                          int64_t pitch_bytes, const uint32_t* boundary_idx, int64_t n, int32_t block,
+                          int32_t dmax, uint8_t* out_disp, uint32_t* out_cost, void* stream) {
+  sbs_frame f{left, right, W, H, C, pitch_bytes, boundary_idx, n, block, dmax, out_disp, out_cost};
+  int st = validate(f, 0);
+  if (st != SBS_OK) return st;
+  if (n == 0) return SBS_OK;
+  st = device_check(nullptr);
+  if (st != SBS_OK) return st;
+  void* ws = nullptr;
+  st = own_workspace(kHeaderBytes, &ws);
+  if (st != SBS_OK) return st;
+  hipError_t e = launch_ref(left, right, W, H, C, pitch_bytes, boundary_idx, n, (block - 1) / 2, dmax, out_disp,
+                            out_cost, &((WsHeader*)ws)->error, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "reference kernel");
+  return SBS_OK;
+}
+
+int sbs_kernel_timing(int32_t enable) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_timing = enable != 0;
+  return SBS_OK;
+}
+
+int32_t sbs_kernel_times(float* ms, int32_t cap) {
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    ev.swap(g_events);
+  }
+  int32_t n = 0;
+  for (auto& pr : ev) {
+    float t = -1.0f;
+    if (hipEventSynchronize(pr.second) == hipSuccess) hipEventElapsedTime(&t, pr.first, pr.second);
+    if (ms && n < cap) ms[n] = t;
+    ++n;
+    hipEventDestroy(pr.first);
+    hipEventDestroy(pr.second);
+  }
+  return n;
+}
+
+int sbs_set_plan(const sbs_plan* plan) {
+  if (!plan || (!plan->cols_per_lane && !plan->chunk && !plan->tile_rows && !plan->waves_per_cu)) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_forced = false;
+    return SBS_OK;
+  }
+  Plan merged;  // fields left at 0 take the defaults for validation
+  merged.cpl = plan->cols_per_lane ? plan->cols_per_lane : 4;
+  merged.chunk = plan->chunk ? plan->chunk : 16;
+  merged.ty = plan->tile_rows ? plan->tile_rows : 32;
+  merged.wpc = plan->waves_per_cu ? plan->waves_per_cu : 8;
+  if (!plan_valid(merged)) return fail(SBS_ERR_INVALID_ARG, "invalid plan");
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_forced = true;
+  g_forced_plan.cpl = plan->cols_per_lane;
+  g_forced_plan.chunk = plan->chunk;
+  g_forced_plan.ty = plan->tile_rows;
+  g_forced_plan.wpc = plan->waves_per_cu;
+  return SBS_OK;
+}
+
+int sbs_get_plan(const sbs_frame* frame, sbs_plan* plan) {
+  if (!frame || !plan) return fail(SBS_ERR_INVALID_ARG, "NULL argument");
+  int st = validate(*frame, 0);
+  if (st != SBS_OK) return st;
+  Plan p = choose_plan(*frame);
+  plan->cols_per_lane = p.cpl;
+  plan->chunk = p.chunk;
+  plan->tile_rows = p.ty;
+  plan->waves_per_cu = p.wpc;
+  return SBS_OK;
+}
+
+int sbs_load_tuning(const char* cache_path) {
+  if (!cache_path) return fail(SBS_ERR_INVALID_ARG, "NULL path");
+  return load_cache(cache_path);
+}
+
+int sbs_tune(const sbs_frame* frames, int32_t nframes, const char* cache_path) {
+  if (nframes < 1 || !frames) return fail(SBS_ERR_INVALID_ARG, "no frames");
+  for (int i = 0; i < nframes; ++i) {
+    int st = validate(frames[i], i);
+    if (st != SBS_OK) return st;
+  }
+  int st = device_check(nullptr);
+  if (st != SBS_OK) return st;
+  bool was_forced;
+  Plan was_plan;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    was_forced = g_forced;
+    was_plan = g_forced_plan;
+  }
+  hipEvent_t a, b;
+  hipEventCreate(&a);
+  hipEventCreate(&b);
+  Plan best;
+  float best_ms = 1e30f;
+  const int chunks[] = {8, 16};
+  const int rows[] = {16, 32, 64};
+  const int wpcs[] = {4, 8, 16};
+  for (int ch : chunks)
+    for (int ty : rows)
+      for (int w : wpcs) {
+        Plan p;
+        p.chunk = ch; p.ty = ty; p.wpc = w;
+        {
+          std::lock_guard<std::mutex> lk(g_mu);
+          g_forced = true;
+          g_forced_plan = p;
+        }
+        st = run(frames, nframes, nullptr, 0, nullptr, kBatched);  // warm-up (and workspace growth)
+        if (st != SBS_OK) goto done;
+        hipEventRecord(a, nullptr);
+        for (int rep = 0; rep < 3; ++rep) {
+          st = run(frames, nframes, nullptr, 0, nullptr, kBatched);
+          if (st != SBS_OK) goto done;
+        }
+        hipEventRecord(b, nullptr);
+        hipEventSynchronize(b);
+        float ms = 0;
+        hipEventElapsedTime(&ms, a, b);
+        if (ms < best_ms) { best_ms = ms; best = p; }
+      }
+done:
+  hipEventDestroy(a);
+  hipEventDestroy(b);
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_forced = was_forced;
+    g_forced_plan = was_plan;
+    if (st == SBS_OK) g_tuned[plan_key(frames[0])] = best;
+  }
+  if (st != SBS_OK) return st;
+  if (cache_path) return save_cache(cache_path);
+  return SBS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,59 @@
+// Internal definitions shared by the HIP kernels and the host layer of libsbs.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sbs {
+
+constexpr int kWave = 64;
+constexpr int kColsPerLane = 4;            // CAD columns owned by one lane
+constexpr int kSpan = kWave * kColsPerLane;  // CAD columns per tile (256)
+constexpr int kMaxChunk = 16;              // largest disparity chunk a kernel instance handles
+constexpr int kRSlack = 32;                // >= kMaxChunk + 3: replicate columns left of the right copy
+constexpr int kDescPerLaunch = 8;          // descriptors carried by one upload kernel
+
+// Per-frame descriptor as the kernels see it (lives in the workspace).
+struct FrameDev {
+  const uint8_t* left;
+  const uint8_t* right;
+  const uint32_t* idx;
+  uint8_t* out_disp;
+  uint32_t* out_cost;
+  int32_t* map;        // W*H: a representative list slot per pixel, or -1
+  uint32_t* keys;      // n: (cost << 8) | d, running minimum per representative slot
+  uint32_t* lp;        // left copy, RGBx u32 per pixel, replicate-padded
+  uint32_t* rp;        // right copy, RGBx u32 per pixel, replicate-padded
+  uint64_t* rowbits;   // per row: one bit per 64-column group holding a listed pixel
+  int64_t pitch;       // bytes between image rows
+  int64_t n;           // list length
+  int64_t item_base;   // first work item of this frame in the batch
+  int64_t nitems;      // work items of this frame (tiles x chunks)
+  int32_t W, H, C;
+  int32_t r, dmax;
+  int32_t lpw, rpw, ph;  // padded copy widths (u32 units) and height (rows)
+  int32_t roff;          // right copy column of image column c is c + r + roff
+  int32_t rbw;           // u64 words per row in rowbits
+  int32_t txo, ty;       // tile: output columns and rows
+  int32_t ntx, nty;      // tiles per row / column
+  int32_t nch, chunk;    // disparity chunks and their size
+  int32_t pad_;
+};
+
+struct DescBatch {
+  FrameDev f[kDescPerLaunch];
+  int32_t first;
+  int32_t count;
+};
+
+// Workspace header at offset 0 of every workspace.
+struct WsHeader {
+  uint32_t error;        // bit 0: an index >= W*H was seen
+  uint32_t pad0[15];
+  unsigned long long head;  // persistent queue head
+  uint64_t pad1[7];
+};
+constexpr size_t kHeaderBytes = 256;
+static_assert(sizeof(WsHeader) <= kHeaderBytes, "header");
+
+}  // namespace sbs

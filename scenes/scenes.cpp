@@ -136,17 +136,26 @@ void make_texture(const sc_params& p, uint64_t purpose, uint64_t id, int w, int 
   }
   out.assign((size_t)w * h * C, 0);
   if (p.texture == 0) {
-    // 3x3 box, replicate border, integer (sum + 4) / 9.
+    // 3x3 box, replicate border, integer (sum + 4) / 9, as row sums then column sums.
+    std::vector<uint16_t> hs((size_t)w * h * C);
 #pragma omp parallel for schedule(static) if ((size_t)w * h > (1u << 18))
-    for (int v = 0; v < h; ++v)
-      for (int u = 0; u < w; ++u)
-        for (int c = 0; c < C; ++c) {
-          int s = 0;
-          for (int j = -1; j <= 1; ++j)
-            for (int i = -1; i <= 1; ++i)
-              s += noise[((size_t)clampi(v + j, 0, h - 1) * w + clampi(u + i, 0, w - 1)) * C + c];
-          out[((size_t)v * w + u) * C + c] = (uint8_t)((s + 4) / 9);
-        }
+    for (int v = 0; v < h; ++v) {
+      const uint8_t* row = &noise[(size_t)v * w * C];
+      uint16_t* o = &hs[(size_t)v * w * C];
+      for (int u = 0; u < w; ++u) {
+        const int ul = u > 0 ? u - 1 : 0, ur = u + 1 < w ? u + 1 : w - 1;
+        for (int c = 0; c < C; ++c)
+          o[(size_t)u * C + c] = (uint16_t)(row[(size_t)ul * C + c] + row[(size_t)u * C + c] + row[(size_t)ur * C + c]);
+      }
+    }
+#pragma omp parallel for schedule(static) if ((size_t)w * h > (1u << 18))
+    for (int v = 0; v < h; ++v) {
+      const uint16_t* a = &hs[(size_t)clampi(v - 1, 0, h - 1) * w * C];
+      const uint16_t* b = &hs[(size_t)v * w * C];
+      const uint16_t* c2 = &hs[(size_t)clampi(v + 1, 0, h - 1) * w * C];
+      uint8_t* o = &out[(size_t)v * w * C];
+      for (size_t i = 0; i < (size_t)w * C; ++i) o[i] = (uint8_t)((a[i] + b[i] + c2[i] + 4) / 9);
+    }
   } else {
     // Separable Gaussian, sigma 1, radius 3, fixed-point weights summing to 2^16.
     double g[7], gs = 0;
@@ -237,6 +246,25 @@ void add_noise(const sc_params& p, uint64_t purpose, int frame, uint8_t* img) {
   }
 }
 
+// Textures that do not change from frame to frame: the background and one
+// texture per region (in region-local coordinates).
+struct Textures {
+  std::vector<uint8_t> bg;
+  std::vector<std::vector<uint8_t>> reg;
+};
+
+void make_textures(const sc_params& p, Textures& t) {
+  int bg_mean = -1;
+  std::vector<Region> reg = layout(p, 0, &bg_mean);
+  make_texture(p, P_BG_TEX, 0, p.W, p.H, bg_mean, t.bg);
+  t.reg.resize(reg.size());
+  for (size_t k = 0; k < reg.size(); ++k)
+    make_texture(p, P_REG_TEX, (uint64_t)k, reg[k].wr, reg[k].hr, reg[k].mean, t.reg[k]);
+}
+
+int compose_frame(const sc_params& p, const Textures& tx, int32_t frame, uint8_t* left, uint8_t* right,
+                  uint8_t* gt, uint8_t* occ, int16_t* rid);
+
 }  // namespace
 
 extern "C" {
@@ -251,19 +279,67 @@ int sc_frame(const sc_params* pp, int32_t frame, uint8_t* left, uint8_t* right,
   const sc_params& p = *pp;
   if (p.W < 1 || p.H < 1 || (p.C != 1 && p.C != 3) || p.dmax_regions < 0 || p.dmax_regions > 255)
     return -1;
+  Textures tx;
+  make_textures(p, tx);
+  return compose_frame(p, tx, frame, left, right, gt, occ, rid);
+}
+
+}  // extern "C"
+
+namespace {
+
+// Fresh noise for pixels of the right image that no left pixel reaches: the
+// same smoothed-uniform process as the textures, but with a counter-based
+// source (a hash of (seed, frame, pixel, channel)) so single pixels can be
+// drawn without making a whole noise image.
+inline uint8_t hash_noise(const sc_params& p, int frame, int u, int v, int c) {
+  uint64_t h = p.seed ^ (P_RIGHT * 0x9E3779B97F4A7C15ULL);
+  h = mix64(h ^ ((uint64_t)frame * 0xD1B54A32D192ED03ULL + 1));
+  h = mix64(h ^ (((uint64_t)v * (uint64_t)p.W + (uint64_t)u) * 0x8CB92BA72F3D8DD7ULL + (uint64_t)c));
+  return (uint8_t)(h >> 56);
+}
+
+uint8_t fresh_value(const sc_params& p, int frame, int x, int y, int c, int mean) {
+  const int W = p.W, H = p.H;
+  int v;
+  if (p.texture == 0) {
+    int s = 0;
+    for (int j = -1; j <= 1; ++j)
+      for (int i = -1; i <= 1; ++i) s += hash_noise(p, frame, clampi(x + i, 0, W - 1), clampi(y + j, 0, H - 1), c);
+    v = (s + 4) / 9;
+  } else {
+    double g[7], gs = 0;
+    for (int k = -3; k <= 3; ++k) { g[k + 3] = std::exp(-0.5 * k * k); gs += g[k + 3]; }
+    int64_t wt[7], ws = 0;
+    for (int k = 0; k < 7; ++k) { wt[k] = (int64_t)std::llround(g[k] / gs * 65536.0); ws += wt[k]; }
+    wt[3] += 65536 - ws;
+    uint64_t s = 0;
+    for (int j = -3; j <= 3; ++j) {
+      uint64_t hsum = 0;
+      for (int i = -3; i <= 3; ++i)
+        hsum += (uint64_t)wt[i + 3] * hash_noise(p, frame, clampi(x + i, 0, W - 1), clampi(y + j, 0, H - 1), c);
+      s += (uint64_t)wt[j + 3] * hsum;
+    }
+    v = (int)std::min<uint64_t>(255, (s + (1ULL << 31)) >> 32);
+  }
+  if (mean >= 0) {
+    int d = v - 128;
+    v = mean + (d >= 0 ? d / 2 : -((-d + 1) / 2));
+  }
+  return clamp_u8(v);
+}
+
+int compose_frame(const sc_params& p, const Textures& tx, int32_t frame, uint8_t* left, uint8_t* right,
+                  uint8_t* gt, uint8_t* occ, int16_t* rid) {
   const int W = p.W, H = p.H, C = p.C;
   const size_t N = (size_t)W * H;
   int bg_mean = -1;
   std::vector<Region> reg = layout(p, frame, &bg_mean);
-
-  std::vector<uint8_t> tex;
-  make_texture(p, P_BG_TEX, 0, W, H, bg_mean, tex);
-  std::memcpy(left, tex.data(), N * C);
+  std::memcpy(left, tx.bg.data(), N * C);
   std::vector<int16_t> zl(N, 0), own(N, -1);
   for (int k = 0; k < (int)reg.size(); ++k) {
     const Region& g = reg[k];
-    std::vector<uint8_t> rt;
-    make_texture(p, P_REG_TEX, (uint64_t)k, g.wr, g.hr, g.mean, rt);
+    const std::vector<uint8_t>& rt = tx.reg[(size_t)k];
     const int x0 = g.cx - g.wr / 2, y0 = g.cy - g.hr / 2;
     for (int v = 0; v < g.hr; ++v) {
       const int y = y0 + v;
@@ -284,11 +360,8 @@ int sc_frame(const sc_params* pp, int32_t frame, uint8_t* left, uint8_t* right,
     }
   }
 
-  // Right image: fresh noise of the same process, then a z-buffered forward
-  // warp of every left pixel to x - d on the same row.
-  std::vector<uint8_t> rtex;
-  make_texture(p, P_RIGHT, (uint64_t)frame, W, H, bg_mean, rtex);
-  std::memcpy(right, rtex.data(), N * C);
+  // Right image: a z-buffered forward warp of every left pixel to x - d on
+  // the same row; pixels no left pixel reaches get fresh smoothed noise.
   std::vector<int16_t> zr(N, -1);
   std::vector<int32_t> src(N, -1);
 #pragma omp parallel for schedule(static) if (N > (1u << 18))
@@ -306,6 +379,13 @@ int sc_frame(const sc_params* pp, int32_t frame, uint8_t* left, uint8_t* right,
       }
     }
   }
+#pragma omp parallel for schedule(static) if (N > (1u << 18))
+  for (int y = 0; y < H; ++y)
+    for (int x = 0; x < W; ++x) {
+      const size_t t = (size_t)y * W + x;
+      if (zr[t] >= 0) continue;
+      for (int c = 0; c < C; ++c) right[t * C + c] = fresh_value(p, frame, x, y, c, bg_mean);
+    }
   if (gt) for (size_t q = 0; q < N; ++q) gt[q] = (uint8_t)zl[q];
   if (occ) {
     for (int y = 0; y < H; ++y)
@@ -322,6 +402,10 @@ int sc_frame(const sc_params* pp, int32_t frame, uint8_t* left, uint8_t* right,
   }
   return 0;
 }
+
+}  // namespace
+
+extern "C" {
 
 // Pixels near the scene's region outlines, the stand-in for a refined
 // boundary set: the left and right image columns first, then pixels by
@@ -407,12 +491,16 @@ int sc_video(const sc_params* pp, int32_t frame0, int32_t nframes, uint8_t* left
   const sc_params& p = *pp;
   const size_t img = (size_t)p.W * p.H * p.C;
   const size_t N = (size_t)p.W * p.H;
+  if (p.W < 1 || p.H < 1 || (p.C != 1 && p.C != 3) || p.dmax_regions < 0 || p.dmax_regions > 255)
+    return -1;
+  Textures tx;
+  make_textures(p, tx);
   int bad = 0;
 #pragma omp parallel for schedule(dynamic, 1) reduction(| : bad)
   for (int i = 0; i < nframes; ++i) {
     std::vector<int16_t> rid(N);
-    int rc = sc_frame(pp, frame0 + i, left + img * i, right + img * i, nullptr, nullptr,
-                      lists ? rid.data() : nullptr);
+    int rc = compose_frame(p, tx, frame0 + i, left + img * i, right + img * i, nullptr, nullptr,
+                           lists ? rid.data() : nullptr);
     if (rc != 0) { bad |= 1; continue; }
     if (lists) {
       int64_t n = sc_contour_list(rid.data(), p.W, p.H, fracs ? fracs[i] : 0.18,

@@ -1,0 +1,62 @@
+"""The C-ABI library loads and exports every symbol include/sbs.h declares,
+and rejects invalid arguments on the host before any device work (CPU only)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2001_07809_amd as sbs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "sbs.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sbs_\w+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported():
+    lib = sbs.lib()
+    names = declared_functions()
+    assert len(names) >= 10
+    for name in names:
+        assert hasattr(lib, name), name
+    assert lib.sbs_abi_version() == 1
+
+
+def _call(W=8, H=4, C=1, pitch=None, n=1, block=3, dmax=2, ptr=1):
+    lib = sbs.lib()
+    p = ctypes.c_void_p(ptr) if ptr else None
+    return lib.sbs_sad_disparity(p, p, W, H, C, W * C if pitch is None else pitch, p, n, block, dmax,
+                                 p, None, None, 0, None)
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(W=0), 1), (dict(H=0), 1), (dict(C=2), 1), (dict(pitch=7), 1), (dict(block=4), 1),
+    (dict(block=0), 1), (dict(dmax=-1), 1), (dict(dmax=256), 1), (dict(n=-1), 1), (dict(ptr=0), 1),
+    (dict(block=129), 2),
+])
+def test_invalid_arguments_rejected_on_host(kw, status):
+    assert _call(**kw) == status
+    assert sbs.lib().sbs_last_error().decode() != ""
+
+
+def test_empty_list_is_a_no_op_without_a_device():
+    assert _call(n=0, ptr=0) == 0
+
+
+def test_workspace_bytes_and_plans():
+    f = sbs.Frame(1, 1, 100, 50, 3, 300, 1, 1000, 15, 31, 1, None)
+    nb = sbs.workspace_bytes([f])
+    assert nb > 100 * 50 * 4 * 3
+    bad = sbs.Frame(1, 1, 100, 50, 2, 300, 1, 1000, 15, 31, 1, None)
+    assert sbs.workspace_bytes([bad]) == 0
+    assert sbs.workspace_bytes([f, f]) > nb
+    with pytest.raises(sbs.SbsError):
+        sbs.set_plan(chunk=12)
+    sbs.set_plan(chunk=8, tile_rows=16)
+    assert sbs.get_plan(f)["chunk"] == 8 and sbs.get_plan(f)["tile_rows"] == 16
+    sbs.set_plan()
+    assert sbs.get_plan(f)["chunk"] in (8, 16)

@@ -1,0 +1,276 @@
+"""GPU parity: the HIP path, called through the C-ABI, against the oracle.
+
+Bar: bit-exact disparity AND cost (integer results). Small cases compare every
+list entry with the oracle. At the full benchmark sizes the whole list is
+checked against the GPU brute-force reference kernel (a separate code path),
+and a random sample of entries against the oracle.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import scenes
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available()
+    return t
+
+
+@pytest.fixture(scope="module")
+def sbs():
+    import paper_2001_07809_amd as m
+    m.lib()
+    return m
+
+
+def dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def run_gpu(torch, sbs, L, R, idx, block, dmax, path="tiled", **kw):
+    Ld, Rd = dev(torch, L), dev(torch, R)
+    Id = dev(torch, np.asarray(idx, np.uint32).view(np.int32))
+    if path == "tiled":
+        d, c = sbs.sad_disparity(Ld, Rd, Id, block, dmax, **kw)
+    else:
+        d, c = sbs.sad_disparity_ref(Ld, Rd, Id, block, dmax)
+    torch.cuda.synchronize()
+    return d.cpu().numpy(), c.cpu().numpy().view(np.uint32)
+
+
+def assert_parity(got, exp, what=""):
+    gd, gc = got
+    ed, ec = exp[0], exp[1]
+    bad = np.flatnonzero((gd != ed) | (gc != ec))
+    assert bad.size == 0, f"{what}: {bad.size} mismatches, first at {bad[:5]}: gpu {gd[bad[:5]]}/{gc[bad[:5]]} oracle {ed[bad[:5]]}/{ec[bad[:5]]}"
+
+
+def test_tiny_random_sweep(torch, sbs):
+    rng = np.random.default_rng(11)
+    for trial in range(40):
+        W = int(rng.integers(1, 90))
+        H = int(rng.integers(1, 70))
+        C = int(rng.choice([1, 3]))
+        block = int(rng.choice([1, 3, 5, 7, 9, 15, 31]))
+        dmax = int(rng.integers(0, 80))
+        shape = (H, W) if C == 1 else (H, W, C)
+        L = rng.integers(0, 256, shape, dtype=np.uint8)
+        R = rng.integers(0, 256, shape, dtype=np.uint8)
+        if trial % 5 == 0:
+            R = (R // 64 * 64).astype(np.uint8)     # coarse levels: many equal costs
+            L = (L // 64 * 64).astype(np.uint8)
+        idx = rng.permutation(W * H).astype(np.uint32)
+        idx = np.concatenate([idx, idx[: max(1, idx.size // 7)]])   # shuffled, with duplicates
+        exp = oracle.sad(L, R, idx, block, dmax)
+        what = f"trial {trial} W{W} H{H} C{C} b{block} d{dmax}"
+        assert_parity(run_gpu(torch, sbs, L, R, idx, block, dmax), exp, what + " tiled")
+        assert_parity(run_gpu(torch, sbs, L, R, idx, block, dmax, path="ref"), exp, what + " ref")
+
+
+def test_tsukuba_shape_full_list(torch, sbs):
+    spec = scenes.PRESETS["tsukuba_gray"]
+    f = scenes.make_frame(spec)
+    idx = scenes.contour_list(f.rid, spec.frac, spec.seed)
+    exp = oracle.sad(f.left, f.right, idx, spec.block, spec.dmax)
+    assert_parity(run_gpu(torch, sbs, f.left, f.right, idx, spec.block, spec.dmax), exp, "tsukuba tiled")
+    assert_parity(run_gpu(torch, sbs, f.left, f.right, idx, spec.block, spec.dmax, path="ref"), exp, "tsukuba ref")
+
+
+def test_oracle_frontend_list(torch, sbs):
+    # The list the oracle's own segmentation front end produces (K=4, open/close, CC >= 50, 18%).
+    spec = scenes.PRESETS["tsukuba_gray"]
+    f = scenes.make_frame(spec)
+    idx = oracle.boundaries(f.left, K=4, mode=0, min_cc=50, frac=0.18, seed=spec.seed)
+    exp = oracle.sad(f.left, f.right, idx, spec.block, spec.dmax)
+    assert_parity(run_gpu(torch, sbs, f.left, f.right, idx, spec.block, spec.dmax), exp, "frontend list")
+    vga = scenes.make_frame(scenes.PRESETS["serve_vga"])
+    idx = oracle.boundaries(vga.left, K=4, mode=0, min_cc=50, frac=0.18, seed=5)
+    exp = oracle.sad(vga.left, vga.right, idx, 11, 31)
+    assert_parity(run_gpu(torch, sbs, vga.left, vga.right, idx, 11, 31), exp, "frontend list rgb")
+
+
+def test_middlebury_shape(torch, sbs):
+    spec = scenes.PRESETS["middlebury_rgb"]
+    f = scenes.make_frame(spec)
+    idx = scenes.contour_list(f.rid, spec.frac, spec.seed)
+    got = run_gpu(torch, sbs, f.left, f.right, idx, spec.block, spec.dmax)
+    ref = run_gpu(torch, sbs, f.left, f.right, idx, spec.block, spec.dmax, path="ref")
+    assert_parity(got, ref, "middlebury tiled vs ref (full list)")
+    rng = np.random.default_rng(3)
+    s = np.sort(rng.choice(idx.size, 20000, replace=False))
+    exp = oracle.sad(f.left, f.right, idx[s], spec.block, spec.dmax)
+    assert_parity((got[0][s], got[1][s]), exp, "middlebury sample vs oracle")
+
+
+def test_uhd_shape_sampled(torch, sbs):
+    spec = scenes.PRESETS["uhd_rgb"]
+    f = scenes.make_frame(spec)
+    idx = scenes.contour_list(f.rid, spec.frac, spec.seed)
+    got = run_gpu(torch, sbs, f.left, f.right, idx, spec.block, spec.dmax)
+    rng = np.random.default_rng(4)
+    s = np.sort(rng.choice(idx.size, 1500, replace=False))
+    exp = oracle.sad(f.left, f.right, idx[s], spec.block, spec.dmax)
+    assert_parity((got[0][s], got[1][s]), exp, "uhd sample vs oracle")
+    s2 = np.sort(rng.choice(idx.size, 60000, replace=False))
+    ref = run_gpu(torch, sbs, f.left, f.right, idx[s2], spec.block, spec.dmax, path="ref")
+    assert_parity((got[0][s2], got[1][s2]), ref, "uhd sample vs ref kernel")
+
+
+def test_plans_agree(torch, sbs):
+    spec = scenes.scaled(scenes.PRESETS["serve_fhd"], W=700, H=333)
+    f = scenes.make_frame(spec)
+    idx = scenes.contour_list(f.rid, 0.2, 1)
+    base = None
+    try:
+        for chunk in (8, 16):
+            for rows in (8, 16, 32, 64):
+                sbs.set_plan(chunk=chunk, tile_rows=rows)
+                got = run_gpu(torch, sbs, f.left, f.right, idx, spec.block, spec.dmax)
+                if base is None:
+                    base = got
+                    exp = oracle.sad(f.left, f.right, idx, spec.block, spec.dmax)
+                    assert_parity(got, exp, "plan base vs oracle")
+                assert_parity(got, base, f"plan chunk {chunk} rows {rows}")
+    finally:
+        sbs.set_plan()
+
+
+def test_edge_cases(torch, sbs):
+    rng = np.random.default_rng(5)
+    # single pixel, single row, single column
+    for (H, W) in [(1, 1), (1, 40), (37, 1)]:
+        L = rng.integers(0, 256, (H, W, 3), dtype=np.uint8)
+        R = rng.integers(0, 256, (H, W, 3), dtype=np.uint8)
+        idx = np.arange(W * H, dtype=np.uint32)
+        exp = oracle.sad(L, R, idx, 5, 9)
+        assert_parity(run_gpu(torch, sbs, L, R, idx, 5, 9), exp, f"{H}x{W}")
+    L = rng.integers(0, 256, (50, 64), dtype=np.uint8)
+    R = rng.integers(0, 256, (50, 64), dtype=np.uint8)
+    idx = np.arange(50 * 64, dtype=np.uint32)
+    for block, dmax in [(1, 0), (1, 40), (3, 0), (33, 255)]:
+        exp = oracle.sad(L, R, idx, block, dmax)
+        assert_parity(run_gpu(torch, sbs, L, R, idx, block, dmax), exp, f"b{block} d{dmax}")
+    # largest block, largest dmax (sampled)
+    L = rng.integers(0, 256, (200, 300, 3), dtype=np.uint8)
+    R = rng.integers(0, 256, (200, 300, 3), dtype=np.uint8)
+    idx = np.sort(rng.choice(200 * 300, 300, replace=False)).astype(np.uint32)
+    exp = oracle.sad(L, R, idx, 127, 255)
+    assert_parity(run_gpu(torch, sbs, L, R, idx, 127, 255), exp, "max block + dmax")
+    # empty list
+    d, c = run_gpu(torch, sbs, L, R, np.zeros(0, np.uint32), 15, 15)
+    assert d.size == 0
+
+
+def test_row_pitch_and_no_cost_and_stream(torch, sbs):
+    rng = np.random.default_rng(6)
+    big = rng.integers(0, 256, (60, 120, 3), dtype=np.uint8)
+    bigr = rng.integers(0, 256, (60, 120, 3), dtype=np.uint8)
+    L = big[:, :97]
+    R = bigr[:, :97]
+    idx = np.arange(60 * 97, dtype=np.uint32)[::3].copy()
+    exp = oracle.sad(np.ascontiguousarray(L), np.ascontiguousarray(R), idx, 7, 20)
+    Ld = dev(torch, big)[:, :97]
+    Rd = dev(torch, bigr)[:, :97]
+    assert Ld.stride(0) == 360
+    Id = dev(torch, idx.view(np.int32))
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        d, c = sbs.sad_disparity(Ld, Rd, Id, 7, 20, stream=s)
+        d2, c2 = sbs.sad_disparity(Ld, Rd, Id, 7, 20, stream=s, with_cost=False)
+    s.synchronize()
+    assert c2 is None
+    assert_parity((d.cpu().numpy(), c.cpu().numpy().view(np.uint32)), exp, "pitched rows")
+    np.testing.assert_array_equal(d2.cpu().numpy(), exp[0])
+
+
+def test_out_of_range_index_reported(torch, sbs):
+    rng = np.random.default_rng(7)
+    L = rng.integers(0, 256, (20, 30), dtype=np.uint8)
+    R = rng.integers(0, 256, (20, 30), dtype=np.uint8)
+    idx = np.array([5, 600, 599, 10**6, 0], np.uint32)
+    d, c = run_gpu(torch, sbs, L, R, idx, 5, 7)
+    assert sbs.check_indices() == 5
+    assert sbs.check_indices() == 0
+    exp = oracle.sad(L, R, idx, 5, 7)
+    assert_parity((d, c), exp, "out of range")
+    assert d[1] == 255 and c[1] == 0xFFFFFFFF and d[3] == 255
+
+
+def _video(spec, nframes):
+    fr = scenes.video_fracs(spec, 0, nframes)
+    left, right, lists = scenes.make_video(spec, 0, nframes, fr)
+    return left, right, lists
+
+
+def test_batched_equals_single_and_oracle(torch, sbs):
+    spec = scenes.scaled(scenes.PRESETS["uhd_video"], W=640, H=360, n_regions=12)
+    left, right, lists = _video(spec, 5)
+    extra = scenes.make_frame(scenes.PRESETS["tsukuba_gray"])
+    extra_idx = scenes.contour_list(extra.rid, 0.3, 9)
+    frames = []
+    keep = []
+    for t in range(5):
+        Ld, Rd, Id = dev(torch, left[t]), dev(torch, right[t]), dev(torch, lists[t].view(np.int32))
+        keep += [Ld, Rd, Id]
+        frames.append((Ld, Rd, Id, spec.block, spec.dmax))
+    Ed, Erd, Eid = dev(torch, extra.left), dev(torch, extra.right), dev(torch, extra_idx.view(np.int32))
+    frames.append((Ed, Erd, Eid, 15, 15))
+    runner = sbs.BatchRunner(frames)
+    runner.run()
+    torch.cuda.synchronize()
+    batched = [(runner.disp[i].cpu().numpy(), runner.cost[i].cpu().numpy().view(np.uint32)) for i in range(6)]
+    for i in range(6):
+        runner.disp[i].fill_(7)
+    runner.run_per_frame()
+    torch.cuda.synchronize()
+    per = [(runner.disp[i].cpu().numpy(), runner.cost[i].cpu().numpy().view(np.uint32)) for i in range(6)]
+    for t in range(5):
+        exp = oracle.sad(left[t], right[t], lists[t], spec.block, spec.dmax)
+        assert_parity(batched[t], exp, f"batched frame {t}")
+        assert_parity(per[t], exp, f"per-frame frame {t}")
+    exp = oracle.sad(extra.left, extra.right, extra_idx, 15, 15)
+    assert_parity(batched[5], exp, "batched mixed frame")
+    assert_parity(per[5], exp, "per-frame mixed frame")
+    assert runner.check_indices() == 0
+
+
+def test_graph_capture_replays(torch, sbs):
+    spec = scenes.scaled(scenes.PRESETS["uhd_video"], W=512, H=288, n_regions=10)
+    left, right, lists = _video(spec, 4)
+    bufs = []
+    frames = []
+    for t in range(3):
+        Ld, Rd, Id = dev(torch, left[t]), dev(torch, right[t]), dev(torch, lists[t].view(np.int32))
+        bufs.append((Ld, Rd, Id))
+        frames.append((Ld, Rd, Id, spec.block, spec.dmax))
+    runner = sbs.BatchRunner(frames)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        runner.run(stream=s)          # warm-up outside capture
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        runner.run()
+    torch.cuda.synchronize()
+    exp0 = oracle.sad(left[0], right[0], lists[0], spec.block, spec.dmax)
+    exp3 = oracle.sad(left[3], right[3], lists[0], spec.block, spec.dmax)
+    for rep in range(4):
+        for i in range(3):
+            runner.disp[i].fill_(0)
+            runner.cost[i].fill_(-1)
+        if rep == 2:
+            # new pixels in frame 0's buffers (same list): the replay must recompute
+            bufs[0][0].copy_(torch.from_numpy(left[3]))
+            bufs[0][1].copy_(torch.from_numpy(right[3]))
+        g.replay()
+        torch.cuda.synchronize()
+        got0 = (runner.disp[0].cpu().numpy(), runner.cost[0].cpu().numpy().view(np.uint32))
+        assert_parity(got0, exp3 if rep >= 2 else exp0, f"replay {rep}")
+        _ = torch.ones(1000, device="cuda").sum().item()   # eager work between replays
