@@ -89,6 +89,8 @@ def main():
     ap.add_argument("--no-compare", action="store_true", help="skip the per-frame / graph comparisons")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target oracle time for the CPU sample")
     ap.add_argument("--tuning", default=os.path.join(ROOT, "paper_2001_07809_amd", "tuning.json"))
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run one plain device copy of MIB mebibytes (HBM counter calibration)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -106,6 +108,15 @@ def main():
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
+    if args.calibrate_copy:
+        nbytes = args.calibrate_copy << 20
+        src = torch.empty(nbytes, dtype=torch.uint8, device="cuda").fill_(1)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": nbytes}), flush=True)
+        return
     sbs.lib()
     if args.tuning and os.path.exists(args.tuning):
         sbs.load_tuning(args.tuning)

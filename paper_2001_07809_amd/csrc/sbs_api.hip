@@ -19,7 +19,7 @@
 
 namespace sbs {
 hipError_t launch_put_desc(FrameDev* table, const FrameDev* host, int nframes, hipStream_t s);
-hipError_t launch_prologue(const FrameDev* table, int f0, int nf, int max_rows, int max_rbjobs, WsHeader* hdr,
+hipError_t launch_prologue(const FrameDev* table, int f0, int nf, int max_rows, int max_tptr, WsHeader* hdr,
                            hipStream_t s);
 hipError_t launch_finalize(const FrameDev* table, int f0, int nf, hipStream_t s);
 hipError_t launch_tile_grid(const FrameDev* table, int fi, int64_t nitems, int chunk, hipStream_t s);
@@ -83,7 +83,7 @@ int device_check(int* cus) {
 
 // ---------------------------------------------------------------- plans
 struct Plan {
-  int cpl = 4, chunk = 16, ty = 32, wpc = 8;
+  int cpl = 4, chunk = 8, ty = 64, wpc = 16;
 };
 bool g_forced = false;
 Plan g_forced_plan;
@@ -103,10 +103,11 @@ std::string plan_key(const sbs_frame& f) {
 }
 
 Plan default_plan(const sbs_frame& f) {
+  (void)f;
   Plan p;
-  p.chunk = (f.dmax + 1) <= 8 ? 8 : 16;
-  p.ty = 32;
-  p.wpc = 8;
+  p.chunk = 8;
+  p.ty = 64;
+  p.wpc = 16;
   return p;
 }
 
@@ -142,18 +143,20 @@ int validate(const sbs_frame& f, int i) {
 }
 
 struct FrameLayout {
-  size_t map_off, keys_off, lp_off, rp_off, rb_off, end;
-  int lpw, rpw, ph, roff, rbw;
+  size_t map_off, keys_off, lp_off, rp_off, rb_off, state_off, tptr_off, end;
+  int lpw, rpw, ph, lpad, rpad, rbw, txo, ntx, tpw;
 };
 
 FrameLayout frame_layout(const sbs_frame& f, size_t base) {
   FrameLayout L;
   const int r = (f.block - 1) / 2;
-  int roff = f.dmax + kRSlack;
-  while ((roff & 3) != 3) ++roff;
-  L.roff = roff;
+  // Left copy: image column c at c + lpad; right copy: at c + rpad. Both pads
+  // are multiples of 4 so 4-pixel groups stay 16-byte aligned; rpad leaves room
+  // for the largest disparity chunk to the left of column 0.
+  L.lpad = (r + 3) & ~3;
+  L.rpad = (L.lpad + f.dmax + kMaxChunk + 1 + 3) & ~3;
   L.lpw = (int)align_up((size_t)f.W + kSpan, 64);
-  L.rpw = (int)align_up((size_t)f.W + kSpan + roff + 4, 64);
+  L.rpw = (int)align_up((size_t)f.W + kSpan + L.rpad, 64);
   L.ph = f.H + 2 * r;
   const int groups = (f.W + 63) / 64;
   L.rbw = (groups + 63) / 64;
@@ -163,6 +166,11 @@ FrameLayout frame_layout(const sbs_frame& f, size_t base) {
   L.lp_off = o; o = align_up(o + (size_t)L.lpw * L.ph * 4, 256);
   L.rp_off = o; o = align_up(o + (size_t)L.rpw * L.ph * 4, 256);
   L.rb_off = o; o = align_up(o + (size_t)f.H * L.rbw * 8, 256);
+  L.txo = (kSpan - L.lpad - r) & ~3;
+  L.ntx = (f.W + L.txo - 1) / L.txo;
+  L.tpw = L.ntx + 1;
+  L.state_off = o; o = align_up(o + 4, 256);
+  L.tptr_off = o; o = align_up(o + (size_t)f.H * L.tpw * 4, 256);
   L.end = o;
   return L;
 }
@@ -271,7 +279,7 @@ int run(const sbs_frame* frames, int nframes, void* workspace, size_t ws_bytes, 
   std::vector<FrameDev> host((size_t)nframes);
   size_t off = kHeaderBytes + table_bytes(nframes);
   int64_t items = 0;
-  int max_rows = 1, max_rbjobs = 1;
+  int max_rows = 1, max_tptr = 1;
   for (int i = 0; i < nframes; ++i) {
     const sbs_frame& f = frames[i];
     FrameLayout L = frame_layout(f, off);
@@ -288,15 +296,18 @@ int run(const sbs_frame* frames, int nframes, void* workspace, size_t ws_bytes, 
     d.lp = (uint32_t*)(base + L.lp_off);
     d.rp = (uint32_t*)(base + L.rp_off);
     d.rowbits = (uint64_t*)(base + L.rb_off);
+    d.state = (uint32_t*)(base + L.state_off);
+    d.tptr = (int32_t*)(base + L.tptr_off);
+    d.tpw = L.tpw;
     d.pitch = f.pitch_bytes;
     d.n = f.n;
     d.W = f.W; d.H = f.H; d.C = f.C;
     d.r = (f.block - 1) / 2;
     d.dmax = f.dmax;
-    d.lpw = L.lpw; d.rpw = L.rpw; d.ph = L.ph; d.roff = L.roff; d.rbw = L.rbw;
-    d.txo = (kSpan - 2 * d.r) & ~3;
+    d.lpw = L.lpw; d.rpw = L.rpw; d.ph = L.ph; d.lpad = L.lpad; d.rpad = L.rpad; d.rbw = L.rbw;
+    d.txo = L.txo;
     d.ty = plan.ty;
-    d.ntx = (f.W + d.txo - 1) / d.txo;
+    d.ntx = L.ntx;
     d.nty = (f.H + d.ty - 1) / d.ty;
     d.chunk = plan.chunk;
     d.nch = (f.dmax + 1 + plan.chunk - 1) / plan.chunk;
@@ -304,14 +315,14 @@ int run(const sbs_frame* frames, int nframes, void* workspace, size_t ws_bytes, 
     d.nitems = f.n > 0 ? (int64_t)d.ntx * d.nty * d.nch : 0;
     items += d.nitems;
     max_rows = std::max(max_rows, L.ph);
-    max_rbjobs = std::max(max_rbjobs, f.H * L.rbw);
+    max_tptr = std::max(max_tptr, f.H * L.tpw);
   }
   hipError_t e = launch_put_desc(table, host.data(), nframes, s);
   if (e != hipSuccess) return hip_fail(e, "descriptor upload");
   if (mode == kPerFrame || mode == kSingle) {
     for (int i = 0; i < nframes; ++i) {
       if (frames[i].n == 0) continue;
-      e = launch_prologue(table, i, 1, host[(size_t)i].ph, frames[i].H * host[(size_t)i].rbw, hdr, s);
+      e = launch_prologue(table, i, 1, host[(size_t)i].ph, frames[i].H * host[(size_t)i].tpw, hdr, s);
       if (e != hipSuccess) return hip_fail(e, "prologue");
       hipEvent_t ev;
       timing_begin(s, &ev);
@@ -322,7 +333,7 @@ int run(const sbs_frame* frames, int nframes, void* workspace, size_t ws_bytes, 
       if (e != hipSuccess) return hip_fail(e, "finalize");
     }
   } else {
-    e = launch_prologue(table, 0, nframes, max_rows, max_rbjobs, hdr, s);
+    e = launch_prologue(table, 0, nframes, max_rows, max_tptr, hdr, s);
     if (e != hipSuccess) return hip_fail(e, "prologue");
     int64_t grid = (int64_t)cus * plan.wpc;
     if (grid > items) grid = items;
@@ -504,9 +515,9 @@ int sbs_set_plan(const sbs_plan* plan) {
   }
   Plan merged;  // fields left at 0 take the defaults for validation
   merged.cpl = plan->cols_per_lane ? plan->cols_per_lane : 4;
-  merged.chunk = plan->chunk ? plan->chunk : 16;
-  merged.ty = plan->tile_rows ? plan->tile_rows : 32;
-  merged.wpc = plan->waves_per_cu ? plan->waves_per_cu : 8;
+  merged.chunk = plan->chunk ? plan->chunk : 8;
+  merged.ty = plan->tile_rows ? plan->tile_rows : 64;
+  merged.wpc = plan->waves_per_cu ? plan->waves_per_cu : 16;
   if (!plan_valid(merged)) return fail(SBS_ERR_INVALID_ARG, "invalid plan");
   std::lock_guard<std::mutex> lk(g_mu);
   g_forced = true;

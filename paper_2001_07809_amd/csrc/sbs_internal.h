@@ -10,8 +10,8 @@ constexpr int kWave = 64;
 constexpr int kColsPerLane = 4;            // CAD columns owned by one lane
 constexpr int kSpan = kWave * kColsPerLane;  // CAD columns per tile (256)
 constexpr int kMaxChunk = 16;              // largest disparity chunk a kernel instance handles
-constexpr int kRSlack = 32;                // >= kMaxChunk + 3: replicate columns left of the right copy
 constexpr int kDescPerLaunch = 8;          // descriptors carried by one upload kernel
+constexpr uint32_t kUnsorted = 1u;         // FrameDev::state bit
 
 // Per-frame descriptor as the kernels see it (lives in the workspace).
 struct FrameDev {
@@ -25,6 +25,8 @@ struct FrameDev {
   uint32_t* lp;        // left copy, RGBx u32 per pixel, replicate-padded
   uint32_t* rp;        // right copy, RGBx u32 per pixel, replicate-padded
   uint64_t* rowbits;   // per row: one bit per 64-column group holding a listed pixel
+  uint32_t* state;     // bit 0: the list is not in non-decreasing raster order
+  int32_t* tptr;       // sorted lists: tptr[y * tpw + t] = first list slot >= y*W + t*txo
   int64_t pitch;       // bytes between image rows
   int64_t n;           // list length
   int64_t item_base;   // first work item of this frame in the batch
@@ -32,12 +34,12 @@ struct FrameDev {
   int32_t W, H, C;
   int32_t r, dmax;
   int32_t lpw, rpw, ph;  // padded copy widths (u32 units) and height (rows)
-  int32_t roff;          // right copy column of image column c is c + r + roff
+  int32_t lpad, rpad;    // copy column of image column c: c + lpad (left), c + rpad (right); multiples of 4
   int32_t rbw;           // u64 words per row in rowbits
   int32_t txo, ty;       // tile: output columns and rows
   int32_t ntx, nty;      // tiles per row / column
   int32_t nch, chunk;    // disparity chunks and their size
-  int32_t pad_;
+  int32_t tpw;           // entries per row of tptr (ntx + 1)
 };
 
 struct DescBatch {

@@ -6,23 +6,27 @@
 // differences between the left window at x and the right window at x - d on
 // the same rows, with replicate padding and ties to the smaller d.
 //
-// Tiled path (per frame):
+// Tiled path (per frame; every kernel also runs over a whole batch of frames):
+//   k_check     clears the result keys, answers indices >= W*H, and finds out
+//               whether the list is in non-decreasing raster order.
 //   k_prep      replicate-padded RGBx copies of both images (one u32 per pixel,
-//               so one v_sad_u8 covers all channels of a pixel) and a cleared
-//               pixel->slot map.
-//   k_scatter   map[p] = largest list slot k with idx[k] == p; keys[k] = max.
-//   k_rowbits   per image row, one bit per 64-column group holding a listed pixel.
+//               so one v_sad_u8 covers all channels of a pixel). For an
+//               unordered list it also clears the pixel->slot map and row bits.
+//   k_scatter   unordered lists: map[p] = largest slot k with idx[k] == p, and
+//               per row one bit per 64-column group that holds a listed pixel.
+//   k_tptr      ordered lists: for each row and tile column, the first list
+//               slot at or after the tile's first pixel (binary search).
 //   k_tile_*    the column-sum kernel. One wavefront owns a tile of output
 //               columns x rows and a chunk of disparities. Each lane owns four
 //               adjacent window columns. Walking down the tile's rows it keeps,
-//               per (column, disparity), running sums of the absolute
-//               differences entering and leaving the w-row window (two
-//               v_sad_u8 per column, disparity and row). On a row that holds
-//               listed pixels it forms prefix sums along the row (in-lane, then
-//               a DPP scan across lanes), stores them in LDS, and each listed
+//               per (column, disparity), the window-column sum of absolute
+//               differences, updated with two v_sad_u8 per (column, disparity,
+//               row): the row entering and the row leaving the window. On a row
+//               that holds listed pixels it forms prefix sums along the row
+//               (in-lane, then a DPP scan across lanes) in LDS; each listed
 //               pixel reads its window sum as a difference of two prefix
-//               entries, then folds (cost << 8 | d) into its slot's key with an
-//               atomic minimum.
+//               entries and folds (cost << 8 | d) into its key with an atomic
+//               minimum (the chunks of one tile run as separate work items).
 //   k_finalize  splits keys into (disparity, cost) for every list entry.
 // Reference path: k_ref evaluates each pixel by brute force straight from the
 // original images, sharing nothing with the tiled path.
@@ -41,69 +45,149 @@ __device__ __forceinline__ uint32_t load_px(const uint8_t* row, int x, int C) {
   return (uint32_t)p[0] | ((uint32_t)p[1] << 8) | ((uint32_t)p[2] << 16);
 }
 
+// Global-memory views (the descriptor's pointers are generic; these let the
+// compiler emit global_load instead of flat_load).
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(1))) const u32x4 g_uint4;
+typedef __attribute__((address_space(1))) const int32_t g_int32;
+typedef __attribute__((address_space(1))) const uint32_t g_uint32;
+typedef __attribute__((address_space(1))) const uint64_t g_uint64;
+
 // ---------------------------------------------------------------------------
 // Descriptor upload: the descriptors travel inside the kernel argument, so a
-// captured graph replays them without touching host memory.
+// captured graph replays them without touching host memory. Each frame's
+// state word is cleared here, before any kernel reads it.
 __global__ void k_put_desc(FrameDev* table, DescBatch b) {
   int i = threadIdx.x;
-  if (i < b.count) table[b.first + i] = b.f[i];
+  if (i < b.count) {
+    table[b.first + i] = b.f[i];
+    *b.f[i].state = 0u;
+  }
 }
 
 __global__ void k_reset_head(WsHeader* h) {
   if (threadIdx.x == 0) h->head = 0ull;
 }
 
-// Padded copies and map clearing. grid: (blocks, frames); frames offset by f0.
-__global__ __launch_bounds__(256) void k_prep(const FrameDev* __restrict__ table, int f0) {
-  const FrameDev& f = table[f0 + blockIdx.y];
-  const int W = f.W, H = f.H, C = f.C, r = f.r;
-  for (int v = blockIdx.x; v < f.ph; v += gridDim.x) {
-    const int y = clampi(v - r, 0, H - 1);
-    const uint8_t* lrow = f.left + (int64_t)y * f.pitch;
-    const uint8_t* rrow = f.right + (int64_t)y * f.pitch;
-    uint32_t* lo = f.lp + (int64_t)v * f.lpw;
-    uint32_t* ro = f.rp + (int64_t)v * f.rpw;
-    for (int u = threadIdx.x; u < f.lpw; u += blockDim.x) lo[u] = load_px(lrow, clampi(u - r, 0, W - 1), C);
-    for (int u = threadIdx.x; u < f.rpw; u += blockDim.x) ro[u] = load_px(rrow, clampi(u - r - f.roff, 0, W - 1), C);
-  }
-  const int64_t N = (int64_t)W * H;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x)
-    f.map[i] = -1;
-}
-
-// map[p] = max k with idx[k] == p; keys cleared; out-of-range entries answered.
-__global__ __launch_bounds__(256) void k_scatter(const FrameDev* __restrict__ table, int f0, WsHeader* hdr) {
+// Keys cleared, out-of-range entries answered, order checked.
+__global__ __launch_bounds__(256) void k_check(const FrameDev* __restrict__ table, int f0, WsHeader* hdr) {
   const FrameDev& f = table[f0 + blockIdx.y];
   const int64_t N = (int64_t)f.W * f.H;
+  bool unsorted = false;
   for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < f.n; k += (int64_t)gridDim.x * blockDim.x) {
     const uint32_t p = f.idx[k];
     f.keys[k] = 0xFFFFFFFFu;
-    if ((int64_t)p < N) {
-      atomicMax(&f.map[p], (int32_t)k);
-    } else {
+    if (k > 0 && f.idx[k - 1] > p) unsorted = true;
+    if ((int64_t)p >= N) {
       f.out_disp[k] = 255;
       if (f.out_cost) f.out_cost[k] = 0xFFFFFFFFu;
       atomicOr(&hdr->error, 1u);
     }
   }
+  if (__builtin_amdgcn_ballot_w64(unsorted) && (threadIdx.x & 63) == 0) atomicOr(f.state, kUnsorted);
 }
 
-// rowbits[y * rbw + w] bit g: some column in [64 (64 w + g), +64) of row y is listed.
-// One wavefront per (row, word); grid: (ceil(H * rbw / 4), frames), 256 threads.
-__global__ __launch_bounds__(256) void k_rowbits(const FrameDev* __restrict__ table, int f0) {
-  const FrameDev& f = table[f0 + blockIdx.y];
-  const int lane = threadIdx.x & 63;
-  const int64_t job = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (job >= (int64_t)f.H * f.rbw) return;
-  const int y = (int)(job / f.rbw), w = (int)(job % f.rbw);
-  const int32_t* mrow = f.map + (int64_t)y * f.W;
-  uint64_t word = 0;
-  for (int g = 0; g < 64; ++g) {
-    const int x = (w * 64 + g) * 64 + lane;
-    const bool hit = x < f.W && mrow[x] >= 0;
-    if (__builtin_amdgcn_ballot_w64(hit)) word |= 1ull << g;
+// Padded copies (and, for unordered lists, map and row-bit clearing). One
+// block per padded row (grid-stride); each thread writes groups of four
+// padded pixels with one 16-byte store. Groups that lie inside the image with
+// a 4-byte-aligned source row read 12 (RGB) or 4 (gray) bytes with aligned
+// dword loads; border groups and unaligned rows read pixel by pixel with
+// clamped coordinates.
+__device__ __forceinline__ uint4 pack_group(const uint8_t* row, int ic0, int W, int C, bool aligned) {
+  uint4 o;
+  if (aligned && ic0 >= 0 && ic0 + 3 < W) {
+    if (C == 3) {
+      const uint32_t* q = (const uint32_t*)(row + (int64_t)ic0 * 3);
+      const uint32_t a = q[0], b = q[1], c = q[2];
+      o.x = a & 0xFFFFFFu;
+      o.y = (a >> 24) | ((b & 0xFFFFu) << 8);
+      o.z = (b >> 16) | ((c & 0xFFu) << 16);
+      o.w = c >> 8;
+    } else {
+      const uint32_t a = *(const uint32_t*)(row + ic0);
+      o.x = a & 0xFFu; o.y = (a >> 8) & 0xFFu; o.z = (a >> 16) & 0xFFu; o.w = a >> 24;
+    }
+  } else {
+    o.x = load_px(row, clampi(ic0 + 0, 0, W - 1), C);
+    o.y = load_px(row, clampi(ic0 + 1, 0, W - 1), C);
+    o.z = load_px(row, clampi(ic0 + 2, 0, W - 1), C);
+    o.w = load_px(row, clampi(ic0 + 3, 0, W - 1), C);
   }
-  if (lane == 0) f.rowbits[job] = word;
+  return o;
+}
+
+__global__ __launch_bounds__(256) void k_prep(const FrameDev* __restrict__ table, int f0) {
+  const FrameDev& f = table[f0 + blockIdx.y];
+  const int W = f.W, H = f.H, C = f.C, r = f.r;
+  const bool unsorted = (*f.state & kUnsorted) != 0;
+  for (int v = blockIdx.x; v < f.ph; v += gridDim.x) {
+    const int y = clampi(v - r, 0, H - 1);
+    const uint8_t* lrow = f.left + (int64_t)y * f.pitch;
+    const uint8_t* rrow = f.right + (int64_t)y * f.pitch;
+    const bool la = ((uintptr_t)lrow & 3) == 0, ra = ((uintptr_t)rrow & 3) == 0;
+    uint4* lo = (uint4*)(f.lp + (int64_t)v * f.lpw);
+    uint4* ro = (uint4*)(f.rp + (int64_t)v * f.rpw);
+    for (int g = threadIdx.x; g < (f.lpw >> 2); g += blockDim.x) lo[g] = pack_group(lrow, 4 * g - f.lpad, W, C, la);
+    for (int g = threadIdx.x; g < (f.rpw >> 2); g += blockDim.x) ro[g] = pack_group(rrow, 4 * g - f.rpad, W, C, ra);
+    if (unsorted && v >= r && v < r + H) {
+      int32_t* mrow = f.map + (int64_t)(v - r) * W;
+      for (int u = threadIdx.x; u < W; u += blockDim.x) mrow[u] = -1;
+      uint64_t* brow = f.rowbits + (int64_t)(v - r) * f.rbw;
+      for (int u = threadIdx.x; u < f.rbw; u += blockDim.x) brow[u] = 0ull;
+    }
+  }
+}
+
+// Unordered lists: map[p] = max k with idx[k] == p; row bits set (one atomic
+// OR per distinct word per wavefront).
+__global__ __launch_bounds__(256) void k_scatter(const FrameDev* __restrict__ table, int f0) {
+  const FrameDev& f = table[f0 + blockIdx.y];
+  if (!(*f.state & kUnsorted)) return;
+  const int64_t N = (int64_t)f.W * f.H;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t first = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63);
+  for (int64_t kb = first; kb < f.n; kb += stride) {       // uniform per wavefront
+    const int64_t k = kb + (threadIdx.x & 63);
+    int64_t word = -1;
+    uint64_t bit = 0;
+    if (k < f.n) {
+      const uint32_t p = f.idx[k];
+      if ((int64_t)p < N) {
+        atomicMax(&f.map[p], (int32_t)k);
+        const int y = (int)(p / (uint32_t)f.W), x = (int)(p % (uint32_t)f.W);
+        word = (int64_t)y * f.rbw + (x >> 12);
+        bit = 1ull << ((x >> 6) & 63);
+      }
+    }
+    bool pending = word >= 0;
+    uint64_t pm;
+    while ((pm = __builtin_amdgcn_ballot_w64(pending)) != 0) {
+      const int leader = __builtin_ctzll(pm);
+      const int64_t lw = __shfl(word, leader, 64);
+      const bool mine = pending && word == lw;
+      uint64_t acc = mine ? bit : 0ull;
+      for (int off = 32; off >= 1; off >>= 1) acc |= __shfl_xor(acc, off, 64);
+      if ((int)(threadIdx.x & 63) == leader) atomicOr((unsigned long long*)&f.rowbits[lw], (unsigned long long)acc);
+      if (mine) pending = false;
+    }
+  }
+}
+
+// Ordered lists: tptr[y * tpw + t] = first slot k with idx[k] >= y*W + min(t*txo, W).
+__global__ __launch_bounds__(256) void k_tptr(const FrameDev* __restrict__ table, int f0) {
+  const FrameDev& f = table[f0 + blockIdx.y];
+  if (*f.state & kUnsorted) return;
+  const int64_t total = (int64_t)f.H * f.tpw;
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < total; j += (int64_t)gridDim.x * blockDim.x) {
+    const int y = (int)(j / f.tpw), t = (int)(j % f.tpw);
+    const uint32_t key = (uint32_t)y * (uint32_t)f.W + (uint32_t)min(t * f.txo, f.W);
+    int64_t lo = 0, hi = f.n;
+    while (lo < hi) {
+      const int64_t mid = (lo + hi) >> 1;
+      if (f.idx[mid] < key) lo = mid + 1; else hi = mid;
+    }
+    f.tptr[j] = (int32_t)lo;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -119,34 +203,42 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
   return v;
 }
 
+// LDS of one work item: prefix sums for the chunk's DC disparities and, for
+// unordered lists, the current row's listed pixels.
 template <int DC>
 struct TileLds {
-  uint32_t pre[DC][kSpan];   // inclusive prefix sums of the window-column sums along the row
-  int32_t eo[kSpan];         // listed pixels of the current row: output column offset
-  int32_t es[kSpan];         //                                 and representative slot
+  uint32_t pre[DC][kSpan];     // inclusive prefix sums of the window-column sums along the row
+  int32_t eo[kSpan];           // unordered lists: listed pixels of the row (output column offset)
+  int32_t es[kSpan];           //                  and their representative slots
 };
 
-// Global-memory views (the descriptor's pointers are generic; these let the
-// compiler emit global_load instead of flat_load).
-typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
-typedef __attribute__((address_space(1))) const u32x4 g_uint4;
-typedef __attribute__((address_space(1))) const int32_t g_int32;
-typedef __attribute__((address_space(1))) const uint64_t g_uint64;
-
-// Loads the pixels one lane needs from padded row `row`: its four left
-// columns, and the DC + 3 right columns that pair with them over the chunk
-// (right index c + DC - 1 - k pairs with left column c at disparity d0 + k).
+// The pixels one lane needs from one padded row: its four left columns, and
+// the DC + 3 right columns that pair with them over the chunk (right index
+// c + DC - k pairs with left column c at disparity d0 + k; index 0 is loaded
+// only to keep the loads 16-byte aligned).
 template <int DC>
-__device__ __forceinline__ void load_row(const FrameDev& f, int row, int lcol, int rbase, uint32_t (&L)[4],
-                                         uint32_t (&R)[DC + 4]) {
-  const u32x4 lv = *(g_uint4*)(f.lp + (int64_t)row * f.lpw + lcol);
-  L[0] = lv.x; L[1] = lv.y; L[2] = lv.z; L[3] = lv.w;
-  g_uint4* rsrc = (g_uint4*)(f.rp + (int64_t)row * f.rpw + rbase);
+struct RowRegs {
+  uint32_t L[4];
+  uint32_t R[DC + 4];
+};
+
+template <int DC>
+__device__ __forceinline__ void load_row(const uint32_t* lrow, const uint32_t* rrow, RowRegs<DC>& o) {
+  const u32x4 lv = *(g_uint4*)lrow;
+  o.L[0] = lv.x; o.L[1] = lv.y; o.L[2] = lv.z; o.L[3] = lv.w;
 #pragma unroll
   for (int q = 0; q < DC / 4 + 1; ++q) {
-    const u32x4 t = rsrc[q];
-    R[4 * q + 0] = t.x; R[4 * q + 1] = t.y; R[4 * q + 2] = t.z; R[4 * q + 3] = t.w;
+    const u32x4 t = ((g_uint4*)rrow)[q];
+    o.R[4 * q + 0] = t.x; o.R[4 * q + 1] = t.y; o.R[4 * q + 2] = t.z; o.R[4 * q + 3] = t.w;
   }
+}
+
+template <int DC>
+__device__ __forceinline__ void add_row(const RowRegs<DC>& a, uint32_t (&cad)[kColsPerLane][DC]) {
+#pragma unroll
+  for (int c = 0; c < kColsPerLane; ++c)
+#pragma unroll
+    for (int k = 0; k < DC; ++k) cad[c][k] = __builtin_amdgcn_sad_u8(a.L[c], a.R[c + DC - k], cad[c][k]);
 }
 
 // One work item = (tile, disparity chunk) of one frame.
@@ -161,18 +253,28 @@ __device__ __forceinline__ void tile_item(const FrameDev& f, int64_t item, TileL
   const int x1 = min(x0 + f.txo, W), y1 = min(y0 + f.ty, H);
   const int d0 = chunk * DC;
   const int dcount = min(DC, f.dmax + 1 - d0);
+  const bool sorted = !(*(g_uint32*)f.state & kUnsorted);
 
-  // Rows of this tile holding a listed pixel in [x0, x1).
+  // Rows of this tile holding a listed pixel in [x0, x1). For ordered lists
+  // lane l keeps the list range of row y0 + l in registers (tp0, tp1).
   bool act = false;
+  int tp0 = 0, tp1 = 0;
   {
     const int y = y0 + lane;
     if (lane < f.ty && y < y1) {
-      const int g0 = x0 >> 6, g1 = (x1 - 1) >> 6;
-      for (int w = g0 >> 6; w <= (g1 >> 6); ++w) {
-        const uint64_t bits = *(g_uint64*)(f.rowbits + (int64_t)y * f.rbw + w);
-        const int lo = max(g0 - 64 * w, 0), hi = min(g1 - 64 * w, 63);
-        const uint64_t m = (hi == 63 ? ~0ull : ((1ull << (hi + 1)) - 1)) & ~((1ull << lo) - 1);
-        if (bits & m) act = true;
+      if (sorted) {
+        const g_int32* tp = (g_int32*)(f.tptr + (int64_t)y * f.tpw + tx);
+        tp0 = tp[0];
+        tp1 = tp[1];
+        act = tp1 > tp0;
+      } else {
+        const int g0 = x0 >> 6, g1 = (x1 - 1) >> 6;
+        for (int w = g0 >> 6; w <= (g1 >> 6); ++w) {
+          const uint64_t bits = *(g_uint64*)(f.rowbits + (int64_t)y * f.rbw + w);
+          const int lo = max(g0 - 64 * w, 0), hi = min(g1 - 64 * w, 63);
+          const uint64_t m = (hi == 63 ? ~0ull : ((1ull << (hi + 1)) - 1)) & ~((1ull << lo) - 1);
+          if (bits & m) act = true;
+        }
       }
     }
   }
@@ -181,8 +283,11 @@ __device__ __forceinline__ void tile_item(const FrameDev& f, int64_t item, TileL
   const int ya = y0 + __builtin_ctzll(rows);
   const int yb = y0 + 63 - __builtin_clzll(rows);
 
-  const int lcol = x0 + kColsPerLane * lane;
-  const int rbase = x0 + kColsPerLane * lane - d0 - (DC - 1) + f.roff;
+  // Per-lane row pointers into the padded copies; padded row q maps to
+  // lp0 + q * lpw and rp0 + q * rpw.
+  const uint32_t* lp0 = f.lp + x0 + kColsPerLane * lane;
+  const uint32_t* rp0 = f.rp + x0 - f.lpad + kColsPerLane * lane - d0 - DC + f.rpad;
+  const int64_t lpw = f.lpw, rpw = f.rpw;
 
   // cad[c][k]: sum over the window's rows of the absolute differences in
   // window column 4 lane + c at disparity d0 + k.
@@ -192,18 +297,64 @@ __device__ __forceinline__ void tile_item(const FrameDev& f, int64_t item, TileL
 #pragma unroll
     for (int k = 0; k < DC; ++k) cad[c][k] = 0;
 
-  // Window of output row ya: padded rows ya .. ya + 2r.
-  for (int row = ya; row <= ya + 2 * r; ++row) {
-    uint32_t L[4], R[DC + 4];
-    load_row<DC>(f, row, lcol, rbase, L, R);
-#pragma unroll
-    for (int c = 0; c < kColsPerLane; ++c)
-#pragma unroll
-      for (int k = 0; k < DC; ++k) cad[c][k] = __builtin_amdgcn_sad_u8(L[c], R[c + DC - 1 - k], cad[c][k]);
+  // Window of output row ya: padded rows ya .. ya + 2r, two rows per pass
+  // with the next row's loads in flight.
+  {
+    const int last = ya + 2 * r;
+    RowRegs<DC> A, B;
+    load_row<DC>(lp0 + ya * lpw, rp0 + ya * rpw, A);
+    for (int q = ya; q <= last; q += 2) {
+      if (q + 1 <= last) load_row<DC>(lp0 + (q + 1) * lpw, rp0 + (q + 1) * rpw, B);
+      add_row<DC>(A, cad);
+      if (q + 1 <= last) {
+        if (q + 2 <= last) load_row<DC>(lp0 + (q + 2) * lpw, rp0 + (q + 2) * rpw, A);
+        add_row<DC>(B, cad);
+      }
+    }
   }
+
+  // Loads for the step y -> y + 1 are issued one iteration ahead: padded row
+  // y + 2r + 1 enters the window, padded row y leaves it.
+  RowRegs<DC> En, Ex;
+  if (ya < yb) {
+    load_row<DC>(lp0 + (ya + 2 * r + 1) * lpw, rp0 + (ya + 2 * r + 1) * rpw, En);
+    load_row<DC>(lp0 + ya * lpw, rp0 + ya * rpw, Ex);
+  }
+  // Unordered lists: map entries of the next active row, loaded ahead.
+  int32_t mv[kColsPerLane];
+  auto load_map = [&](int y) {
+#pragma unroll
+    for (int c = 0; c < kColsPerLane; ++c) {
+      const int o = kColsPerLane * lane + c - f.lpad;
+      mv[c] = (o >= 0 && x0 + o < x1) ? *(g_int32*)(f.map + (int64_t)y * W + x0 + o) : -1;
+    }
+  };
+  if (!sorted) load_map(ya);
 
   for (int y = ya; y <= yb; ++y) {
     if ((rows >> (y - y0)) & 1ull) {
+      // Listed pixels of this row in this tile: first slot e0 and count.
+      int e0 = 0, cnt = 0;
+      uint32_t pfirst = 0;
+      if (sorted) {
+        e0 = __builtin_amdgcn_readlane(tp0, y - y0);
+        cnt = __builtin_amdgcn_readlane(tp1, y - y0) - e0;
+        if (lane < cnt) pfirst = *(g_uint32*)(f.idx + e0 + lane);   // in flight during the scans
+      } else {
+#pragma unroll
+        for (int c = 0; c < kColsPerLane; ++c) {
+          const uint64_t b = __builtin_amdgcn_ballot_w64(mv[c] >= 0);
+          if (mv[c] >= 0) {
+            const int pos = cnt + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32),
+                                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0u));
+            sm.eo[pos] = kColsPerLane * lane + c - f.lpad;
+            sm.es[pos] = mv[c];
+          }
+          cnt += __builtin_popcountll(b);
+        }
+        const uint64_t later = (y - y0 + 1 < 64) ? (rows >> (y - y0 + 1)) : 0ull;
+        if (later) load_map(y + 1 + __builtin_ctzll(later));
+      }
       // Prefix sums of the window-column sums along the row, to LDS.
 #pragma unroll
       for (int k = 0; k < DC; ++k) {
@@ -216,60 +367,53 @@ __device__ __forceinline__ void tile_item(const FrameDev& f, int64_t item, TileL
         o.x = excl + q0; o.y = excl + q1; o.z = excl + q2; o.w = excl + q3;
         *reinterpret_cast<uint4*>(&sm.pre[k][kColsPerLane * lane]) = o;
       }
-      // Listed pixels of this row owned by this tile (output offset o = window column - r).
-      int total = 0;
-#pragma unroll
-      for (int c = 0; c < kColsPerLane; ++c) {
-        const int o = kColsPerLane * lane + c - r;
-        int32_t m = -1;
-        if (o >= 0 && x0 + o < x1) m = *(g_int32*)(f.map + (int64_t)y * W + x0 + o);
-        const uint64_t b = __builtin_amdgcn_ballot_w64(m >= 0);
-        if (m >= 0) {
-          const int pos = total + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32),
-                                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0u));
-          sm.eo[pos] = o;
-          sm.es[pos] = m;
-        }
-        total += __builtin_popcountll(b);
-      }
       __syncthreads();
-      for (int e0 = 0; e0 < total; e0 += kWave) {
-        const int e = e0 + lane;
-        if (e < total) {
-          const int o = sm.eo[e];
-          const int s = sm.es[e];
-          uint32_t best = 0xFFFFFFFFu;
+      // Each listed pixel: window sum = prefix at its right edge minus prefix
+      // left of its left edge; fold the chunk's best (cost << 8 | d) into its key.
+      for (int e = lane; e < cnt; e += kWave) {
+        int o, slot;
+        if (sorted) {
+          const uint32_t p = e < kWave ? pfirst : *(g_uint32*)(f.idx + e0 + e);
+          o = (int)(p - (uint32_t)y * (uint32_t)W) - x0;
+          slot = e0 + e;
+        } else {
+          o = sm.eo[e];
+          slot = sm.es[e];
+        }
+        uint32_t best = 0xFFFFFFFFu;
 #pragma unroll
-          for (int k = 0; k < DC; ++k) {
-            if (k < dcount) {
-              const uint32_t hi = sm.pre[k][o + 2 * r];
-              const uint32_t lo = o > 0 ? sm.pre[k][o - 1] : 0u;
-              best = min(best, ((hi - lo) << 8) | (uint32_t)(d0 + k));
-            }
+        for (int k = 0; k < DC; ++k) {
+          if (k < dcount) {
+            const uint32_t hi = sm.pre[k][o + f.lpad + r];
+            const uint32_t lo = o + f.lpad - r > 0 ? sm.pre[k][o + f.lpad - r - 1] : 0u;
+            best = min(best, ((hi - lo) << 8) | (uint32_t)(d0 + k));
           }
-          atomicMin(&f.keys[s], best);
         }
+        atomicMin(&f.keys[slot], best);
       }
-      __syncthreads();
+      __syncthreads();   // LDS free for the next row
     }
     if (y < yb) {
-      // Slide the window down one row: add padded row y + 2r + 1, drop padded row y.
-      uint32_t Ln[4], Rn[DC + 4], Lo[4], Ro[DC + 4];
-      load_row<DC>(f, y + 2 * r + 1, lcol, rbase, Ln, Rn);
-      load_row<DC>(f, y, lcol, rbase, Lo, Ro);
+      // Slide the window down one row.
 #pragma unroll
       for (int c = 0; c < kColsPerLane; ++c)
 #pragma unroll
         for (int k = 0; k < DC; ++k) {
-          const uint32_t out = __builtin_amdgcn_sad_u8(Lo[c], Ro[c + DC - 1 - k], 0u);
-          cad[c][k] = __builtin_amdgcn_sad_u8(Ln[c], Rn[c + DC - 1 - k], cad[c][k]) - out;
+          const uint32_t out = __builtin_amdgcn_sad_u8(Ex.L[c], Ex.R[c + DC - k], 0u);
+          cad[c][k] = __builtin_amdgcn_sad_u8(En.L[c], En.R[c + DC - k], cad[c][k]) - out;
         }
+      if (y + 1 < yb) {
+        load_row<DC>(lp0 + (y + 2 * r + 2) * lpw, rp0 + (y + 2 * r + 2) * rpw, En);
+        load_row<DC>(lp0 + (y + 1) * lpw, rp0 + (y + 1) * rpw, Ex);
+      }
     }
   }
 }
 
+// Occupancy target: four wavefronts per SIMD (128 VGPRs) for the 8-disparity
+// chunk, two for the 16-disparity chunk.
 template <int DC>
-__global__ __launch_bounds__(64) void k_tile_grid(const FrameDev* __restrict__ table, int fi) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(DC == 8 ? 4 : 2, 8))) void k_tile_grid(const FrameDev* __restrict__ table, int fi) {
   __shared__ TileLds<DC> sm;
   const FrameDev& f = table[fi];
   tile_item<DC>(f, (int64_t)blockIdx.x, sm);
@@ -277,7 +421,7 @@ __global__ __launch_bounds__(64) void k_tile_grid(const FrameDev* __restrict__ t
 
 // Persistent form: every workgroup pops work items of all frames from one queue.
 template <int DC>
-__global__ __launch_bounds__(64) void k_tile_persistent(const FrameDev* __restrict__ table, int nframes,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(DC == 8 ? 4 : 2, 8))) void k_tile_persistent(const FrameDev* __restrict__ table, int nframes,
                                                         int64_t total, WsHeader* hdr) {
   __shared__ TileLds<DC> sm;
   __shared__ long long next_item;
@@ -301,10 +445,11 @@ __global__ __launch_bounds__(64) void k_tile_persistent(const FrameDev* __restri
 __global__ __launch_bounds__(256) void k_finalize(const FrameDev* __restrict__ table, int f0) {
   const FrameDev& f = table[f0 + blockIdx.y];
   const int64_t N = (int64_t)f.W * f.H;
+  const bool unsorted = (*f.state & kUnsorted) != 0;
   for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < f.n; k += (int64_t)gridDim.x * blockDim.x) {
     const uint32_t p = f.idx[k];
     if ((int64_t)p >= N) continue;
-    const uint32_t key = f.keys[f.map[p]];
+    const uint32_t key = f.keys[unsorted ? (int64_t)f.map[p] : k];
     f.out_disp[k] = (uint8_t)(key & 0xFFu);
     if (f.out_cost) f.out_cost[k] = key >> 8;
   }
@@ -366,20 +511,22 @@ hipError_t launch_put_desc(FrameDev* table, const FrameDev* host, int nframes, h
   return hipGetLastError();
 }
 
-hipError_t launch_prologue(const FrameDev* table, int f0, int nf, int max_rows, int max_rbjobs, WsHeader* hdr,
+hipError_t launch_prologue(const FrameDev* table, int f0, int nf, int max_rows, int max_tptr, WsHeader* hdr,
                            hipStream_t s) {
-  int gx = max_rows < 1024 ? max_rows : 1024;
+  hipLaunchKernelGGL(k_check, dim3(64, nf), dim3(256), 0, s, table, f0, hdr);
+  int gx = max_rows < 2048 ? max_rows : 2048;
   if (gx < 1) gx = 1;
   hipLaunchKernelGGL(k_prep, dim3(gx, nf), dim3(256), 0, s, table, f0);
-  hipLaunchKernelGGL(k_scatter, dim3(256, nf), dim3(256), 0, s, table, f0, hdr);
-  int gr = (max_rbjobs + 3) / 4;
-  if (gr < 1) gr = 1;
-  hipLaunchKernelGGL(k_rowbits, dim3(gr, nf), dim3(256), 0, s, table, f0);
+  hipLaunchKernelGGL(k_scatter, dim3(256, nf), dim3(256), 0, s, table, f0);
+  int gt = (max_tptr + 255) / 256;
+  if (gt > 1024) gt = 1024;
+  if (gt < 1) gt = 1;
+  hipLaunchKernelGGL(k_tptr, dim3(gt, nf), dim3(256), 0, s, table, f0);
   return hipGetLastError();
 }
 
 hipError_t launch_finalize(const FrameDev* table, int f0, int nf, hipStream_t s) {
-  hipLaunchKernelGGL(k_finalize, dim3(256, nf), dim3(256), 0, s, table, f0);
+  hipLaunchKernelGGL(k_finalize, dim3(64, nf), dim3(256), 0, s, table, f0);
   return hipGetLastError();
 }
 
