@@ -23,8 +23,8 @@ hipError_t launch_prologue(const FrameDev* table, int f0, int nf, int max_rows, 
                            hipStream_t s);
 hipError_t launch_finalize(const FrameDev* table, int f0, int nf, hipStream_t s);
 hipError_t launch_tile_grid(const FrameDev* table, int fi, int64_t nitems, int chunk, hipStream_t s);
-hipError_t launch_tile_persistent(const FrameDev* table, int nframes, int64_t total, int chunk, int grid,
-                                  WsHeader* hdr, hipStream_t s);
+hipError_t launch_tile_persistent(const FrameDev* table, int nframes, const QueueTotals& totals, int chunk,
+                                  int grid, WsHeader* hdr, hipStream_t s);
 hipError_t launch_ref(const uint8_t* L, const uint8_t* R, int W, int H, int C, int64_t pitch, const uint32_t* idx,
                       int64_t n, int r, int dmax, uint8_t* od, uint32_t* oc, uint32_t* err, hipStream_t s);
 }  // namespace sbs
@@ -163,8 +163,9 @@ FrameLayout frame_layout(const sbs_frame& f, size_t base) {
   size_t o = align_up(base, 256);
   L.map_off = o; o = align_up(o + (size_t)f.W * f.H * 4, 256);
   L.keys_off = o; o = align_up(o + (size_t)std::max<int64_t>(f.n, 1) * 4, 256);
-  L.lp_off = o; o = align_up(o + (size_t)L.lpw * L.ph * 4, 256);
-  L.rp_off = o; o = align_up(o + (size_t)L.rpw * L.ph * 4, 256);
+  // One spare padded row at the bottom: the tile kernel's last prefetch reads it and discards it.
+  L.lp_off = o; o = align_up(o + (size_t)L.lpw * (L.ph + 1) * 4, 256);
+  L.rp_off = o; o = align_up(o + (size_t)L.rpw * (L.ph + 1) * 4, 256);
   L.rb_off = o; o = align_up(o + (size_t)f.H * L.rbw * 8, 256);
   L.txo = (kSpan - L.lpad - r) & ~3;
   L.ntx = (f.W + L.txo - 1) / L.txo;
@@ -279,6 +280,7 @@ int run(const sbs_frame* frames, int nframes, void* workspace, size_t ws_bytes, 
   std::vector<FrameDev> host((size_t)nframes);
   size_t off = kHeaderBytes + table_bytes(nframes);
   int64_t items = 0;
+  QueueTotals qt{};
   int max_rows = 1, max_tptr = 1;
   for (int i = 0; i < nframes; ++i) {
     const sbs_frame& f = frames[i];
@@ -314,6 +316,12 @@ int run(const sbs_frame* frames, int nframes, void* workspace, size_t ws_bytes, 
     d.item_base = items;
     d.nitems = f.n > 0 ? (int64_t)d.ntx * d.nty * d.nch : 0;
     items += d.nitems;
+    const int64_t ntiles = f.n > 0 ? (int64_t)d.ntx * d.nty : 0;
+    for (int q = 0; q < kQueues; ++q) {
+      d.xbase[q] = qt.t[q];
+      const int64_t tq = ntiles > q ? (ntiles - q + kQueues - 1) / kQueues : 0;
+      qt.t[q] += tq * d.nch;
+    }
     max_rows = std::max(max_rows, L.ph);
     max_tptr = std::max(max_tptr, f.H * L.tpw);
   }
@@ -339,7 +347,7 @@ int run(const sbs_frame* frames, int nframes, void* workspace, size_t ws_bytes, 
     if (grid > items) grid = items;
     hipEvent_t ev;
     timing_begin(s, &ev);
-    e = launch_tile_persistent(table, nframes, items, plan.chunk, (int)std::max<int64_t>(grid, 1), hdr, s);
+    e = launch_tile_persistent(table, nframes, qt, plan.chunk, (int)std::max<int64_t>(grid, 1), hdr, s);
     timing_end(s, ev);
     if (e != hipSuccess) return hip_fail(e, "persistent tile kernel");
     e = launch_finalize(table, 0, nframes, s);

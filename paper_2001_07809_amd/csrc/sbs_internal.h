@@ -12,6 +12,7 @@ constexpr int kSpan = kWave * kColsPerLane;  // CAD columns per tile (256)
 constexpr int kMaxChunk = 16;              // largest disparity chunk a kernel instance handles
 constexpr int kDescPerLaunch = 8;          // descriptors carried by one upload kernel
 constexpr uint32_t kUnsorted = 1u;         // FrameDev::state bit
+constexpr int kQueues = 8;                 // one work queue per XCD; tile t's items go to queue t % 8
 
 // Per-frame descriptor as the kernels see it (lives in the workspace).
 struct FrameDev {
@@ -29,8 +30,9 @@ struct FrameDev {
   int32_t* tptr;       // sorted lists: tptr[y * tpw + t] = first list slot >= y*W + t*txo
   int64_t pitch;       // bytes between image rows
   int64_t n;           // list length
-  int64_t item_base;   // first work item of this frame in the batch
+  int64_t item_base;   // first work item of this frame in the batch (one-queue order)
   int64_t nitems;      // work items of this frame (tiles x chunks)
+  int64_t xbase[kQueues];  // first item of this frame in each XCD queue
   int32_t W, H, C;
   int32_t r, dmax;
   int32_t lpw, rpw, ph;  // padded copy widths (u32 units) and height (rows)
@@ -49,13 +51,19 @@ struct DescBatch {
 };
 
 // Workspace header at offset 0 of every workspace.
+struct QueueTotals {
+  int64_t t[kQueues];
+};
+
 struct WsHeader {
   uint32_t error;        // bit 0: an index >= W*H was seen
   uint32_t pad0[15];
-  unsigned long long head;  // persistent queue head
-  uint64_t pad1[7];
+  struct {
+    unsigned long long head;  // next item of this queue (own 64-byte line)
+    uint64_t pad[7];
+  } q[kQueues];
 };
-constexpr size_t kHeaderBytes = 256;
+constexpr size_t kHeaderBytes = 1024;
 static_assert(sizeof(WsHeader) <= kHeaderBytes, "header");
 
 }  // namespace sbs

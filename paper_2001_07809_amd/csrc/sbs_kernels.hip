@@ -66,7 +66,7 @@ __global__ void k_put_desc(FrameDev* table, DescBatch b) {
 }
 
 __global__ void k_reset_head(WsHeader* h) {
-  if (threadIdx.x == 0) h->head = 0ull;
+  if (threadIdx.x < kQueues) h->q[threadIdx.x].head = 0ull;
 }
 
 // Keys cleared, out-of-range entries answered, order checked.
@@ -204,16 +204,20 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
 }
 
 // LDS of one work item: prefix sums for the chunk's DC disparities and, for
-// unordered lists, the current row's listed pixels.
+// unordered lists, the current row's listed pixels. pre[k][4 + j] is the
+// inclusive prefix sum over window columns 0..j; pre[k][0..3] stay zero, so a
+// window that starts at column 0 needs no special case.
 template <int DC>
 struct TileLds {
-  uint32_t pre[DC][kSpan];     // inclusive prefix sums of the window-column sums along the row
+  uint32_t pre[DC][kSpan + 4] __attribute__((aligned(16)));
   int32_t eo[kSpan];           // unordered lists: listed pixels of the row (output column offset)
   int32_t es[kSpan];           //                  and their representative slots
 };
 
+typedef __attribute__((address_space(3))) u32x4 lds_u32x4;
+
 // The pixels one lane needs from one padded row: its four left columns, and
-// the DC + 3 right columns that pair with them over the chunk (right index
+// the DC + 4 right columns that pair with them over the chunk (right index
 // c + DC - k pairs with left column c at disparity d0 + k; index 0 is loaded
 // only to keep the loads 16-byte aligned).
 template <int DC>
@@ -241,18 +245,18 @@ __device__ __forceinline__ void add_row(const RowRegs<DC>& a, uint32_t (&cad)[kC
     for (int k = 0; k < DC; ++k) cad[c][k] = __builtin_amdgcn_sad_u8(a.L[c], a.R[c + DC - k], cad[c][k]);
 }
 
-// One work item = (tile, disparity chunk) of one frame.
+// One work item: tile `tile` (row-major over the frame's ntx x nty tiles),
+// disparity chunk `chunk` (disparities chunk*DC .. +DC-1).
 template <int DC>
-__device__ __forceinline__ void tile_item(const FrameDev& f, int64_t item, TileLds<DC>& sm) {
+__device__ __forceinline__ void tile_item(const FrameDev& f, int tile, int chunk, TileLds<DC>& sm) {
   const int lane = threadIdx.x;
-  const int chunk = (int)(item % f.nch);
-  const int64_t tile = item / f.nch;
-  const int tx = (int)(tile % f.ntx), tyi = (int)(tile / f.ntx);
+  const int tx = tile % f.ntx, tyi = tile / f.ntx;
   const int W = f.W, H = f.H, r = f.r;
   const int x0 = tx * f.txo, y0 = tyi * f.ty;
   const int x1 = min(x0 + f.txo, W), y1 = min(y0 + f.ty, H);
   const int d0 = chunk * DC;
   const int dcount = min(DC, f.dmax + 1 - d0);
+  const int lpad = f.lpad;
   const bool sorted = !(*(g_uint32*)f.state & kUnsorted);
 
   // Rows of this tile holding a listed pixel in [x0, x1). For ordered lists
@@ -286,8 +290,13 @@ __device__ __forceinline__ void tile_item(const FrameDev& f, int64_t item, TileL
   // Per-lane row pointers into the padded copies; padded row q maps to
   // lp0 + q * lpw and rp0 + q * rpw.
   const uint32_t* lp0 = f.lp + x0 + kColsPerLane * lane;
-  const uint32_t* rp0 = f.rp + x0 - f.lpad + kColsPerLane * lane - d0 - DC + f.rpad;
+  const uint32_t* rp0 = f.rp + x0 - lpad + kColsPerLane * lane - d0 - DC + f.rpad;
   const int64_t lpw = f.lpw, rpw = f.rpw;
+
+  // Disparities beyond dmax (last chunk only) never win: their keys are forced to ~0.
+  uint32_t kill[DC];
+#pragma unroll
+  for (int k = 0; k < DC; ++k) kill[k] = k < dcount ? 0u : 0xFFFFFFFFu;
 
   // cad[c][k]: sum over the window's rows of the absolute differences in
   // window column 4 lane + c at disparity d0 + k.
@@ -297,148 +306,167 @@ __device__ __forceinline__ void tile_item(const FrameDev& f, int64_t item, TileL
 #pragma unroll
     for (int k = 0; k < DC; ++k) cad[c][k] = 0;
 
-  // Window of output row ya: padded rows ya .. ya + 2r, two rows per pass
-  // with the next row's loads in flight.
+  // Window of output row ya: padded rows ya .. ya + 2r (an odd count), in
+  // pairs with the next row's loads in flight, then the last row.
   {
     const int last = ya + 2 * r;
     RowRegs<DC> A, B;
     load_row<DC>(lp0 + ya * lpw, rp0 + ya * rpw, A);
-    for (int q = ya; q <= last; q += 2) {
-      if (q + 1 <= last) load_row<DC>(lp0 + (q + 1) * lpw, rp0 + (q + 1) * rpw, B);
+    for (int q = ya; q < last; q += 2) {
+      load_row<DC>(lp0 + (q + 1) * lpw, rp0 + (q + 1) * rpw, B);
       add_row<DC>(A, cad);
-      if (q + 1 <= last) {
-        if (q + 2 <= last) load_row<DC>(lp0 + (q + 2) * lpw, rp0 + (q + 2) * rpw, A);
-        add_row<DC>(B, cad);
-      }
+      load_row<DC>(lp0 + (q + 2) * lpw, rp0 + (q + 2) * rpw, A);
+      add_row<DC>(B, cad);
     }
+    add_row<DC>(A, cad);
   }
 
-  // Loads for the step y -> y + 1 are issued one iteration ahead: padded row
-  // y + 2r + 1 enters the window, padded row y leaves it.
-  RowRegs<DC> En, Ex;
-  if (ya < yb) {
-    load_row<DC>(lp0 + (ya + 2 * r + 1) * lpw, rp0 + (ya + 2 * r + 1) * rpw, En);
-    load_row<DC>(lp0 + ya * lpw, rp0 + ya * rpw, Ex);
-  }
   // Unordered lists: map entries of the next active row, loaded ahead.
   int32_t mv[kColsPerLane];
   auto load_map = [&](int y) {
 #pragma unroll
     for (int c = 0; c < kColsPerLane; ++c) {
-      const int o = kColsPerLane * lane + c - f.lpad;
+      const int o = kColsPerLane * lane + c - lpad;
       mv[c] = (o >= 0 && x0 + o < x1) ? *(g_int32*)(f.map + (int64_t)y * W + x0 + o) : -1;
     }
   };
   if (!sorted) load_map(ya);
 
-  for (int y = ya; y <= yb; ++y) {
-    if ((rows >> (y - y0)) & 1ull) {
-      // Listed pixels of this row in this tile: first slot e0 and count.
-      int e0 = 0, cnt = 0;
-      uint32_t pfirst = 0;
-      if (sorted) {
-        e0 = __builtin_amdgcn_readlane(tp0, y - y0);
-        cnt = __builtin_amdgcn_readlane(tp1, y - y0) - e0;
-        if (lane < cnt) pfirst = *(g_uint32*)(f.idx + e0 + lane);   // in flight during the scans
-      } else {
+  // Work on an active row: prefix sums to LDS, then every listed pixel of the
+  // row reads its window sum as the difference of two prefix entries.
+  auto row_work = [&](int y) {
+    int e0 = 0, cnt = 0;
+    uint32_t pfirst = 0;
+    if (sorted) {
+      e0 = __builtin_amdgcn_readlane(tp0, y - y0);
+      cnt = __builtin_amdgcn_readlane(tp1, y - y0) - e0;
+      if (lane < cnt) pfirst = *(g_uint32*)(f.idx + e0 + lane);   // in flight during the scans
+    } else {
 #pragma unroll
-        for (int c = 0; c < kColsPerLane; ++c) {
-          const uint64_t b = __builtin_amdgcn_ballot_w64(mv[c] >= 0);
-          if (mv[c] >= 0) {
-            const int pos = cnt + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32),
-                                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0u));
-            sm.eo[pos] = kColsPerLane * lane + c - f.lpad;
-            sm.es[pos] = mv[c];
-          }
-          cnt += __builtin_popcountll(b);
+      for (int c = 0; c < kColsPerLane; ++c) {
+        const uint64_t b = __builtin_amdgcn_ballot_w64(mv[c] >= 0);
+        if (mv[c] >= 0) {
+          const int pos = cnt + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32),
+                                                               __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0u));
+          sm.eo[pos] = kColsPerLane * lane + c - lpad;
+          sm.es[pos] = mv[c];
         }
-        const uint64_t later = (y - y0 + 1 < 64) ? (rows >> (y - y0 + 1)) : 0ull;
-        if (later) load_map(y + 1 + __builtin_ctzll(later));
+        cnt += __builtin_popcountll(b);
       }
-      // Prefix sums of the window-column sums along the row, to LDS.
+      const uint64_t later = (y - y0 + 1 < 64) ? (rows >> (y - y0 + 1)) : 0ull;
+      if (later) load_map(y + 1 + __builtin_ctzll(later));
+    }
+#pragma unroll
+    for (int k = 0; k < DC; ++k) {
+      const uint32_t q0 = cad[0][k];
+      const uint32_t q1 = q0 + cad[1][k];
+      const uint32_t q2 = q1 + cad[2][k];
+      const uint32_t q3 = q2 + cad[3][k];
+      const uint32_t excl = wave_incl_scan(q3) - q3;
+      u32x4 o;
+      o.x = excl + q0; o.y = excl + q1; o.z = excl + q2; o.w = excl + q3;
+      *(lds_u32x4*)&sm.pre[k][4 + kColsPerLane * lane] = o;
+    }
+    __syncthreads();
+    // Output offset o (0 <= o < txo): window columns o + lpad - r .. o + lpad + r.
+    for (int e = lane; e < cnt; e += kWave) {
+      int o, slot;
+      if (sorted) {
+        const uint32_t p = e < kWave ? pfirst : *(g_uint32*)(f.idx + e0 + e);
+        o = (int)(p - (uint32_t)y * (uint32_t)W) - x0;
+        slot = e0 + e;
+      } else {
+        o = sm.eo[e];
+        slot = sm.es[e];
+      }
+      const int ih = 4 + o + lpad + r, il = 3 + o + lpad - r;
+      uint32_t best = 0xFFFFFFFFu;
 #pragma unroll
       for (int k = 0; k < DC; ++k) {
-        const uint32_t q0 = cad[0][k];
-        const uint32_t q1 = q0 + cad[1][k];
-        const uint32_t q2 = q1 + cad[2][k];
-        const uint32_t q3 = q2 + cad[3][k];
-        const uint32_t excl = wave_incl_scan(q3) - q3;
-        uint4 o;
-        o.x = excl + q0; o.y = excl + q1; o.z = excl + q2; o.w = excl + q3;
-        *reinterpret_cast<uint4*>(&sm.pre[k][kColsPerLane * lane]) = o;
+        const uint32_t s = sm.pre[k][ih] - sm.pre[k][il];
+        best = min(best, ((s << 8) | (uint32_t)(d0 + k)) | kill[k]);
       }
-      __syncthreads();
-      // Each listed pixel: window sum = prefix at its right edge minus prefix
-      // left of its left edge; fold the chunk's best (cost << 8 | d) into its key.
-      for (int e = lane; e < cnt; e += kWave) {
-        int o, slot;
-        if (sorted) {
-          const uint32_t p = e < kWave ? pfirst : *(g_uint32*)(f.idx + e0 + e);
-          o = (int)(p - (uint32_t)y * (uint32_t)W) - x0;
-          slot = e0 + e;
-        } else {
-          o = sm.eo[e];
-          slot = sm.es[e];
-        }
-        uint32_t best = 0xFFFFFFFFu;
-#pragma unroll
-        for (int k = 0; k < DC; ++k) {
-          if (k < dcount) {
-            const uint32_t hi = sm.pre[k][o + f.lpad + r];
-            const uint32_t lo = o + f.lpad - r > 0 ? sm.pre[k][o + f.lpad - r - 1] : 0u;
-            best = min(best, ((hi - lo) << 8) | (uint32_t)(d0 + k));
-          }
-        }
-        atomicMin(&f.keys[slot], best);
-      }
-      __syncthreads();   // LDS free for the next row
+      atomicMin(&f.keys[slot], best);
     }
-    if (y < yb) {
-      // Slide the window down one row.
+    __syncthreads();   // LDS free for the next row
+  };
+
+  // Walk down the rows. The loads for the step y -> y + 1 (padded row
+  // y + 2r + 1 enters the window, padded row y leaves it) are issued one step
+  // ahead; the copies hold one spare padded row so the last, unused prefetch
+  // stays in bounds.
+  const uint32_t* lin = lp0 + (int64_t)(ya + 2 * r + 1) * lpw;
+  const uint32_t* rin = rp0 + (int64_t)(ya + 2 * r + 1) * rpw;
+  const uint32_t* lout = lp0 + (int64_t)ya * lpw;
+  const uint32_t* rout = rp0 + (int64_t)ya * rpw;
+  RowRegs<DC> En, Ex;
+  load_row<DC>(lin, rin, En);
+  load_row<DC>(lout, rout, Ex);
+  for (int y = ya; y < yb; ++y) {
+    if ((rows >> (y - y0)) & 1ull) row_work(y);
 #pragma unroll
-      for (int c = 0; c < kColsPerLane; ++c)
+    for (int c = 0; c < kColsPerLane; ++c)
 #pragma unroll
-        for (int k = 0; k < DC; ++k) {
-          const uint32_t out = __builtin_amdgcn_sad_u8(Ex.L[c], Ex.R[c + DC - k], 0u);
-          cad[c][k] = __builtin_amdgcn_sad_u8(En.L[c], En.R[c + DC - k], cad[c][k]) - out;
-        }
-      if (y + 1 < yb) {
-        load_row<DC>(lp0 + (y + 2 * r + 2) * lpw, rp0 + (y + 2 * r + 2) * rpw, En);
-        load_row<DC>(lp0 + (y + 1) * lpw, rp0 + (y + 1) * rpw, Ex);
+      for (int k = 0; k < DC; ++k) {
+        const uint32_t out = __builtin_amdgcn_sad_u8(Ex.L[c], Ex.R[c + DC - k], 0u);
+        cad[c][k] = __builtin_amdgcn_sad_u8(En.L[c], En.R[c + DC - k], cad[c][k]) - out;
       }
-    }
+    lin += lpw; rin += rpw; lout += lpw; rout += rpw;
+    load_row<DC>(lin, rin, En);
+    load_row<DC>(lout, rout, Ex);
   }
+  row_work(yb);
+}
+
+template <int DC>
+__device__ __forceinline__ void zero_lds_front(TileLds<DC>& sm) {
+  if (threadIdx.x < DC * 4) sm.pre[threadIdx.x >> 2][threadIdx.x & 3] = 0u;
+  __syncthreads();
 }
 
 // Occupancy target: four wavefronts per SIMD (128 VGPRs) for the 8-disparity
 // chunk, two for the 16-disparity chunk.
 template <int DC>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(DC == 8 ? 4 : 2, 8))) void k_tile_grid(const FrameDev* __restrict__ table, int fi) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(DC == 8 ? 4 : 2, 8))) void k_tile_grid(
+    const FrameDev* __restrict__ table, int fi) {
   __shared__ TileLds<DC> sm;
+  zero_lds_front<DC>(sm);
   const FrameDev& f = table[fi];
-  tile_item<DC>(f, (int64_t)blockIdx.x, sm);
+  const uint32_t item = blockIdx.x;
+  tile_item<DC>(f, (int)(item / (uint32_t)f.nch), (int)(item % (uint32_t)f.nch), sm);
 }
 
-// Persistent form: every workgroup pops work items of all frames from one queue.
+// Persistent form: one work queue per XCD. Tile t of a frame goes to queue
+// t % 8, so the disparity chunks of a tile run on one XCD and share its L2.
+// Workgroup w starts on queue w % 8 (the XCD the hardware places it on) and,
+// once that queue is empty, takes items from the others.
 template <int DC>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(DC == 8 ? 4 : 2, 8))) void k_tile_persistent(const FrameDev* __restrict__ table, int nframes,
-                                                        int64_t total, WsHeader* hdr) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(DC == 8 ? 4 : 2, 8))) void k_tile_persistent(
+    const FrameDev* __restrict__ table, int nframes, QueueTotals totals, WsHeader* hdr) {
   __shared__ TileLds<DC> sm;
   __shared__ long long next_item;
-  for (;;) {
-    if (threadIdx.x == 0) next_item = (long long)atomicAdd(&hdr->head, 1ull);
-    __syncthreads();
-    const int64_t it = next_item;
-    __syncthreads();
-    if (it >= total) return;
-    // frame of this item: last frame with item_base <= it
-    int lo = 0, hi = nframes - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (table[mid].item_base <= it) lo = mid; else hi = mid - 1;
+  zero_lds_front<DC>(sm);
+  const int home = blockIdx.x % kQueues;
+  for (int qi = 0; qi < kQueues; ++qi) {
+    const int q = (home + qi) % kQueues;
+    const int64_t total = totals.t[q];
+    for (;;) {
+      if (threadIdx.x == 0) next_item = (long long)atomicAdd(&hdr->q[q].head, 1ull);
+      __syncthreads();
+      const int64_t it = next_item;
+      __syncthreads();
+      if (it >= total) break;
+      // frame of this item: last frame with xbase[q] <= it
+      int lo = 0, hi = nframes - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (table[mid].xbase[q] <= it) lo = mid; else hi = mid - 1;
+      }
+      const FrameDev& f = table[lo];
+      const uint32_t local = (uint32_t)(it - f.xbase[q]);
+      const int tile = q + kQueues * (int)(local / (uint32_t)f.nch);
+      tile_item<DC>(f, tile, (int)(local % (uint32_t)f.nch), sm);
     }
-    const FrameDev& f = table[lo];
-    tile_item<DC>(f, it - f.item_base, sm);
   }
 }
 
@@ -537,14 +565,13 @@ hipError_t launch_tile_grid(const FrameDev* table, int fi, int64_t nitems, int c
   return hipGetLastError();
 }
 
-hipError_t launch_tile_persistent(const FrameDev* table, int nframes, int64_t total, int chunk, int grid,
-                                  WsHeader* hdr, hipStream_t s) {
+hipError_t launch_tile_persistent(const FrameDev* table, int nframes, const QueueTotals& totals, int chunk,
+                                  int grid, WsHeader* hdr, hipStream_t s) {
   hipLaunchKernelGGL(k_reset_head, dim3(1), dim3(64), 0, s, hdr);
-  if (total <= 0) return hipGetLastError();
   if (chunk == 8)
-    hipLaunchKernelGGL(k_tile_persistent<8>, dim3(grid), dim3(64), 0, s, table, nframes, total, hdr);
+    hipLaunchKernelGGL(k_tile_persistent<8>, dim3(grid), dim3(64), 0, s, table, nframes, totals, hdr);
   else
-    hipLaunchKernelGGL(k_tile_persistent<16>, dim3(grid), dim3(64), 0, s, table, nframes, total, hdr);
+    hipLaunchKernelGGL(k_tile_persistent<16>, dim3(grid), dim3(64), 0, s, table, nframes, totals, hdr);
   return hipGetLastError();
 }
 
