@@ -240,7 +240,10 @@ def main():
         idx0 = lists[0]
         rng = np.random.default_rng(0)
         perm = np.sort(rng.permutation(idx0.size))
-        probe = idx0[perm[:: max(1, idx0.size // 256)]][:256]
+        # Size the sample from a probe run (the first, small call also pays the
+        # thread-pool start-up, so it is not timed).
+        oracle.sad(left[0], right[0], idx0[:64], spec.block, spec.dmax, threads=threads)
+        probe = idx0[perm[:: max(1, idx0.size // 4096)]][:4096]
         t0 = time.perf_counter()
         oracle.sad(left[0], right[0], probe, spec.block, spec.dmax, threads=threads)
         per_entry = (time.perf_counter() - t0) / max(probe.size, 1)

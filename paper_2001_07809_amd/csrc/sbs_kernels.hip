@@ -193,6 +193,20 @@ __global__ __launch_bounds__(256) void k_tptr(const FrameDev* __restrict__ table
 // ---------------------------------------------------------------------------
 // Wave-wide inclusive prefix sum with DPP: shifts within rows of 16 lanes,
 // then broadcasts of lane 15 and lane 31 to the rows above.
+#define SBS_DPP_STEP(v, ctrl, rmask) \
+  (v) += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(v), (ctrl), (rmask), 0xf, false)
+
+// Four independent scans with their steps interleaved, so each DPP read has
+// other work between it and the write of its source.
+__device__ __forceinline__ void wave_incl_scan4(uint32_t& a, uint32_t& b, uint32_t& c, uint32_t& d) {
+  SBS_DPP_STEP(a, 0x111, 0xf); SBS_DPP_STEP(b, 0x111, 0xf); SBS_DPP_STEP(c, 0x111, 0xf); SBS_DPP_STEP(d, 0x111, 0xf);
+  SBS_DPP_STEP(a, 0x112, 0xf); SBS_DPP_STEP(b, 0x112, 0xf); SBS_DPP_STEP(c, 0x112, 0xf); SBS_DPP_STEP(d, 0x112, 0xf);
+  SBS_DPP_STEP(a, 0x114, 0xf); SBS_DPP_STEP(b, 0x114, 0xf); SBS_DPP_STEP(c, 0x114, 0xf); SBS_DPP_STEP(d, 0x114, 0xf);
+  SBS_DPP_STEP(a, 0x118, 0xf); SBS_DPP_STEP(b, 0x118, 0xf); SBS_DPP_STEP(c, 0x118, 0xf); SBS_DPP_STEP(d, 0x118, 0xf);
+  SBS_DPP_STEP(a, 0x142, 0xa); SBS_DPP_STEP(b, 0x142, 0xa); SBS_DPP_STEP(c, 0x142, 0xa); SBS_DPP_STEP(d, 0x142, 0xa);
+  SBS_DPP_STEP(a, 0x143, 0xc); SBS_DPP_STEP(b, 0x143, 0xc); SBS_DPP_STEP(c, 0x143, 0xc); SBS_DPP_STEP(d, 0x143, 0xc);
+}
+
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
   v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, false);  // row_shr:1
   v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, false);  // row_shr:2
@@ -357,15 +371,24 @@ __device__ __forceinline__ void tile_item(const FrameDev& f, int tile, int chunk
       if (later) load_map(y + 1 + __builtin_ctzll(later));
     }
 #pragma unroll
-    for (int k = 0; k < DC; ++k) {
-      const uint32_t q0 = cad[0][k];
-      const uint32_t q1 = q0 + cad[1][k];
-      const uint32_t q2 = q1 + cad[2][k];
-      const uint32_t q3 = q2 + cad[3][k];
-      const uint32_t excl = wave_incl_scan(q3) - q3;
-      u32x4 o;
-      o.x = excl + q0; o.y = excl + q1; o.z = excl + q2; o.w = excl + q3;
-      *(lds_u32x4*)&sm.pre[k][4 + kColsPerLane * lane] = o;
+    for (int k0 = 0; k0 < DC; k0 += 4) {
+      uint32_t q[4][4], t[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        q[i][0] = cad[0][k0 + i];
+        q[i][1] = q[i][0] + cad[1][k0 + i];
+        q[i][2] = q[i][1] + cad[2][k0 + i];
+        q[i][3] = q[i][2] + cad[3][k0 + i];
+        t[i] = q[i][3];
+      }
+      wave_incl_scan4(t[0], t[1], t[2], t[3]);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const uint32_t excl = t[i] - q[i][3];
+        u32x4 o;
+        o.x = excl + q[i][0]; o.y = excl + q[i][1]; o.z = excl + q[i][2]; o.w = excl + q[i][3];
+        *(lds_u32x4*)&sm.pre[k0 + i][4 + kColsPerLane * lane] = o;
+      }
     }
     __syncthreads();
     // Output offset o (0 <= o < txo): window columns o + lpad - r .. o + lpad + r.
