@@ -89,6 +89,9 @@ def main():
     ap.add_argument("--no-compare", action="store_true", help="skip the per-frame / graph comparisons")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target oracle time for the CPU sample")
     ap.add_argument("--tuning", default=os.path.join(ROOT, "paper_2001_07809_amd", "tuning.json"))
+    ap.add_argument("--serve", action="store_true",
+                    help="serving mode: 2000 mixed-resolution requests, continuous batching, p50/p99 latency")
+    ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run one plain device copy of MIB mebibytes (HBM counter calibration)")
     args = ap.parse_args()
@@ -120,6 +123,9 @@ def main():
     sbs.lib()
     if args.tuning and os.path.exists(args.tuning):
         sbs.load_tuning(args.tuning)
+    if args.serve:
+        serve_main(args)
+        return
 
     spec = scenes.PRESETS[args.workload]
     F = args.frames
@@ -291,6 +297,93 @@ def main():
         "batching": compare,
         "h2d": {"bytes": h2d_bytes, "seconds": round(h2d_s, 3), "note": "excluded from value"},
         "cpu_baseline": cpu,
+    }
+    print(json.dumps(rec), flush=True)
+
+
+SERVE_CLASSES = [("serve_vga", 1000), ("serve_fhd", 600), ("serve_uhd", 400)]
+SERVE_FRACS = (0.12, 0.16, 0.20, 0.24)
+
+
+def serve_main(args):
+    """Serving: Poisson arrivals of mixed-resolution requests, continuous batching."""
+    import numpy as np
+    import torch
+
+    import scenes
+    from paper_2001_07809_amd.serve import Request, Server
+
+    dev = torch.device("cuda:0")
+    scale = args.serve_requests / 2000.0
+    counts = [(name, max(1, int(round(c * scale)))) for name, c in SERVE_CLASSES]
+    # Pools: 8 scenes per class, each with lists at 4 fractions, resident on the GPU.
+    t0 = time.time()
+    pools = {}
+    for ci, (name, _) in enumerate(counts):
+        spec = scenes.PRESETS[name]
+        entries = []
+        for s_i in range(8):
+            sp = scenes.scaled(spec, seed=spec.seed + 1000 * ci + s_i)
+            f = scenes.make_frame(sp)
+            Ld, Rd = torch.from_numpy(f.left).to(dev), torch.from_numpy(f.right).to(dev)
+            lists = [torch.from_numpy(scenes.contour_list(f.rid, fr, sp.seed).view(np.int32)).to(dev)
+                     for fr in SERVE_FRACS]
+            entries.append((Ld, Rd, lists))
+        pools[name] = (spec, entries)
+    torch.cuda.synchronize()
+    log(f"serving pools ready in {time.time() - t0:.1f}s")
+
+    rng = np.random.default_rng(105)
+    kinds = np.concatenate([np.full(c, i) for i, (_, c) in enumerate(counts)])
+    rng.shuffle(kinds)
+    picks = rng.integers(0, len(SERVE_FRACS), kinds.size)
+
+    def make_requests(arrivals):
+        reqs, used = [], [0, 0, 0]
+        for i, (k, fpick) in enumerate(zip(kinds[:len(arrivals)], picks[:len(arrivals)])):
+            name = counts[k][0]
+            spec, entries = pools[name]
+            Ld, Rd, lists = entries[used[k] % 8]
+            used[k] += 1
+            reqs.append(Request(i, Ld, Rd, lists[fpick], spec.block, spec.dmax, float(arrivals[i]), name))
+        return reqs
+
+    free, total = torch.cuda.mem_get_info()
+    budget = int(0.25 * free)
+    # Warm-up, then saturation: all requests at t = 0 (closed loop).
+    Server(budget).run_trace(make_requests(np.zeros(min(64, kinds.size))))
+    sat = Server(budget).run_trace(make_requests(np.zeros(kinds.size)))
+    lam_sat = sat["frames_per_s"]
+    log(f"saturation {lam_sat:.1f} frames/s, batches {sat['batches']}")
+    runs = []
+    for frac in (0.5, 0.7, 0.9):
+        lam = frac * lam_sat
+        arr = np.cumsum(rng.exponential(1.0 / lam, kinds.size))
+        st = Server(budget).run_trace(make_requests(arr))
+        st["rate_fraction_of_saturation"] = frac
+        st["offered_frames_per_s"] = lam
+        runs.append(st)
+        log(f"lambda {lam:.1f}/s: p50 {st['p50_ms']:.2f} ms p99 {st['p99_ms']:.2f} ms {st['frames_per_s']:.1f} frames/s")
+    evals = 0
+    for k, fpick in zip(kinds, picks):
+        spec, entries = pools[counts[k][0]]
+        evals += entries[0][2][fpick].numel() * (spec.dmax + 1)
+    rec = {
+        "metric": "serving: frames/s and p50/p99 latency (continuous batching)",
+        "value": lam_sat,
+        "unit": "frames/s",
+        "n_gpus": 1,
+        "higher_is_better": True,
+        "data": "synthetic",
+        "dtype": "u8",
+        "config": {"workload": f"{kinds.size} requests, mix " + "/".join(f"{c} {n}" for n, c in counts)
+                   + "; pools of 8 resident scenes x 4 list fractions per class",
+                   "classes": {n: {"W": pools[n][0].W, "H": pools[n][0].H, "block": pools[n][0].block,
+                                   "dmax": pools[n][0].dmax} for n, _ in counts},
+                   "budget_bytes": budget, "max_inflight_batches": 2, "max_batch": 64},
+        "saturation": sat,
+        "saturation_evals_per_s": evals / (kinds.size / lam_sat),
+        "poisson": runs,
     }
     print(json.dumps(rec), flush=True)
 

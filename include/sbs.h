@@ -186,6 +186,43 @@ int sbs_get_plan(const sbs_frame* frame, sbs_plan* plan);
 int sbs_kernel_timing(int32_t enable);
 int32_t sbs_kernel_times(float* ms, int32_t cap);
 
+/*
+ * Disparity map reconstruction (Sec. III "Disparity Map Reconstruction from
+ * Boundaries"): the listed pixels' disparities are spread to a dense u8 map.
+ * Stage 1 (Algorithm 1, fill along scan lines): in each row, every pixel
+ * strictly between two consecutive listed pixels with equal disparity takes
+ * that disparity. Stage 2 (Algorithm 2, peek): every pixel still undetermined
+ * looks at the nearest determined pixel above and below in its column (in
+ * stage 1's output); if their difference exceeds `threshold` it takes the
+ * smaller, else their mean rounded half up; with only one of them it takes
+ * that one; with none, 0. A repeated index keeps the disparity of its last
+ * list entry; indices >= W*H are ignored.
+ *   idx, disp   device, n entries (e.g. a list and the out_disp it produced)
+ *   out_map     device, W*H bytes, row-major
+ *   workspace   device, >= sbs_reconstruct_workspace_bytes(W, H)
+ */
+size_t sbs_reconstruct_workspace_bytes(int32_t W, int32_t H);
+int sbs_reconstruct(const uint32_t* idx, const uint8_t* disp, int64_t n, int32_t W, int32_t H, int32_t threshold,
+                    uint8_t* out_map, void* workspace, size_t workspace_bytes, void* stream);
+
+/*
+ * Depth-based selective blurring (Sec. III, Eq. 1-2): a pixel whose depth
+ * (disparity) lies outside every range of interest [lo_i, hi_i] is replaced,
+ * per channel, by the convolution of the image with h = h_g / sum(h_g),
+ * h_g(n1, n2) = exp(-(n1^2 + n2^2) / (2 sigma^2)), on a square support of side
+ * 2 ceil(3 sigma) + 1 with replicate borders; other pixels keep their value.
+ *   img         device, HWC u8, rows `pitch` bytes apart
+ *   depth       device, W*H u8
+ *   ranges      HOST array of nranges (lo, hi) pairs, nranges <= 16
+ *   out         device, W*H*C float32, HWC, not rounded
+ *   workspace   device, >= sbs_selective_blur_workspace_bytes(W, H, C)
+ * Computed in fp32 (separable passes); SBS_ERR_UNSUPPORTED if ceil(3 sigma) > 64.
+ */
+size_t sbs_selective_blur_workspace_bytes(int32_t W, int32_t H, int32_t C);
+int sbs_selective_blur(const uint8_t* img, int32_t W, int32_t H, int32_t C, int64_t pitch, const uint8_t* depth,
+                       const int32_t* ranges, int32_t nranges, float sigma, float* out, void* workspace,
+                       size_t workspace_bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

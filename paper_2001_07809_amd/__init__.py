@@ -44,7 +44,8 @@ class SbsError(RuntimeError):
 
 def build() -> str:
     """Compile libsbs.so for gfx950 (always recompiles)."""
-    srcs = [os.path.join(_CSRC, "sbs_kernels.hip"), os.path.join(_CSRC, "sbs_api.hip")]
+    srcs = [os.path.join(_CSRC, "sbs_kernels.hip"), os.path.join(_CSRC, "sbs_api.hip"),
+            os.path.join(_CSRC, "sbs_post.hip")]
     cmd = [HIPCC, *HIP_FLAGS, *srcs, "-o", _SO + ".tmp"]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
@@ -94,6 +95,10 @@ def lib():
         "sbs_set_plan": ([ctypes.POINTER(Plan)], ctypes.c_int),
         "sbs_get_plan": ([FP, ctypes.POINTER(Plan)], ctypes.c_int),
         "sbs_kernel_timing": ([I32], ctypes.c_int),
+        "sbs_reconstruct_workspace_bytes": ([I32, I32], SZ),
+        "sbs_reconstruct": ([V, V, I64, I32, I32, I32, V, V, SZ, V], ctypes.c_int),
+        "sbs_selective_blur_workspace_bytes": ([I32, I32, I32], SZ),
+        "sbs_selective_blur": ([V, I32, I32, I32, I64, V, V, I32, ctypes.c_float, V, V, SZ, V], ctypes.c_int),
         "sbs_kernel_times": ([ctypes.POINTER(ctypes.c_float), I32], I32),
     }
     for name, (args, res) in sig.items():
@@ -237,6 +242,32 @@ def tune(frames, cache_path: str | None = None):
 
 def load_tuning(cache_path: str):
     _check(lib().sbs_load_tuning(cache_path.encode()))
+
+
+def reconstruct(idx, disp, W: int, H: int, threshold: int, stream=None):
+    """Dense u8 disparity map [H, W] from listed pixels (Algorithms 1 and 2)."""
+    torch = _torch()
+    dev = idx.device
+    out = torch.empty((H, W), dtype=torch.uint8, device=dev)
+    nb = int(lib().sbs_reconstruct_workspace_bytes(W, H))
+    ws = torch.empty(max(nb, 256), dtype=torch.uint8, device=dev)
+    _check(lib().sbs_reconstruct(idx.data_ptr(), disp.data_ptr(), idx.numel(), W, H, threshold, out.data_ptr(),
+                                 ws.data_ptr(), ws.numel(), _stream_handle(stream)))
+    return out
+
+
+def selective_blur(img, depth, ranges, sigma: float, stream=None):
+    """Float32 HWC image with pixels outside the depth ranges blurred (Eq. 1-2)."""
+    torch = _torch()
+    W, H, C, pitch = _image_args(img)
+    rg = (ctypes.c_int32 * max(2 * len(ranges), 2))(*[int(v) for pr in ranges for v in pr])
+    out = torch.empty(img.shape, dtype=torch.float32, device=img.device)
+    nb = int(lib().sbs_selective_blur_workspace_bytes(W, H, C))
+    ws = torch.empty(max(nb, 256), dtype=torch.uint8, device=img.device)
+    _check(lib().sbs_selective_blur(img.data_ptr(), W, H, C, pitch, depth.data_ptr(), rg, len(ranges),
+                                    float(sigma), out.data_ptr(), ws.data_ptr(), ws.numel(),
+                                    _stream_handle(stream)))
+    return out
 
 
 class BatchRunner:

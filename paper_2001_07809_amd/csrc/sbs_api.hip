@@ -29,11 +29,20 @@ hipError_t launch_ref(const uint8_t* L, const uint8_t* R, int W, int H, int C, i
                       int64_t n, int r, int dmax, uint8_t* od, uint32_t* oc, uint32_t* err, hipStream_t s);
 }  // namespace sbs
 
+namespace {
+thread_local std::string g_err;
+}  // namespace
+
+namespace sbs {
+int report_error(int status, const char* msg) {
+  g_err = msg;
+  return status;
+}
+}  // namespace sbs
+
 using namespace sbs;
 
 namespace {
-
-thread_local std::string g_err;
 
 int fail(int status, const char* fmt, ...) {
   char buf[512];

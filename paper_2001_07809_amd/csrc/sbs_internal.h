@@ -66,4 +66,7 @@ struct WsHeader {
 constexpr size_t kHeaderBytes = 1024;
 static_assert(sizeof(WsHeader) <= kHeaderBytes, "header");
 
+// Records `msg` as the calling thread's last error (sbs_last_error) and returns status.
+int report_error(int status, const char* msg);
+
 }  // namespace sbs

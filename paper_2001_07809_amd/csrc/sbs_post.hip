@@ -1,0 +1,254 @@
+// Steps after the disparity search (arXiv 2001.07809, Sec. III):
+//   * disparity map reconstruction from the listed pixels' disparities:
+//     Algorithm 1 (fill along scan lines), then Algorithm 2 (peek along
+//     columns at the nearest determined pixels above and below);
+//   * depth-based selective blurring with the normalised Gaussian of Eq. 1-2.
+// Declared in include/sbs.h.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <string>
+
+#include "../../include/sbs.h"
+#include "sbs_internal.h"
+
+namespace sbs_post {
+
+constexpr int kRowThreads = 256;
+
+// slot[p] = largest list position k with idx[k] == p (so a repeated index keeps its last value).
+__global__ __launch_bounds__(256) void k_rc_clear(int32_t* slot, int64_t N) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x)
+    slot[i] = -1;
+}
+
+__global__ __launch_bounds__(256) void k_rc_scatter(const uint32_t* idx, int64_t n, int64_t N, int32_t* slot) {
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t p = idx[k];
+    if ((int64_t)p < N) atomicMax(&slot[p], (int32_t)k);
+  }
+}
+
+// Algorithm 1 on one row per block: a pixel strictly between two consecutive
+// listed pixels of the row that carry the same disparity takes it. Each
+// thread owns a contiguous segment; the nearest listed pixel to the left and
+// to the right of every pixel come from block-wide max/min scans over the
+// segments. Output: f[p] = disparity or -1 (undetermined).
+__global__ __launch_bounds__(kRowThreads) void k_rc_fill(const int32_t* slot, const uint8_t* disp, int32_t W,
+                                                           int32_t H, int16_t* f) {
+  __shared__ int32_t lastpos[kRowThreads];
+  __shared__ int32_t firstpos[kRowThreads];
+  const int t = threadIdx.x;
+  const int seg = (W + kRowThreads - 1) / kRowThreads;
+  for (int y = blockIdx.x; y < H; y += gridDim.x) {
+    const int32_t* srow = slot + (int64_t)y * W;
+    int16_t* frow = f + (int64_t)y * W;
+    const int xa = min(t * seg, W), xb = min(xa + seg, W);
+    int last = -1, first = W;
+    for (int x = xa; x < xb; ++x)
+      if (srow[x] >= 0) { last = x; if (first == W) first = x; }
+    lastpos[t] = last;
+    firstpos[t] = first;
+    __syncthreads();
+    // inclusive max-scan of lastpos (left to right), inclusive min-scan of firstpos (right to left)
+    for (int off = 1; off < kRowThreads; off <<= 1) {
+      const int a = t >= off ? lastpos[t - off] : -1;
+      const int b = t + off < kRowThreads ? firstpos[t + off] : W;
+      __syncthreads();
+      lastpos[t] = max(lastpos[t], a);
+      firstpos[t] = min(firstpos[t], b);
+      __syncthreads();
+    }
+    int prev = t > 0 ? lastpos[t - 1] : -1;          // nearest listed pixel left of this segment
+    int next = t + 1 < kRowThreads ? firstpos[t + 1] : W;  // nearest right of this segment
+    // Left to right through the segment carrying the nearest listed pixel on
+    // the left; the nearest on the right is found by a short forward search
+    // inside the segment (segments are W / 256 pixels), else it is `next`.
+    for (int x = xa; x < xb; ++x) {
+      const int32_t k = srow[x];
+      if (k >= 0) {
+        frow[x] = disp[k];
+        prev = x;
+        continue;
+      }
+      int nx = next;
+      for (int u = x + 1; u < xb; ++u)
+        if (srow[u] >= 0) { nx = u; break; }
+      int16_t v = -1;
+      if (prev >= 0 && nx < W) {
+        const uint8_t dl = disp[srow[prev]], dr = disp[srow[nx]];
+        if (dl == dr) v = dl;
+      }
+      frow[x] = v;
+    }
+    __syncthreads();
+  }
+}
+
+// Algorithm 2 on one column per thread: an undetermined pixel takes the
+// smaller of its nearest determined pixels above and below when their range
+// exceeds the threshold, else their mean rounded half up; one-sided when only
+// one exists; 0 when the column has none. Reads only Algorithm 1's output.
+__global__ __launch_bounds__(256) void k_rc_peek(const int16_t* f, int32_t W, int32_t H, int32_t threshold,
+                                                 int16_t* up, uint8_t* out) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= W) return;
+  int16_t last = -1;
+  for (int y = 0; y < H; ++y) {
+    const int16_t v = f[(int64_t)y * W + x];
+    up[(int64_t)y * W + x] = last;
+    if (v >= 0) last = v;
+  }
+  int16_t below = -1;
+  for (int y = H - 1; y >= 0; --y) {
+    const int64_t q = (int64_t)y * W + x;
+    const int16_t v = f[q];
+    if (v >= 0) {
+      out[q] = (uint8_t)v;
+      below = v;
+      continue;
+    }
+    const int a = up[q], b = below;
+    int r;
+    if (a < 0 && b < 0) r = 0;
+    else if (a < 0) r = b;
+    else if (b < 0) r = a;
+    else if (abs(a - b) > threshold) r = min(a, b);
+    else r = (a + b + 1) / 2;
+    out[q] = (uint8_t)r;
+  }
+}
+
+// Selective blur: separable Gaussian (normalised per axis, so the product is
+// Eq. 2's normalised 2-D kernel), replicate border, fp32 accumulation.
+constexpr int kMaxRadius = 64;
+constexpr int kMaxRanges = 16;
+
+struct BlurArgs {
+  float g[2 * kMaxRadius + 1];
+  int32_t lo[kMaxRanges], hi[kMaxRanges];
+  int32_t rad, nranges;
+};
+
+__global__ __launch_bounds__(256) void k_blur_h(const uint8_t* img, int32_t W, int32_t H, int32_t C, int64_t pitch,
+                                                BlurArgs a, float* tmp) {
+  const int64_t total = (int64_t)W * H * C;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int c = (int)(i % C);
+    const int64_t px = i / C;
+    const int x = (int)(px % W), y = (int)(px / W);
+    const uint8_t* row = img + (int64_t)y * pitch;
+    float s = 0.f;
+    for (int k = -a.rad; k <= a.rad; ++k) {
+      const int xx = min(max(x + k, 0), W - 1);
+      s += a.g[k + a.rad] * (float)row[(int64_t)xx * C + c];
+    }
+    tmp[i] = s;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_blur_v(const uint8_t* img, const uint8_t* depth, int32_t W, int32_t H,
+                                                int32_t C, int64_t pitch, BlurArgs a, const float* tmp, float* out) {
+  const int64_t total = (int64_t)W * H * C;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int c = (int)(i % C);
+    const int64_t px = i / C;
+    const int x = (int)(px % W), y = (int)(px / W);
+    const int dv = depth[px];
+    bool keep = false;
+    for (int t = 0; t < a.nranges; ++t) keep |= (dv >= a.lo[t] && dv <= a.hi[t]);
+    if (keep) {
+      out[i] = (float)img[(int64_t)y * pitch + (int64_t)x * C + c];
+      continue;
+    }
+    float s = 0.f;
+    for (int k = -a.rad; k <= a.rad; ++k) {
+      const int yy = min(max(y + k, 0), H - 1);
+      s += a.g[k + a.rad] * tmp[((int64_t)yy * W + x) * C + c];
+    }
+    out[i] = s;
+  }
+}
+
+int fail(int st, const char* fmt, ...) {
+  char buf[256];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  return sbs::report_error(st, buf);
+}
+
+size_t align256(size_t v) { return (v + 255) / 256 * 256; }
+
+}  // namespace sbs_post
+
+using namespace sbs_post;
+
+extern "C" {
+
+size_t sbs_reconstruct_workspace_bytes(int32_t W, int32_t H) {
+  if (W < 1 || H < 1) return 0;
+  const size_t N = (size_t)W * H;
+  return align256(N * 4) + align256(N * 2) + align256(N * 2);
+}
+
+int sbs_reconstruct(const uint32_t* idx, const uint8_t* disp, int64_t n, int32_t W, int32_t H, int32_t threshold,
+                    uint8_t* out_map, void* workspace, size_t workspace_bytes, void* stream) {
+  if (W < 1 || H < 1 || (int64_t)W * H > INT32_MAX) return fail(SBS_ERR_INVALID_ARG, "bad W/H");
+  if (n < 0 || n > INT32_MAX) return fail(SBS_ERR_INVALID_ARG, "bad n");
+  if (!out_map || !workspace || (n > 0 && (!idx || !disp))) return fail(SBS_ERR_INVALID_ARG, "NULL pointer");
+  if (threshold < 0) return fail(SBS_ERR_INVALID_ARG, "threshold < 0");
+  if (workspace_bytes < sbs_reconstruct_workspace_bytes(W, H)) return fail(SBS_ERR_INVALID_ARG, "workspace too small");
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t N = (int64_t)W * H;
+  char* base = (char*)workspace;
+  int32_t* slot = (int32_t*)base;
+  int16_t* f = (int16_t*)(base + align256(N * 4));
+  int16_t* up = (int16_t*)(base + align256(N * 4) + align256(N * 2));
+  hipLaunchKernelGGL(k_rc_clear, dim3(1024), dim3(256), 0, s, slot, N);
+  if (n > 0) hipLaunchKernelGGL(k_rc_scatter, dim3(256), dim3(256), 0, s, idx, n, N, slot);
+  hipLaunchKernelGGL(k_rc_fill, dim3(H < 4096 ? H : 4096), dim3(kRowThreads), 0, s, slot, disp, W, H, f);
+  hipLaunchKernelGGL(k_rc_peek, dim3((W + 255) / 256), dim3(256), 0, s, f, W, H, threshold, up, out_map);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(SBS_ERR_HIP, "reconstruct: %s", hipGetErrorString(e));
+  return SBS_OK;
+}
+
+size_t sbs_selective_blur_workspace_bytes(int32_t W, int32_t H, int32_t C) {
+  if (W < 1 || H < 1 || (C != 1 && C != 3)) return 0;
+  return align256((size_t)W * H * C * 4);
+}
+
+int sbs_selective_blur(const uint8_t* img, int32_t W, int32_t H, int32_t C, int64_t pitch, const uint8_t* depth,
+                       const int32_t* ranges, int32_t nranges, float sigma, float* out, void* workspace,
+                       size_t workspace_bytes, void* stream) {
+  if (W < 1 || H < 1 || (C != 1 && C != 3) || pitch < (int64_t)W * C) return fail(SBS_ERR_INVALID_ARG, "bad image");
+  if (!img || !depth || !out || !workspace) return fail(SBS_ERR_INVALID_ARG, "NULL pointer");
+  if (nranges < 0 || nranges > kMaxRanges || (nranges > 0 && !ranges))
+    return fail(SBS_ERR_INVALID_ARG, "nranges must be in [0, %d]", kMaxRanges);
+  if (!(sigma > 0.f)) return fail(SBS_ERR_INVALID_ARG, "sigma must be > 0");
+  const int rad = (int)std::ceil(3.0 * (double)sigma);
+  if (rad > kMaxRadius) return fail(SBS_ERR_UNSUPPORTED, "sigma too large (radius %d > %d)", rad, kMaxRadius);
+  if (workspace_bytes < sbs_selective_blur_workspace_bytes(W, H, C)) return fail(SBS_ERR_INVALID_ARG, "workspace too small");
+  BlurArgs a{};
+  double gs = 0.0;
+  double g[2 * kMaxRadius + 1];
+  for (int k = -rad; k <= rad; ++k) { g[k + rad] = std::exp(-(double)(k * k) / (2.0 * (double)sigma * sigma)); gs += g[k + rad]; }
+  for (int k = 0; k <= 2 * rad; ++k) a.g[k] = (float)(g[k] / gs);
+  a.rad = rad;
+  a.nranges = nranges;
+  for (int t = 0; t < nranges; ++t) { a.lo[t] = ranges[2 * t]; a.hi[t] = ranges[2 * t + 1]; }
+  hipStream_t s = (hipStream_t)stream;
+  float* tmp = (float*)workspace;
+  hipLaunchKernelGGL(k_blur_h, dim3(2048), dim3(256), 0, s, img, W, H, C, pitch, a, tmp);
+  hipLaunchKernelGGL(k_blur_v, dim3(2048), dim3(256), 0, s, img, depth, W, H, C, pitch, a, tmp, out);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(SBS_ERR_HIP, "blur: %s", hipGetErrorString(e));
+  return SBS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,201 @@
+"""Serving loop with continuous batching for boundary-pixel SAD disparity.
+
+Requests are frames with their boundary lists (device tensors; a request's
+inputs stay resident in HBM from arrival to completion). The server:
+
+* admits waiting requests in arrival order while the HBM footprint of the
+  work in flight stays within a byte budget and a batch slot is free. The
+  footprint of a request is its workspace share plus its outputs;
+* launches each admitted group as ONE persistent batched call
+  (``sbs_sad_disparity_batched``). Up to ``max_inflight`` batches run at once
+  on separate HIP streams, so requests that arrive while others are on the GPU
+  are admitted as soon as a slot and memory free up, and their work overlaps
+  on the device;
+* completes a request when its batch's HIP event has fired, and records its
+  latency (completion minus arrival).
+
+Each request's result depends only on its own frame: it is the same alone and
+in any mix (the GPU tests check this bit for bit).
+"""
+from __future__ import annotations
+
+import ctypes
+import time
+from dataclasses import dataclass, field
+
+import paper_2001_07809_amd as sbs
+
+
+@dataclass
+class Request:
+    rid: int
+    left: object            # torch.uint8 [H, W] or [H, W, 3] on the GPU
+    right: object
+    idx: object             # torch.int32 [n] on the GPU
+    block: int
+    dmax: int
+    arrival: float = 0.0    # seconds on the server clock
+    klass: str = ""
+    disp: object = None
+    cost: object = None
+    t_admit: float = -1.0
+    t_done: float = -1.0
+    footprint: int = 0
+
+
+@dataclass
+class _Batch:
+    reqs: list
+    workspace: object
+    desc: object
+    event: object
+    stream: object
+    nbytes: int
+
+
+class BudgetError(RuntimeError):
+    pass
+
+
+class Server:
+    def __init__(self, budget_bytes: int, max_inflight: int = 2, max_batch: int = 64, device=None,
+                 with_cost: bool = True):
+        import torch
+        self.torch = torch
+        self.device = device or torch.device("cuda")
+        self.budget = int(budget_bytes)
+        self.max_inflight = max_inflight
+        self.max_batch = max_batch
+        self.with_cost = with_cost
+        self.streams = [torch.cuda.Stream(device=self.device) for _ in range(max_inflight)]
+        self._next_stream = 0
+        self.waiting: list[Request] = []
+        self.inflight: list[_Batch] = []
+        self.done: list[Request] = []
+        self.in_use = 0
+        self.peak_in_use = 0
+        self.batches = 0
+        self.t0 = time.perf_counter()
+
+    def now(self) -> float:
+        return time.perf_counter() - self.t0
+
+    # -- footprint ---------------------------------------------------------
+    def _frame(self, r: Request, disp, cost):
+        return sbs.make_frame(r.left, r.right, r.idx, r.block, r.dmax, disp, cost)
+
+    def footprint(self, r: Request) -> int:
+        n = r.idx.numel()
+        f = sbs.Frame(r.left.data_ptr(), r.right.data_ptr(), *sbs._image_args(r.left)[:3],
+                      sbs._image_args(r.left)[3], r.idx.data_ptr(), n, r.block, r.dmax, 1, None)
+        ws = sbs.workspace_bytes([f])
+        if ws == 0:
+            raise ValueError(f"request {r.rid}: invalid frame")
+        return ws + n * (5 if self.with_cost else 1) + 4096
+
+    def submit(self, r: Request):
+        r.footprint = self.footprint(r)
+        if r.footprint > self.budget:
+            raise BudgetError(f"request {r.rid} needs {r.footprint} bytes, budget is {self.budget}")
+        self.waiting.append(r)
+
+    # -- engine ------------------------------------------------------------
+    def poll(self):
+        still = []
+        for b in self.inflight:
+            if b.event.query():
+                t = self.now()
+                for r in b.reqs:
+                    r.t_done = t
+                    self.done.append(r)
+                self.in_use -= b.nbytes
+            else:
+                still.append(b)
+        self.inflight = still
+
+    def launch(self) -> bool:
+        """Admit what fits and launch one batch. Returns True if a batch was launched."""
+        torch = self.torch
+        if not self.waiting or len(self.inflight) >= self.max_inflight:
+            return False
+        free = self.budget - self.in_use
+        take, total = [], 0
+        for r in self.waiting:
+            if len(take) >= self.max_batch or total + r.footprint > free:
+                break
+            take.append(r)
+            total += r.footprint
+        if not take:
+            return False
+        self.waiting = self.waiting[len(take):]
+        t = self.now()
+        frames = []
+        for r in take:
+            n = r.idx.numel()
+            r.disp = torch.empty(n, dtype=torch.uint8, device=self.device)
+            r.cost = torch.empty(n, dtype=torch.int32, device=self.device) if self.with_cost else None
+            r.t_admit = t
+            frames.append(self._frame(r, r.disp, r.cost))
+        desc = (sbs.Frame * len(frames))(*frames)
+        nbytes = int(sbs.lib().sbs_workspace_bytes(desc, len(frames)))
+        stream = self.streams[self._next_stream]
+        self._next_stream = (self._next_stream + 1) % len(self.streams)
+        stream.wait_stream(torch.cuda.current_stream())   # inputs and outputs were made on the caller's stream
+        with torch.cuda.stream(stream):
+            ws = torch.empty(max(nbytes, 1024), dtype=torch.uint8, device=self.device)
+            ws[:1024].zero_()
+            sbs._check(sbs.lib().sbs_sad_disparity_batched(desc, len(frames), ctypes.c_void_p(ws.data_ptr()),
+                                                           ws.numel(), ctypes.c_void_p(stream.cuda_stream)))
+            ev = torch.cuda.Event()
+            ev.record(stream)
+        self.in_use += total
+        self.peak_in_use = max(self.peak_in_use, self.in_use)
+        self.inflight.append(_Batch(take, ws, desc, ev, stream, total))
+        self.batches += 1
+        return True
+
+    def drain(self):
+        while self.waiting or self.inflight:
+            self.poll()
+            self.launch()
+
+    def run_trace(self, requests: list[Request]) -> dict:
+        """Replays requests at their arrival times (seconds after start) and returns latency stats."""
+        pending = sorted(requests, key=lambda r: r.arrival)
+        self.t0 = time.perf_counter()
+        i = 0
+        while i < len(pending) or self.waiting or self.inflight:
+            t = self.now()
+            while i < len(pending) and pending[i].arrival <= t:
+                self.submit(pending[i])
+                i += 1
+            self.poll()
+            launched = self.launch()
+            if not launched and i < len(pending) and not self.inflight and not self.waiting:
+                # idle until the next arrival
+                dt = pending[i].arrival - self.now()
+                if dt > 0:
+                    time.sleep(min(dt, 0.0005))
+        return self.stats(requests)
+
+    def stats(self, requests: list[Request]) -> dict:
+        import numpy as np
+        lat = np.array([r.t_done - r.arrival for r in requests])
+        span = max(r.t_done for r in requests) - min(r.arrival for r in requests)
+        out = {
+            "requests": len(requests),
+            "p50_ms": float(np.percentile(lat, 50) * 1e3),
+            "p99_ms": float(np.percentile(lat, 99) * 1e3),
+            "mean_ms": float(lat.mean() * 1e3),
+            "frames_per_s": len(requests) / span if span > 0 else float("inf"),
+            "batches": self.batches,
+            "peak_bytes_in_flight": self.peak_in_use,
+            "budget_bytes": self.budget,
+        }
+        by = {}
+        for k in sorted({r.klass for r in requests}):
+            lk = np.array([r.t_done - r.arrival for r in requests if r.klass == k])
+            by[k] = {"n": int(lk.size), "p50_ms": float(np.percentile(lk, 50) * 1e3),
+                     "p99_ms": float(np.percentile(lk, 99) * 1e3)}
+        out["by_class"] = by
+        return out

@@ -1,0 +1,80 @@
+"""Serving loop: each request's result is identical alone and in the mix
+(tolerance 0), admission respects the HBM budget, oversized requests are
+refused, and the results match the oracle."""
+import numpy as np
+import pytest
+
+import oracle
+import scenes
+
+pytestmark = pytest.mark.gpu
+
+CLASSES = [
+    scenes.SceneSpec(200, 150, 3, 5, 15, mean_shift=1, seed=7, block=11, dmax=15),
+    scenes.SceneSpec(320, 240, 3, 8, 31, mean_shift=1, seed=8, block=15, dmax=31),
+    scenes.SceneSpec(480, 272, 3, 10, 47, mean_shift=1, seed=9, block=21, dmax=47),
+]
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    import paper_2001_07809_amd as sbs
+    from paper_2001_07809_amd.serve import BudgetError, Request, Server
+    pool = []
+    for ci, spec in enumerate(CLASSES):
+        for s_i in range(2):
+            sp = scenes.scaled(spec, seed=spec.seed * 10 + s_i)
+            f = scenes.make_frame(sp)
+            idx = scenes.contour_list(f.rid, 0.12 + 0.05 * s_i + 0.02 * ci, sp.seed)
+            pool.append((sp, f, idx))
+    return torch, sbs, Request, Server, BudgetError, pool
+
+
+def _requests(env, n, arrivals):
+    torch, sbs, Request, Server, BudgetError, pool = env
+    reqs = []
+    for i in range(n):
+        sp, f, idx = pool[(i * 5) % len(pool)]
+        reqs.append(Request(i, torch.from_numpy(f.left).cuda(), torch.from_numpy(f.right).cuda(),
+                            torch.from_numpy(idx.view(np.int32)).cuda(), sp.block, sp.dmax, float(arrivals[i]),
+                            f"{sp.W}x{sp.H}"))
+    return reqs
+
+
+def test_each_result_same_alone_and_in_the_mix(env):
+    torch, sbs, Request, Server, BudgetError, pool = env
+    reqs = _requests(env, 24, np.zeros(24))
+    srv = Server(budget_bytes=64 << 20, max_inflight=2, max_batch=5)
+    st = srv.run_trace(reqs)
+    assert st["batches"] >= 5 and srv.peak_in_use <= srv.budget
+    for r in reqs:
+        d1, c1 = sbs.sad_disparity(r.left, r.right, r.idx, r.block, r.dmax)
+        torch.cuda.synchronize()
+        assert torch.equal(r.disp, d1) and torch.equal(r.cost, c1), f"request {r.rid}"
+    # and against the oracle for one request of each class
+    seen = set()
+    for r in reqs:
+        if r.klass in seen:
+            continue
+        seen.add(r.klass)
+        d, c, _ = oracle.sad(r.left.cpu().numpy(), r.right.cpu().numpy(), r.idx.cpu().numpy().view(np.uint32),
+                             r.block, r.dmax)
+        np.testing.assert_array_equal(r.disp.cpu().numpy(), d)
+        np.testing.assert_array_equal(r.cost.cpu().numpy().view(np.uint32), c)
+
+
+def test_poisson_trace_and_budget(env):
+    torch, sbs, Request, Server, BudgetError, pool = env
+    rng = np.random.default_rng(3)
+    arr = np.cumsum(rng.exponential(0.002, 30))
+    reqs = _requests(env, 30, arr)
+    budget = 6 << 20
+    srv = Server(budget_bytes=budget, max_inflight=2, max_batch=64)
+    st = srv.run_trace(reqs)
+    assert st["requests"] == 30 and st["p99_ms"] >= st["p50_ms"] > 0
+    assert srv.peak_in_use <= budget
+    assert all(r.t_done >= r.t_admit >= r.arrival for r in reqs)
+    tiny = Server(budget_bytes=1 << 16)
+    with pytest.raises(BudgetError):
+        tiny.submit(_requests(env, 1, [0.0])[0])

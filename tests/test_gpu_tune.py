@@ -1,0 +1,38 @@
+"""Autotuner: sbs_tune picks a plan, writes it to a JSON cache, the cache
+loads back, later calls use it, and results do not depend on the plan."""
+import json
+
+import numpy as np
+import pytest
+
+import scenes
+
+pytestmark = pytest.mark.gpu
+
+
+def test_tune_cache_roundtrip(tmp_path):
+    import torch
+    import paper_2001_07809_amd as sbs
+    spec = scenes.scaled(scenes.PRESETS["uhd_video"], W=700, H=400, n_regions=10)
+    fr = scenes.video_fracs(spec, 0, 3)
+    left, right, lists = scenes.make_video(spec, 0, 3, fr)
+    frames = [(torch.from_numpy(left[t]).cuda(), torch.from_numpy(right[t]).cuda(),
+               torch.from_numpy(lists[t].view(np.int32)).cuda(), spec.block, spec.dmax) for t in range(3)]
+    runner = sbs.BatchRunner(frames)
+    runner.run()
+    torch.cuda.synchronize()
+    before = [d.clone() for d in runner.disp]
+    cache = tmp_path / "tuning.json"
+    sbs.tune(list(runner.desc), str(cache))
+    data = json.loads(cache.read_text())
+    assert len(data) == 1
+    (key, plan), = data.items()
+    assert key.startswith("gfx950/700x400x3/b31/d127/") and plan["chunk"] in (8, 16)
+    sbs.load_tuning(str(cache))
+    assert sbs.get_plan(runner.desc[0]) == plan
+    for d in runner.disp:
+        d.fill_(0)
+    runner.run()
+    torch.cuda.synchronize()
+    for a, b in zip(before, runner.disp):
+        assert torch.equal(a, b)
