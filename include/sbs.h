@@ -163,7 +163,7 @@ int sbs_sad_disparity_per_frame(const sbs_frame* frames, int32_t nframes, void* 
  * (cols_per_lane, chunk, tile_rows, waves_per_cu); 0 in a field means
  * "automatic". sbs_set_plan forces a plan for subsequent calls (all fields 0
  * restores automatic choice); sbs_get_plan reports the plan the library would
- * use for a frame. Valid cols_per_lane: 4; chunk: 8, 16; tile_rows: 8..64;
+ * use for a frame. Valid cols_per_lane: 4; chunk: 8, 16; tile_rows: 8..128;
  * waves_per_cu: 1..16.
  */
 typedef struct {

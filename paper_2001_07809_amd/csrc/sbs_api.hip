@@ -112,10 +112,9 @@ std::string plan_key(const sbs_frame& f) {
 }
 
 Plan default_plan(const sbs_frame& f) {
-  (void)f;
   Plan p;
   p.chunk = 8;
-  p.ty = 64;
+  p.ty = f.H >= 1024 ? 128 : 64;   // tall frames: spread each tile's window warm-up over more rows
   p.wpc = 16;
   return p;
 }
@@ -429,7 +428,7 @@ int save_cache(const char* path) {
 }
 
 bool plan_valid(const Plan& p) {
-  return p.cpl == 4 && (p.chunk == 8 || p.chunk == 16) && p.ty >= 8 && p.ty <= 64 && p.wpc >= 1 && p.wpc <= 16;
+  return p.cpl == 4 && (p.chunk == 8 || p.chunk == 16) && p.ty >= 8 && p.ty <= 128 && p.wpc >= 1 && p.wpc <= 16;
 }
 
 }  // namespace
@@ -583,7 +582,7 @@ int sbs_tune(const sbs_frame* frames, int32_t nframes, const char* cache_path) {
   Plan best;
   float best_ms = 1e30f;
   const int chunks[] = {8, 16};
-  const int rows[] = {16, 32, 64};
+  const int rows[] = {32, 64, 128};
   const int wpcs[] = {4, 8, 16};
   for (int ch : chunks)
     for (int ty : rows)

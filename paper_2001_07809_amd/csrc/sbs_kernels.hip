@@ -224,7 +224,7 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
 template <int DC>
 struct TileLds {
   uint32_t pre[DC][kSpan + 4] __attribute__((aligned(16)));
-  int32_t eo[kSpan];           // unordered lists: listed pixels of the row (output column offset)
+  int16_t eo[kSpan];           // unordered lists: listed pixels of the row (output column offset)
   int32_t es[kSpan];           //                  and their representative slots
 };
 
@@ -273,33 +273,53 @@ __device__ __forceinline__ void tile_item(const FrameDev& f, int tile, int chunk
   const int lpad = f.lpad;
   const bool sorted = !(*(g_uint32*)f.state & kUnsorted);
 
-  // Rows of this tile holding a listed pixel in [x0, x1). For ordered lists
-  // lane l keeps the list range of row y0 + l in registers (tp0, tp1).
-  bool act = false;
-  int tp0 = 0, tp1 = 0;
-  {
-    const int y = y0 + lane;
-    if (lane < f.ty && y < y1) {
-      if (sorted) {
-        const g_int32* tp = (g_int32*)(f.tptr + (int64_t)y * f.tpw + tx);
-        tp0 = tp[0];
-        tp1 = tp[1];
-        act = tp1 > tp0;
-      } else {
-        const int g0 = x0 >> 6, g1 = (x1 - 1) >> 6;
-        for (int w = g0 >> 6; w <= (g1 >> 6); ++w) {
-          const uint64_t bits = *(g_uint64*)(f.rowbits + (int64_t)y * f.rbw + w);
-          const int lo = max(g0 - 64 * w, 0), hi = min(g1 - 64 * w, 63);
-          const uint64_t m = (hi == 63 ? ~0ull : ((1ull << (hi + 1)) - 1)) & ~((1ull << lo) - 1);
-          if (bits & m) act = true;
-        }
-      }
+  // Rows of this tile (up to 128, two 64-bit masks) holding a listed pixel
+  // in [x0, x1). For ordered lists lane l keeps the list ranges of rows
+  // y0 + l and y0 + 64 + l in registers.
+  int tpa0 = 0, tpa1 = 0, tpb0 = 0, tpb1 = 0;
+  auto row_active = [&](int y, int& t0, int& t1) -> bool {
+    if (y >= y1) return false;
+    if (sorted) {
+      const g_int32* tp = (g_int32*)(f.tptr + (int64_t)y * f.tpw + tx);
+      t0 = tp[0];
+      t1 = tp[1];
+      return t1 > t0;
     }
-  }
-  const uint64_t rows = __builtin_amdgcn_ballot_w64(act);
-  if (rows == 0) return;
-  const int ya = y0 + __builtin_ctzll(rows);
-  const int yb = y0 + 63 - __builtin_clzll(rows);
+    const int g0 = x0 >> 6, g1 = (x1 - 1) >> 6;
+    bool a = false;
+    for (int w = g0 >> 6; w <= (g1 >> 6); ++w) {
+      const uint64_t bits = *(g_uint64*)(f.rowbits + (int64_t)y * f.rbw + w);
+      const int lo = max(g0 - 64 * w, 0), hi = min(g1 - 64 * w, 63);
+      const uint64_t m = (hi == 63 ? ~0ull : ((1ull << (hi + 1)) - 1)) & ~((1ull << lo) - 1);
+      if (bits & m) a = true;
+    }
+    return a;
+  };
+  const bool acta = lane < f.ty && row_active(y0 + lane, tpa0, tpa1);
+  const bool actb = lane + 64 < f.ty && row_active(y0 + 64 + lane, tpb0, tpb1);
+  const uint64_t rows_a = __builtin_amdgcn_ballot_w64(acta);
+  const uint64_t rows_b = __builtin_amdgcn_ballot_w64(actb);
+  if ((rows_a | rows_b) == 0) return;
+  const int ya = y0 + (rows_a ? __builtin_ctzll(rows_a) : 64 + __builtin_ctzll(rows_b));
+  const int yb = y0 + (rows_b ? 127 - __builtin_clzll(rows_b) : 63 - __builtin_clzll(rows_a));
+  auto is_active = [&](int y) -> bool {
+    const int i = y - y0;
+    return i < 64 ? ((rows_a >> i) & 1ull) : ((rows_b >> (i - 64)) & 1ull);
+  };
+  // first active row after y, or -1
+  auto next_active = [&](int y) -> int {
+    const int i = y - y0 + 1;
+    if (i < 64) {
+      const uint64_t m = rows_a >> i;
+      if (m) return y + 1 + __builtin_ctzll(m);
+      return rows_b ? y0 + 64 + __builtin_ctzll(rows_b) : -1;
+    }
+    if (i < 128) {
+      const uint64_t m = rows_b >> (i - 64);
+      if (m) return y + 1 + __builtin_ctzll(m);
+    }
+    return -1;
+  };
 
   // Per-lane row pointers into the padded copies; padded row q maps to
   // lp0 + q * lpw and rp0 + q * rpw.
@@ -352,8 +372,14 @@ __device__ __forceinline__ void tile_item(const FrameDev& f, int tile, int chunk
     int e0 = 0, cnt = 0;
     uint32_t pfirst = 0;
     if (sorted) {
-      e0 = __builtin_amdgcn_readlane(tp0, y - y0);
-      cnt = __builtin_amdgcn_readlane(tp1, y - y0) - e0;
+      const int i = y - y0;
+      if (i < 64) {
+        e0 = __builtin_amdgcn_readlane(tpa0, i);
+        cnt = __builtin_amdgcn_readlane(tpa1, i) - e0;
+      } else {
+        e0 = __builtin_amdgcn_readlane(tpb0, i - 64);
+        cnt = __builtin_amdgcn_readlane(tpb1, i - 64) - e0;
+      }
       if (lane < cnt) pfirst = *(g_uint32*)(f.idx + e0 + lane);   // in flight during the scans
     } else {
 #pragma unroll
@@ -362,13 +388,13 @@ __device__ __forceinline__ void tile_item(const FrameDev& f, int tile, int chunk
         if (mv[c] >= 0) {
           const int pos = cnt + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32),
                                                                __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0u));
-          sm.eo[pos] = kColsPerLane * lane + c - lpad;
+          sm.eo[pos] = (int16_t)(kColsPerLane * lane + c - lpad);
           sm.es[pos] = mv[c];
         }
         cnt += __builtin_popcountll(b);
       }
-      const uint64_t later = (y - y0 + 1 < 64) ? (rows >> (y - y0 + 1)) : 0ull;
-      if (later) load_map(y + 1 + __builtin_ctzll(later));
+      const int nxt = next_active(y);
+      if (nxt >= 0) load_map(nxt);
     }
 #pragma unroll
     for (int k0 = 0; k0 < DC; k0 += 4) {
@@ -426,7 +452,7 @@ __device__ __forceinline__ void tile_item(const FrameDev& f, int tile, int chunk
   load_row<DC>(lin, rin, En);
   load_row<DC>(lout, rout, Ex);
   for (int y = ya; y < yb; ++y) {
-    if ((rows >> (y - y0)) & 1ull) row_work(y);
+    if (is_active(y)) row_work(y);
 #pragma unroll
     for (int c = 0; c < kColsPerLane; ++c)
 #pragma unroll
