@@ -6,6 +6,7 @@
 #include <chrono>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <fstream>
 #include <map>
@@ -264,6 +265,10 @@ int run(const sbs_frame* frames, int nframes, void* workspace, size_t ws_bytes, 
   int64_t live = 0;
   for (int i = 0; i < nframes; ++i) live += frames[i].n;
   if (live == 0) return SBS_OK;
+  // Test hook: SBS_TEST_FAIL=launch makes the call fail as a failed launch
+  // would, after validation and before any device work.
+  if (const char* tf = getenv("SBS_TEST_FAIL"))
+    if (std::strcmp(tf, "launch") == 0) return fail(SBS_ERR_HIP, "injected launch failure (SBS_TEST_FAIL)");
   int cus = 0;
   int st = device_check(&cus);
   if (st != SBS_OK) return st;

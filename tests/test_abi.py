@@ -60,3 +60,11 @@ def test_workspace_bytes_and_plans():
     assert sbs.get_plan(f)["chunk"] == 8 and sbs.get_plan(f)["tile_rows"] == 16
     sbs.set_plan()
     assert sbs.get_plan(f)["chunk"] in (8, 16)
+
+
+def test_injected_launch_failure_reported(monkeypatch):
+    monkeypatch.setenv("SBS_TEST_FAIL", "launch")
+    assert _call() == 4
+    assert "injected" in sbs.lib().sbs_last_error().decode()
+    monkeypatch.delenv("SBS_TEST_FAIL")
+    assert _call(W=0) == 1
