@@ -52,6 +52,7 @@ typedef __attribute__((address_space(1))) const u32x4 g_uint4;
 typedef __attribute__((address_space(1))) const int32_t g_int32;
 typedef __attribute__((address_space(1))) const uint32_t g_uint32;
 typedef __attribute__((address_space(1))) const uint64_t g_uint64;
+typedef __attribute__((address_space(1))) uint32_t g_uint32_rw;
 
 // ---------------------------------------------------------------------------
 // Descriptor upload: the descriptors travel inside the kernel argument, so a
@@ -217,6 +218,18 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
   return v;
 }
 
+// Keeps the row loop's steps in program order: an empty instruction that
+// takes every accumulator as operand and clobbers memory, so neither the
+// arithmetic on the accumulators nor loads and LDS traffic move across it.
+template <int DC>
+__device__ __forceinline__ void pin_step(uint32_t (&cad)[kColsPerLane][DC]) {
+#pragma unroll
+  for (int c = 0; c < kColsPerLane; ++c)
+#pragma unroll
+    for (int k = 0; k < DC; k += 4)
+      asm volatile("" : "+v"(cad[c][k]), "+v"(cad[c][k + 1]), "+v"(cad[c][k + 2]), "+v"(cad[c][k + 3])::"memory");
+}
+
 // LDS of one work item: prefix sums for the chunk's DC disparities and, for
 // unordered lists, the current row's listed pixels. pre[k][4 + j] is the
 // inclusive prefix sum over window columns 0..j; pre[k][0..3] stay zero, so a
@@ -241,12 +254,13 @@ struct RowRegs {
 };
 
 template <int DC>
-__device__ __forceinline__ void load_row(const uint32_t* lrow, const uint32_t* rrow, RowRegs<DC>& o) {
-  const u32x4 lv = *(g_uint4*)lrow;
+__device__ __forceinline__ void load_row(const uint32_t* lrow, const uint32_t* rrow, uint32_t lo, RowRegs<DC>& o) {
+  // lrow, rrow: the wave's row bases (uniform); lo: this lane's word offset
+  const u32x4 lv = *(g_uint4*)(lrow + lo);
   o.L[0] = lv.x; o.L[1] = lv.y; o.L[2] = lv.z; o.L[3] = lv.w;
 #pragma unroll
   for (int q = 0; q < DC / 4 + 1; ++q) {
-    const u32x4 t = ((g_uint4*)rrow)[q];
+    const u32x4 t = *(g_uint4*)(rrow + lo + 4 * q);
     o.R[4 * q + 0] = t.x; o.R[4 * q + 1] = t.y; o.R[4 * q + 2] = t.z; o.R[4 * q + 3] = t.w;
   }
 }
@@ -261,8 +275,8 @@ __device__ __forceinline__ void add_row(const RowRegs<DC>& a, uint32_t (&cad)[kC
 
 // One work item: tile `tile` (row-major over the frame's ntx x nty tiles),
 // disparity chunk `chunk` (disparities chunk*DC .. +DC-1).
-template <int DC>
-__device__ __forceinline__ void tile_item(const FrameDev& f, int tile, int chunk, TileLds<DC>& sm) {
+template <int DC, bool kSorted>
+__device__ __forceinline__ void tile_item_impl(const FrameDev& f, int tile, int chunk, TileLds<DC>& sm) {
   const int lane = threadIdx.x;
   const int tx = tile % f.ntx, tyi = tile / f.ntx;
   const int W = f.W, H = f.H, r = f.r;
@@ -271,7 +285,7 @@ __device__ __forceinline__ void tile_item(const FrameDev& f, int tile, int chunk
   const int d0 = chunk * DC;
   const int dcount = min(DC, f.dmax + 1 - d0);
   const int lpad = f.lpad;
-  const bool sorted = !(*(g_uint32*)f.state & kUnsorted);
+  constexpr bool sorted = kSorted;
 
   // Rows of this tile (up to 128, two 64-bit masks) holding a listed pixel
   // in [x0, x1). For ordered lists lane l keeps the list ranges of rows
@@ -321,10 +335,12 @@ __device__ __forceinline__ void tile_item(const FrameDev& f, int tile, int chunk
     return -1;
   };
 
-  // Per-lane row pointers into the padded copies; padded row q maps to
-  // lp0 + q * lpw and rp0 + q * rpw.
-  const uint32_t* lp0 = f.lp + x0 + kColsPerLane * lane;
-  const uint32_t* rp0 = f.rp + x0 - lpad + kColsPerLane * lane - d0 - DC + f.rpad;
+  // Row bases into the padded copies (the same for the whole wave): padded
+  // row q of the tile starts at lp0 + q * lpw and rp0 + q * rpw; lane l reads
+  // from word lo = 4 l on.
+  const uint32_t* lp0 = f.lp + x0;
+  const uint32_t* rp0 = f.rp + x0 - lpad - d0 - DC + f.rpad;
+  const uint32_t lo = kColsPerLane * (uint32_t)lane;
   const int64_t lpw = f.lpw, rpw = f.rpw;
 
   // Disparities beyond dmax (last chunk only) never win: their keys are forced to ~0.
@@ -345,57 +361,49 @@ __device__ __forceinline__ void tile_item(const FrameDev& f, int tile, int chunk
   {
     const int last = ya + 2 * r;
     RowRegs<DC> A, B;
-    load_row<DC>(lp0 + ya * lpw, rp0 + ya * rpw, A);
+    load_row<DC>(lp0 + ya * lpw, rp0 + ya * rpw, lo, A);
     for (int q = ya; q < last; q += 2) {
-      load_row<DC>(lp0 + (q + 1) * lpw, rp0 + (q + 1) * rpw, B);
+      load_row<DC>(lp0 + (q + 1) * lpw, rp0 + (q + 1) * rpw, lo, B);
       add_row<DC>(A, cad);
-      load_row<DC>(lp0 + (q + 2) * lpw, rp0 + (q + 2) * rpw, A);
+      load_row<DC>(lp0 + (q + 2) * lpw, rp0 + (q + 2) * rpw, lo, A);
       add_row<DC>(B, cad);
     }
     add_row<DC>(A, cad);
   }
 
-  // Unordered lists: map entries of the next active row, loaded ahead.
-  int32_t mv[kColsPerLane];
-  auto load_map = [&](int y) {
-#pragma unroll
-    for (int c = 0; c < kColsPerLane; ++c) {
-      const int o = kColsPerLane * lane + c - lpad;
-      mv[c] = (o >= 0 && x0 + o < x1) ? *(g_int32*)(f.map + (int64_t)y * W + x0 + o) : -1;
-    }
-  };
-  if (!sorted) load_map(ya);
-
-  // Work on an active row: prefix sums to LDS, then every listed pixel of the
-  // row reads its window sum as the difference of two prefix entries.
-  auto row_work = [&](int y) {
-    int e0 = 0, cnt = 0;
-    uint32_t pfirst = 0;
-    if (sorted) {
+  // Each active row y takes three steps around the vertical update of the
+  // main loop:
+  //   prefix_row(y)  the window's prefix sums for the chunk's disparities to LDS;
+  //   (vertical update y -> y + 1: the one point where the wave waits for its
+  //    loads, issued one row earlier)
+  //   take_row(y)    the row's listed pixels from what that wait delivered,
+  //                  then the loads for the next step and the next active row;
+  //   entries_row(y) window sums of the row's listed pixels as differences of
+  //                  two prefix entries, folded into their keys.
+  // Loaded values are only used after the wait of the vertical update, so no
+  // other step waits for memory and the key updates, the last memory
+  // operations of a row, are not waited for until the next row's update.
+  int e0 = 0, cnt = 0;
+  uint32_t pf_cur = 0, pf_next = 0;        // ordered lists: first 64 list entries of the row
+  int32_t mv[kColsPerLane];                // unordered lists: pixel map of the next active row
+  const uint32_t mlo = kColsPerLane * (uint32_t)lane;   // this lane's first window column
+  auto load_next = [&](int y) {            // list data of active row y (y < 0: none)
+    if (y < 0) return;
+    if constexpr (kSorted) {
       const int i = y - y0;
-      if (i < 64) {
-        e0 = __builtin_amdgcn_readlane(tpa0, i);
-        cnt = __builtin_amdgcn_readlane(tpa1, i) - e0;
-      } else {
-        e0 = __builtin_amdgcn_readlane(tpb0, i - 64);
-        cnt = __builtin_amdgcn_readlane(tpb1, i - 64) - e0;
-      }
-      if (lane < cnt) pfirst = *(g_uint32*)(f.idx + e0 + lane);   // in flight during the scans
+      const int t0 = i < 64 ? __builtin_amdgcn_readlane(tpa0, i) : __builtin_amdgcn_readlane(tpb0, i - 64);
+      const int t1 = i < 64 ? __builtin_amdgcn_readlane(tpa1, i) : __builtin_amdgcn_readlane(tpb1, i - 64);
+      if ((int)lane < t1 - t0) pf_next = *(g_uint32*)(f.idx + t0 + lane);
     } else {
+      const int32_t* mrow = f.map + (int64_t)y * W + x0 - lpad;   // window column j -> image column x0 - lpad + j
 #pragma unroll
       for (int c = 0; c < kColsPerLane; ++c) {
-        const uint64_t b = __builtin_amdgcn_ballot_w64(mv[c] >= 0);
-        if (mv[c] >= 0) {
-          const int pos = cnt + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32),
-                                                               __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0u));
-          sm.eo[pos] = (int16_t)(kColsPerLane * lane + c - lpad);
-          sm.es[pos] = mv[c];
-        }
-        cnt += __builtin_popcountll(b);
+        const int o = (int)mlo + c - lpad;
+        mv[c] = (o >= 0 && x0 + o < x1) ? *(g_int32*)(mrow + mlo + c) : -1;
       }
-      const int nxt = next_active(y);
-      if (nxt >= 0) load_map(nxt);
     }
+  };
+  auto prefix_row = [&]() {
 #pragma unroll
     for (int k0 = 0; k0 < DC; k0 += 4) {
       uint32_t q[4][4], t[4];
@@ -416,26 +424,50 @@ __device__ __forceinline__ void tile_item(const FrameDev& f, int tile, int chunk
         *(lds_u32x4*)&sm.pre[k0 + i][4 + kColsPerLane * lane] = o;
       }
     }
-    __syncthreads();
-    // Output offset o (0 <= o < txo): window columns o + lpad - r .. o + lpad + r.
-    for (int e = lane; e < cnt; e += kWave) {
-      int o, slot;
-      if (sorted) {
-        const uint32_t p = e < kWave ? pfirst : *(g_uint32*)(f.idx + e0 + e);
-        o = (int)(p - (uint32_t)y * (uint32_t)W) - x0;
-        slot = e0 + e;
-      } else {
-        o = sm.eo[e];
-        slot = sm.es[e];
-      }
-      const int ih = 4 + o + lpad + r, il = 3 + o + lpad - r;
-      uint32_t best = 0xFFFFFFFFu;
+  };
+  auto take_row = [&](int y) {
+    cnt = 0;
+    if constexpr (kSorted) {
+      const int i = y - y0;
+      e0 = i < 64 ? __builtin_amdgcn_readlane(tpa0, i) : __builtin_amdgcn_readlane(tpb0, i - 64);
+      cnt = (i < 64 ? __builtin_amdgcn_readlane(tpa1, i) : __builtin_amdgcn_readlane(tpb1, i - 64)) - e0;
+      pf_cur = pf_next;
+    } else {
 #pragma unroll
-      for (int k = 0; k < DC; ++k) {
-        const uint32_t s = sm.pre[k][ih] - sm.pre[k][il];
-        best = min(best, ((s << 8) | (uint32_t)(d0 + k)) | kill[k]);
+      for (int c = 0; c < kColsPerLane; ++c) {
+        const uint64_t b = __builtin_amdgcn_ballot_w64(mv[c] >= 0);
+        if (mv[c] >= 0) {
+          const int pos = cnt + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32),
+                                                               __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0u));
+          sm.eo[pos] = (int16_t)(kColsPerLane * lane + c - lpad);
+          sm.es[pos] = mv[c];
+        }
+        cnt += __builtin_popcountll(b);
       }
-      atomicMin(&f.keys[slot], best);
+    }
+  };
+  // Window sums of one listed pixel at output offset o (0 <= o < txo; window
+  // columns o + lpad - r .. o + lpad + r), folded into key `slot`.
+  auto entry = [&](int o, int slot) {
+    const int ih = 4 + o + lpad + r, il = 3 + o + lpad - r;
+    uint32_t best = 0xFFFFFFFFu;
+#pragma unroll
+    for (int k = 0; k < DC; ++k) {
+      const uint32_t s = sm.pre[k][ih] - sm.pre[k][il];
+      best = min(best, ((s << 8) | (uint32_t)(d0 + k)) | kill[k]);
+    }
+    // a global (not flat) atomic: it counts only against the vector-memory counter
+    __hip_atomic_fetch_min((g_uint32_rw*)(f.keys + slot), best, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  };
+  auto entries_row = [&](int y) {
+    __syncthreads();
+    if constexpr (kSorted) {
+      const uint32_t rowbase = (uint32_t)y * (uint32_t)W + (uint32_t)x0;
+      if ((int)lane < cnt) entry((int)(pf_cur - rowbase), e0 + (int)lane);
+      // rows with more than 64 listed pixels in the tile: the rest loaded here
+      for (int e = (int)lane + kWave; e < cnt; e += kWave) entry((int)(*(g_uint32*)(f.idx + e0 + e) - rowbase), e0 + e);
+    } else {
+      for (int e = lane; e < cnt; e += kWave) entry(sm.eo[e], sm.es[e]);
     }
     __syncthreads();   // LDS free for the next row
   };
@@ -449,10 +481,13 @@ __device__ __forceinline__ void tile_item(const FrameDev& f, int tile, int chunk
   const uint32_t* lout = lp0 + (int64_t)ya * lpw;
   const uint32_t* rout = rp0 + (int64_t)ya * rpw;
   RowRegs<DC> En, Ex;
-  load_row<DC>(lin, rin, En);
-  load_row<DC>(lout, rout, Ex);
+  load_next(ya);
+  load_row<DC>(lin, rin, lo, En);
+  load_row<DC>(lout, rout, lo, Ex);
   for (int y = ya; y < yb; ++y) {
-    if (is_active(y)) row_work(y);
+    const bool act = is_active(y);
+    if (act) prefix_row();
+    pin_step<DC>(cad);
 #pragma unroll
     for (int c = 0; c < kColsPerLane; ++c)
 #pragma unroll
@@ -460,11 +495,31 @@ __device__ __forceinline__ void tile_item(const FrameDev& f, int tile, int chunk
         const uint32_t out = __builtin_amdgcn_sad_u8(Ex.L[c], Ex.R[c + DC - k], 0u);
         cad[c][k] = __builtin_amdgcn_sad_u8(En.L[c], En.R[c + DC - k], cad[c][k]) - out;
       }
+    pin_step<DC>(cad);
+    if (act) {
+      take_row(y);
+      load_next(next_active(y));
+    }
     lin += lpw; rin += rpw; lout += lpw; rout += rpw;
-    load_row<DC>(lin, rin, En);
-    load_row<DC>(lout, rout, Ex);
+    load_row<DC>(lin, rin, lo, En);
+    load_row<DC>(lout, rout, lo, Ex);
+    if (act) entries_row(y);
+    // R[0] only pads the loads to 16 bytes; keeping it live stops its
+    // register from being reused while the load is still in flight.
+    asm volatile("" ::"v"(En.R[0]), "v"(Ex.R[0]));
   }
-  row_work(yb);
+  prefix_row();
+  take_row(yb);
+  entries_row(yb);
+}
+
+// Ordered and unordered lists take separate instances (fewer live registers in each).
+template <int DC>
+__device__ __forceinline__ void tile_item(const FrameDev& f, int tile, int chunk, TileLds<DC>& sm) {
+  if (*(g_uint32*)f.state & kUnsorted)
+    tile_item_impl<DC, false>(f, tile, chunk, sm);
+  else
+    tile_item_impl<DC, true>(f, tile, chunk, sm);
 }
 
 template <int DC>
