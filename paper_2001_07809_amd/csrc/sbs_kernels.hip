@@ -221,13 +221,13 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
 // Keeps the row loop's steps in program order: an empty instruction that
 // takes every accumulator as operand and clobbers memory, so neither the
 // arithmetic on the accumulators nor loads and LDS traffic move across it.
-template <int DC>
-__device__ __forceinline__ void pin_step(uint32_t (&cad)[kColsPerLane][DC]) {
+template <int N>
+__device__ __forceinline__ void pin_step(uint32_t (&v)[kColsPerLane][N]) {
 #pragma unroll
   for (int c = 0; c < kColsPerLane; ++c)
 #pragma unroll
-    for (int k = 0; k < DC; k += 4)
-      asm volatile("" : "+v"(cad[c][k]), "+v"(cad[c][k + 1]), "+v"(cad[c][k + 2]), "+v"(cad[c][k + 3])::"memory");
+    for (int k = 0; k < N; k += 4)
+      asm volatile("" : "+v"(v[c][k]), "+v"(v[c][k + 1]), "+v"(v[c][k + 2]), "+v"(v[c][k + 3])::"memory");
 }
 
 // LDS of one work item: prefix sums for the chunk's DC disparities and, for
@@ -265,17 +265,60 @@ __device__ __forceinline__ void load_row(const uint32_t* lrow, const uint32_t* r
   }
 }
 
-template <int DC>
-__device__ __forceinline__ void add_row(const RowRegs<DC>& a, uint32_t (&cad)[kColsPerLane][DC]) {
+// Accumulators per lane: kPack == false keeps one 32-bit sum per (column,
+// disparity); kPack == true keeps disparities d0 + 2j and d0 + 2j + 1 of a
+// column in the low and high 16 bits of one register (usable while a window
+// column's sum, at most block * 255 * C, fits in 16 bits).
+template <int DC, bool kPack>
+struct Acc {
+  static constexpr int N = kPack ? DC / 2 : DC;
+  uint32_t v[kColsPerLane][N];
+  // window column 4 lane + c, disparity d0 + k
+  __device__ __forceinline__ uint32_t get(int c, int k) const {
+    if constexpr (kPack) return (k & 1) ? (v[c][k >> 1] >> 16) : (v[c][k >> 1] & 0xFFFFu);
+    else return v[c][k];
+  }
+};
+
+// Adds one padded row to the accumulators.
+template <int DC, bool kPack>
+__device__ __forceinline__ void add_row(const RowRegs<DC>& a, Acc<DC, kPack>& acc) {
 #pragma unroll
   for (int c = 0; c < kColsPerLane; ++c)
 #pragma unroll
-    for (int k = 0; k < DC; ++k) cad[c][k] = __builtin_amdgcn_sad_u8(a.L[c], a.R[c + DC - k], cad[c][k]);
+    for (int j = 0; j < Acc<DC, kPack>::N; ++j) {
+      if constexpr (kPack)
+        acc.v[c][j] = __builtin_amdgcn_sad_hi_u8(a.L[c], a.R[c + DC - 2 * j - 1],
+                                                 __builtin_amdgcn_sad_u8(a.L[c], a.R[c + DC - 2 * j], acc.v[c][j]));
+      else
+        acc.v[c][j] = __builtin_amdgcn_sad_u8(a.L[c], a.R[c + DC - j], acc.v[c][j]);
+    }
+}
+
+// Moves the window down one row: padded row `ex` leaves, `en` enters. The
+// leaving row is taken off first, so no partial sum exceeds a full window.
+template <int DC, bool kPack>
+__device__ __forceinline__ void slide_row(const RowRegs<DC>& en, const RowRegs<DC>& ex, Acc<DC, kPack>& acc) {
+#pragma unroll
+  for (int c = 0; c < kColsPerLane; ++c)
+#pragma unroll
+    for (int j = 0; j < Acc<DC, kPack>::N; ++j) {
+      if constexpr (kPack) {
+        const uint32_t out = __builtin_amdgcn_sad_hi_u8(ex.L[c], ex.R[c + DC - 2 * j - 1],
+                                                        __builtin_amdgcn_sad_u8(ex.L[c], ex.R[c + DC - 2 * j], 0u));
+        const uint32_t t = acc.v[c][j] - out;   // no borrow between the halves: each half holds its own row
+        acc.v[c][j] = __builtin_amdgcn_sad_hi_u8(en.L[c], en.R[c + DC - 2 * j - 1],
+                                                 __builtin_amdgcn_sad_u8(en.L[c], en.R[c + DC - 2 * j], t));
+      } else {
+        const uint32_t out = __builtin_amdgcn_sad_u8(ex.L[c], ex.R[c + DC - j], 0u);
+        acc.v[c][j] = __builtin_amdgcn_sad_u8(en.L[c], en.R[c + DC - j], acc.v[c][j] - out);
+      }
+    }
 }
 
 // One work item: tile `tile` (row-major over the frame's ntx x nty tiles),
 // disparity chunk `chunk` (disparities chunk*DC .. +DC-1).
-template <int DC, bool kSorted>
+template <int DC, bool kSorted, bool kPack>
 __device__ __forceinline__ void tile_item_impl(const FrameDev& f, int tile, int chunk, TileLds<DC>& sm) {
   const int lane = threadIdx.x;
   const int tx = tile % f.ntx, tyi = tile / f.ntx;
@@ -348,13 +391,13 @@ __device__ __forceinline__ void tile_item_impl(const FrameDev& f, int tile, int 
 #pragma unroll
   for (int k = 0; k < DC; ++k) kill[k] = k < dcount ? 0u : 0xFFFFFFFFu;
 
-  // cad[c][k]: sum over the window's rows of the absolute differences in
-  // window column 4 lane + c at disparity d0 + k.
-  uint32_t cad[kColsPerLane][DC];
+  // acc: per window column 4 lane + c and disparity d0 + k, the sum over the
+  // window's rows of the absolute differences (summed over channels).
+  Acc<DC, kPack> acc;
 #pragma unroll
   for (int c = 0; c < kColsPerLane; ++c)
 #pragma unroll
-    for (int k = 0; k < DC; ++k) cad[c][k] = 0;
+    for (int j = 0; j < Acc<DC, kPack>::N; ++j) acc.v[c][j] = 0;
 
   // Window of output row ya: padded rows ya .. ya + 2r (an odd count), in
   // pairs with the next row's loads in flight, then the last row.
@@ -364,11 +407,11 @@ __device__ __forceinline__ void tile_item_impl(const FrameDev& f, int tile, int 
     load_row<DC>(lp0 + ya * lpw, rp0 + ya * rpw, lo, A);
     for (int q = ya; q < last; q += 2) {
       load_row<DC>(lp0 + (q + 1) * lpw, rp0 + (q + 1) * rpw, lo, B);
-      add_row<DC>(A, cad);
+      add_row<DC, kPack>(A, acc);
       load_row<DC>(lp0 + (q + 2) * lpw, rp0 + (q + 2) * rpw, lo, A);
-      add_row<DC>(B, cad);
+      add_row<DC, kPack>(B, acc);
     }
-    add_row<DC>(A, cad);
+    add_row<DC, kPack>(A, acc);
   }
 
   // Each active row y takes three steps around the vertical update of the
@@ -409,10 +452,10 @@ __device__ __forceinline__ void tile_item_impl(const FrameDev& f, int tile, int 
       uint32_t q[4][4], t[4];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        q[i][0] = cad[0][k0 + i];
-        q[i][1] = q[i][0] + cad[1][k0 + i];
-        q[i][2] = q[i][1] + cad[2][k0 + i];
-        q[i][3] = q[i][2] + cad[3][k0 + i];
+        q[i][0] = acc.get(0, k0 + i);
+        q[i][1] = q[i][0] + acc.get(1, k0 + i);
+        q[i][2] = q[i][1] + acc.get(2, k0 + i);
+        q[i][3] = q[i][2] + acc.get(3, k0 + i);
         t[i] = q[i][3];
       }
       wave_incl_scan4(t[0], t[1], t[2], t[3]);
@@ -487,15 +530,9 @@ __device__ __forceinline__ void tile_item_impl(const FrameDev& f, int tile, int 
   for (int y = ya; y < yb; ++y) {
     const bool act = is_active(y);
     if (act) prefix_row();
-    pin_step<DC>(cad);
-#pragma unroll
-    for (int c = 0; c < kColsPerLane; ++c)
-#pragma unroll
-      for (int k = 0; k < DC; ++k) {
-        const uint32_t out = __builtin_amdgcn_sad_u8(Ex.L[c], Ex.R[c + DC - k], 0u);
-        cad[c][k] = __builtin_amdgcn_sad_u8(En.L[c], En.R[c + DC - k], cad[c][k]) - out;
-      }
-    pin_step<DC>(cad);
+    pin_step(acc.v);
+    slide_row<DC, kPack>(En, Ex, acc);
+    pin_step(acc.v);
     if (act) {
       take_row(y);
       load_next(next_active(y));
@@ -514,12 +551,18 @@ __device__ __forceinline__ void tile_item_impl(const FrameDev& f, int tile, int 
 }
 
 // Ordered and unordered lists take separate instances (fewer live registers in each).
+// Ordered and unordered lists, packed and 32-bit accumulators take separate
+// instances (fewer live registers in each).
 template <int DC>
 __device__ __forceinline__ void tile_item(const FrameDev& f, int tile, int chunk, TileLds<DC>& sm) {
-  if (*(g_uint32*)f.state & kUnsorted)
-    tile_item_impl<DC, false>(f, tile, chunk, sm);
-  else
-    tile_item_impl<DC, true>(f, tile, chunk, sm);
+  const bool unsorted = *(g_uint32*)f.state & kUnsorted;
+  if (f.pack) {
+    if (unsorted) tile_item_impl<DC, false, true>(f, tile, chunk, sm);
+    else tile_item_impl<DC, true, true>(f, tile, chunk, sm);
+  } else {
+    if (unsorted) tile_item_impl<DC, false, false>(f, tile, chunk, sm);
+    else tile_item_impl<DC, true, false>(f, tile, chunk, sm);
+  }
 }
 
 template <int DC>

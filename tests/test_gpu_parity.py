@@ -274,3 +274,21 @@ def test_graph_capture_replays(torch, sbs):
         got0 = (runner.disp[0].cpu().numpy(), runner.cost[0].cpu().numpy().view(np.uint32))
         assert_parity(got0, exp3 if rep >= 2 else exp0, f"replay {rep}")
         _ = torch.ones(1000, device="cuda").sum().item()   # eager work between replays
+
+
+def test_saturated_sums_at_the_16_bit_accumulator_limit(torch, sbs):
+    """Blocks on both sides of the packed-accumulator bound (block * 255 * C <= 65535):
+    images at 0 and 255 so window column sums reach their maximum."""
+    rng = np.random.default_rng(21)
+    H, W = 180, 140
+    for C, blocks in [(3, (83, 85, 87)), (1, (127,))]:
+        shape = (H, W, C) if C == 3 else (H, W)
+        L = (rng.integers(0, 2, shape) * 255).astype(np.uint8)
+        L[:, : W // 2] = 255
+        R = np.zeros(shape, np.uint8)
+        R[H // 3:, :] = (rng.integers(0, 2, R[H // 3:].shape) * 255).astype(np.uint8)
+        idx = np.sort(rng.choice(H * W, 400, replace=False)).astype(np.uint32)
+        for block in blocks:
+            exp = oracle.sad(L, R, idx, block, 20)
+            assert exp[1].max() >= block * 255 * C // 2, "inputs must drive column sums near the limit"
+            assert_parity(run_gpu(torch, sbs, L, R, idx, block, 20), exp, f"C{C} b{block} saturated")
