@@ -92,6 +92,8 @@ def main():
     ap.add_argument("--serve", action="store_true",
                     help="serving mode: 2000 mixed-resolution requests, continuous batching, p50/p99 latency")
     ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--paper", action="store_true",
+                    help="the paper's whole chain (Table 3 setting) per frame: stage times and Eq. 3 on synthetic GT")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run one plain device copy of MIB mebibytes (HBM counter calibration)")
     args = ap.parse_args()
@@ -125,6 +127,9 @@ def main():
         sbs.load_tuning(args.tuning)
     if args.serve:
         serve_main(args)
+        return
+    if args.paper:
+        paper_main(args)
         return
 
     spec = scenes.PRESETS[args.workload]
@@ -303,6 +308,61 @@ def main():
 
 SERVE_CLASSES = [("serve_vga", 1000), ("serve_fhd", 600), ("serve_uhd", 400)]
 SERVE_FRACS = (0.12, 0.16, 0.20, 0.24)
+
+
+def paper_main(args):
+    """Raw stereo pair to blurred image on the device, in the paper's Table 3
+    setting (K = 10, fill/remove + 4% rule, 9x9 SAD on L*), per workload:
+    GPU time of each stage (HIP events on the stream the stages run on) and
+    the percentage of bad pixels (Eq. 3, delta = 1) against the generator's
+    ground truth, on listed and on all unoccluded pixels."""
+    import numpy as np
+    import torch
+
+    import paper_2001_07809_amd as sbs
+    from paper_2001_07809_amd import pipeline
+    import scenes
+
+    out = {"metric": "paper chain: stage ms per frame; bad-pixel % (Eq. 3)", "workloads": {}}
+    for name, dmax, thr in [("tsukuba_gray", 15, 0), ("middlebury_rgb", 63, 1), ("uhd_rgb", 127, 1)]:
+        spec = scenes.PRESETS[name]
+        f = scenes.make_frame(spec)
+        L = torch.from_numpy(f.left).cuda()
+        R = torch.from_numpy(f.right).cuda()
+        H, W = f.gt.shape
+        p = pipeline.PaperParams(dmax=dmax, threshold=thr, ranges=((0, dmax // 3),))
+        stages = ["lightness", "front_end", "sad", "reconstruct", "blur"]
+        times = {k: [] for k in stages}
+        for it in range(args.warmup + args.steps):
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(len(stages) + 1)]
+            ev[0].record()
+            l8 = sbs.lightness(L); r8 = sbs.lightness(R)
+            ev[1].record()
+            lst = sbs.boundaries(l8, K=p.K, mode=p.mode)     # reads the list length back (one sync)
+            ev[2].record()
+            d, c = sbs.sad_disparity(l8, r8, lst, p.block, p.dmax)
+            ev[3].record()
+            dense = sbs.reconstruct(lst, d, W, H, p.threshold)
+            ev[4].record()
+            sbs.selective_blur(L, dense, p.ranges, p.sigma)
+            ev[5].record()
+            torch.cuda.synchronize()
+            if it >= args.warmup:
+                for k, st in enumerate(stages):
+                    times[st].append(ev[k].elapsed_time(ev[k + 1]))
+        idx = lst.cpu().numpy().view(np.uint32)
+        dl = d.cpu().numpy()
+        occ = f.occ.reshape(-1)
+        b_list = pipeline.bad_pixel_percent(dl, f.gt.reshape(-1)[idx], mask=occ[idx] == 0)
+        b_dense = pipeline.bad_pixel_percent(dense.cpu().numpy().reshape(-1), f.gt.reshape(-1), mask=occ == 0)
+        rec = {"size": f"{W}x{H}x{spec.C}", "block": p.block, "dmax": dmax, "K": p.K, "threshold": thr,
+               "listed_fraction": round(idx.size / (W * H), 4),
+               "stage_ms": {k: round(float(np.median(v)), 4) for k, v in times.items()},
+               "total_ms": round(float(sum(np.median(v) for v in times.values())), 4),
+               "bad_pixel_pct_listed": round(b_list, 3), "bad_pixel_pct_dense": round(b_dense, 3)}
+        log(f"paper chain {name}: {rec}")
+        out["workloads"][name] = rec
+    print(json.dumps(out), flush=True)
 
 
 def serve_main(args):

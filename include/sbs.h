@@ -223,6 +223,55 @@ int sbs_selective_blur(const uint8_t* img, int32_t W, int32_t H, int32_t C, int6
                        const int32_t* ranges, int32_t nranges, float sigma, float* out, void* workspace,
                        size_t workspace_bytes, void* stream);
 
+/*
+ * Lightness (Sec. III, Colour Space Conversion): the L of CIE L*a*b* per
+ * pixel, scaled to 8 bits. C == 3: sRGB decode of each channel, Y = 0.2126 R
+ * + 0.7152 G + 0.0722 B on linear values, L* = 116 f(Y) - 16 with the CIE f
+ * (cube root above (6/29)^3, linear below), L8 = round-half-away(L* 255/100),
+ * in fp64 with every operation rounded on its own. C == 1: L8 = the gray value.
+ *   img      device, HWC u8, rows `pitch` bytes apart (pitch >= W*C)
+ *   out_l8   device, W*H bytes, row-major
+ * Asynchronous on `stream`. SBS_ERR_INVALID_ARG for bad geometry or NULL.
+ */
+int sbs_lightness(const uint8_t* img, int32_t W, int32_t H, int32_t C, int64_t pitch, uint8_t* out_l8, void* stream);
+
+/*
+ * Refined segment-boundary pixels of the left image, the list the disparity
+ * search runs on (Sec. III: Colour Space Conversion, Segmentation, Segment
+ * Boundary Detection, Refinement; the border rule of Disparity Measurement).
+ *   lightness -> 256-bin histogram -> K-means on the bins (distance |a - b|,
+ *   exact rational centres, start c_k = Lmin + floor((2k+1)(Lmax-Lmin+1)/2K),
+ *   ties to the lower cluster, empty clusters keep their centre, stop when no
+ *   bin changes or after 1000 passes, clusters renumbered by ascending centre)
+ *   -> label image ->
+ *     mode 0 (configured): 3x3 open then close on the labels (replicate
+ *       border), 8-neighbour boundary map, keep 8-connected components of at
+ *       least min_cc pixels;
+ *     mode 1 (paper): 8-neighbour boundary map, 'fill' (a 0 whose eight
+ *       neighbours are 1 becomes 1), 'remove' (a 1 whose four 4-neighbours are
+ *       1 becomes 0), both with outside pixels = 0; then drop the smallest
+ *       8-connected components, ties by smallest raster index, while the
+ *       dropped total stays <= floor(0.04 * all boundary pixels)
+ *   -> list = left and right border columns plus the kept pixels, ascending.
+ *   img          device, HWC u8, rows `pitch` bytes apart; C = 1 or 3
+ *   K            clusters, 1..64
+ *   out_idx      device, capacity W*H u32: raster indices y*W + x, ascending
+ *   out_count    device, one int64: the list length (written by the GPU, so
+ *                the call stays asynchronous)
+ *   out_refined  device W*H bytes or NULL: the kept boundary map (1/0),
+ *                without the border columns
+ *   out_labels   device W*H bytes or NULL: the label image the boundary map
+ *                is taken from (after open/close in mode 0)
+ *   workspace    device, >= sbs_boundaries_workspace_bytes(W, H) bytes; the
+ *                library keeps nothing in it between calls
+ * W*H <= 2^31 - 1 and H <= 262140 (else SBS_ERR_UNSUPPORTED). Asynchronous
+ * on `stream`; SBS_ERR_INVALID_ARG for bad arguments (nothing is launched then).
+ */
+size_t sbs_boundaries_workspace_bytes(int32_t W, int32_t H);
+int sbs_boundaries(const uint8_t* img, int32_t W, int32_t H, int32_t C, int64_t pitch, int32_t K, int32_t mode,
+                   int32_t min_cc, uint32_t* out_idx, int64_t* out_count, uint8_t* out_refined, uint8_t* out_labels,
+                   void* workspace, size_t workspace_bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

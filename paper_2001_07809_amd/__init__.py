@@ -45,7 +45,7 @@ class SbsError(RuntimeError):
 def build() -> str:
     """Compile libsbs.so for gfx950 (always recompiles)."""
     srcs = [os.path.join(_CSRC, "sbs_kernels.hip"), os.path.join(_CSRC, "sbs_api.hip"),
-            os.path.join(_CSRC, "sbs_post.hip")]
+            os.path.join(_CSRC, "sbs_post.hip"), os.path.join(_CSRC, "sbs_front.hip")]
     cmd = [HIPCC, *HIP_FLAGS, *srcs, "-o", _SO + ".tmp"]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
@@ -100,6 +100,9 @@ def lib():
         "sbs_selective_blur_workspace_bytes": ([I32, I32, I32], SZ),
         "sbs_selective_blur": ([V, I32, I32, I32, I64, V, V, I32, ctypes.c_float, V, V, SZ, V], ctypes.c_int),
         "sbs_kernel_times": ([ctypes.POINTER(ctypes.c_float), I32], I32),
+        "sbs_lightness": ([V, I32, I32, I32, I64, V, V], ctypes.c_int),
+        "sbs_boundaries_workspace_bytes": ([I32, I32], SZ),
+        "sbs_boundaries": ([V, I32, I32, I32, I64, I32, I32, I32, V, V, V, V, V, SZ, V], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -268,6 +271,37 @@ def selective_blur(img, depth, ranges, sigma: float, stream=None):
                                     float(sigma), out.data_ptr(), ws.data_ptr(), ws.numel(),
                                     _stream_handle(stream)))
     return out
+
+
+def lightness(img, stream=None):
+    """u8 lightness [H, W] of a device image (gray passes through)."""
+    torch = _torch()
+    W, H, C, pitch = _image_args(img)
+    out = torch.empty((H, W), dtype=torch.uint8, device=img.device)
+    _check(lib().sbs_lightness(img.data_ptr(), W, H, C, pitch, out.data_ptr(), _stream_handle(stream)))
+    return out
+
+
+def boundaries(img, K: int = 4, mode: int = 0, min_cc: int = 50, with_maps: bool = False, stream=None):
+    """Ascending int32 device list of refined boundary pixels (plus border
+    columns) of a device image. With ``with_maps`` also returns the kept
+    boundary map and the label image [H, W] u8."""
+    torch = _torch()
+    W, H, C, pitch = _image_args(img)
+    dev = img.device
+    out = torch.empty(W * H, dtype=torch.int32, device=dev)
+    count = torch.zeros(1, dtype=torch.int64, device=dev)
+    refined = torch.empty((H, W), dtype=torch.uint8, device=dev) if with_maps else None
+    labels = torch.empty((H, W), dtype=torch.uint8, device=dev) if with_maps else None
+    nb = int(lib().sbs_boundaries_workspace_bytes(W, H))
+    ws = torch.empty(max(nb, 256), dtype=torch.uint8, device=dev)
+    _check(lib().sbs_boundaries(img.data_ptr(), W, H, C, pitch, K, mode, min_cc, out.data_ptr(), count.data_ptr(),
+                                None if refined is None else refined.data_ptr(),
+                                None if labels is None else labels.data_ptr(), ws.data_ptr(), ws.numel(),
+                                _stream_handle(stream)))
+    n = int(count.item())
+    lst = out[:n]
+    return (lst, refined, labels) if with_maps else lst
 
 
 class BatchRunner:

@@ -1,0 +1,609 @@
+// The step before the disparity search (arXiv 2001.07809, Sec. III): from a
+// left image to the ascending list of its refined segment-boundary pixels.
+//   lightness      CIE L* of each pixel, scaled to 8 bits ("Colour Space
+//                  Conversion"); gray images pass through
+//   histogram      256 bins of lightness ("Segmentation")
+//   k-means        on the bins, distance |a - b|, exact rational centres
+//   labels         each pixel takes its bin's cluster, renumbered by
+//                  ascending centre
+//   refinement     configured: 3x3 open then close on the labels; paper:
+//                  Moore-neighbour boundary, then 'fill', then 'remove'
+//                  ("Segment Boundary Detection", "Refinement")
+//   components     8-connected components of the boundary map by lock-free
+//                  union-find; each root is its component's smallest raster
+//                  index
+//   filter         configured: keep components of at least min_cc pixels;
+//                  paper: drop the smallest components (ties by raster order)
+//                  while the dropped total stays within 4% of all boundary
+//                  pixels
+//   list           left and right border columns plus the kept pixels, in
+//                  ascending raster order ("Disparity Measurement": pixels on
+//                  the left/right borders of the map count as boundary)
+// Declared in include/sbs.h.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <cstdarg>
+#include <cstdio>
+
+#include "../../include/sbs.h"
+#include "sbs_internal.h"
+
+namespace sbs_front {
+
+constexpr int kBlock = 256;
+constexpr int kScanPer = 1024;     // elements per block in the device-wide scans
+constexpr int kMaxK = 64;
+constexpr int kMaxPasses = 1000;
+
+// ---------------------------------------------------------------------------
+// Lightness. sRGB decode of each channel, luminance Y = 0.2126 R + 0.7152 G +
+// 0.0722 B on linear values, L* = 116 f(Y) - 16 with f the CIE cube-root law
+// (linear below (6/29)^3), scaled by 255/100 and rounded half away from zero.
+// fp64 without contraction: every product and sum is rounded on its own.
+__device__ __forceinline__ double srgb_linear(int v) {
+#pragma clang fp contract(off)
+  const double c = v / 255.0;
+  return c <= 0.04045 ? c / 12.92 : pow((c + 0.055) / 1.055, 2.4);
+}
+
+__global__ __launch_bounds__(kBlock) void k_light(const uint8_t* __restrict__ img, int32_t W, int32_t H, int32_t C,
+                                                  int64_t pitch, uint8_t* __restrict__ L8) {
+#pragma clang fp contract(off)
+  __shared__ double lin[256];
+  if (C == 3) {
+    lin[threadIdx.x] = srgb_linear((int)threadIdx.x);
+    __syncthreads();
+  }
+  const int64_t N = (int64_t)W * H;
+  const double e = 6.0 / 29.0;
+  const double e3 = e * e * e, k3 = 3 * e * e;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
+    const int y = (int)(i / W), x = (int)(i % W);
+    const uint8_t* p = img + (int64_t)y * pitch + (int64_t)x * C;
+    if (C == 1) { L8[i] = p[0]; continue; }
+    const double Y = 0.2126 * lin[p[0]] + 0.7152 * lin[p[1]] + 0.0722 * lin[p[2]];
+    const double f = Y > e3 ? cbrt(Y) : Y / k3 + 4.0 / 29.0;
+    const double s = (116.0 * f - 16.0) * 255.0 / 100.0;
+    const double q = s >= 0 ? floor(s + 0.5) : -floor(-s + 0.5);
+    L8[i] = (uint8_t)(q < 0 ? 0 : (q > 255 ? 255 : (int)q));
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_fill(uint8_t* p, int64_t n, uint8_t v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
+// Histogram: per-block counts in LDS, then one global add per bin.
+__global__ __launch_bounds__(kBlock) void k_hist(const uint8_t* __restrict__ L8, int64_t N,
+                                                 unsigned long long* __restrict__ hist) {
+  __shared__ uint32_t h[256];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x)
+    atomicAdd(&h[L8[i]], 1u);
+  __syncthreads();
+  if (h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], (unsigned long long)h[threadIdx.x]);
+}
+
+// K-means on the occupied bins, one block, thread b owns bin b. Centres are
+// S_k / N_k (exact rationals); start c_k = Lmin + floor((2k+1)(Lmax-Lmin+1) /
+// 2K) with N_k = 1; a bin goes to the nearest centre, ties to the lower k; an
+// empty cluster keeps its centre; passes stop when no bin changes (at most
+// 1000). Clusters are then renumbered by ascending centre (ties by index).
+// Output: lut[b] = label of bin b (0 for empty bins).
+__global__ __launch_bounds__(256) void k_kmeans(const unsigned long long* __restrict__ hist, int32_t K,
+                                                uint8_t* __restrict__ lut, int32_t* __restrict__ passes_out) {
+  __shared__ long long S[kMaxK], Nn[kMaxK];
+  __shared__ unsigned long long s2[kMaxK], n2[kMaxK];
+  __shared__ int lo_s, hi_s, changed;
+  __shared__ int rank[kMaxK];
+  const int b = threadIdx.x;
+  const long long hb = (long long)hist[b];
+  if (b == 0) { lo_s = 256; hi_s = -1; }
+  __syncthreads();
+  if (hb > 0) { atomicMin(&lo_s, b); atomicMax(&hi_s, b); }
+  __syncthreads();
+  const int lo = lo_s, hi = hi_s;
+  if (hi < 0) {   // empty image cannot occur (N >= 1), kept for completeness
+    lut[b] = 0;
+    if (b == 0) *passes_out = 0;
+    return;
+  }
+  if (b < K) { S[b] = lo + ((long long)(2 * b + 1) * (hi - lo + 1)) / (2 * K); Nn[b] = 1; }
+  int assign = -1;
+  int pass = 0;
+  for (; pass < kMaxPasses; ++pass) {
+    if (b == 0) changed = 0;
+    if (b < K) { s2[b] = 0; n2[b] = 0; }
+    __syncthreads();
+    if (hb > 0) {
+      int best = 0;
+      for (int k = 1; k < K; ++k) {
+        // |b - S_k/N_k| < |b - S_best/N_best|  <=>  |b N_k - S_k| N_best < |b N_best - S_best| N_k
+        const long long dk = llabs((long long)b * Nn[k] - S[k]);
+        const long long db = llabs((long long)b * Nn[best] - S[best]);
+        if ((__int128)dk * Nn[best] < (__int128)db * Nn[k]) best = k;
+      }
+      if (assign != best) { assign = best; changed = 1; }
+    }
+    __syncthreads();
+    const int ch = changed;
+    if (!ch && pass > 0) break;
+    if (hb > 0) {
+      atomicAdd(&s2[assign], (unsigned long long)(b * hb));
+      atomicAdd(&n2[assign], (unsigned long long)hb);
+    }
+    __syncthreads();
+    if (b < K && n2[b] > 0) { S[b] = (long long)s2[b]; Nn[b] = (long long)n2[b]; }
+    __syncthreads();
+    if (!ch) break;
+  }
+  if (b < K) {
+    int rk = 0;
+    for (int j = 0; j < K; ++j) {
+      const __int128 a = (__int128)S[j] * Nn[b], c = (__int128)S[b] * Nn[j];
+      rk += (a < c) || (a == c && j < b);
+    }
+    rank[b] = rk;
+  }
+  __syncthreads();
+  lut[b] = assign < 0 ? 0 : (uint8_t)rank[assign];
+  if (b == 0) *passes_out = pass + 1;
+}
+
+__global__ __launch_bounds__(kBlock) void k_label(const uint8_t* __restrict__ L8, int64_t N,
+                                                  const uint8_t* __restrict__ lut, uint8_t* __restrict__ lab) {
+  __shared__ uint8_t t[256];
+  t[threadIdx.x] = lut[threadIdx.x];
+  __syncthreads();
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x)
+    lab[i] = t[L8[i]];
+}
+
+// ---------------------------------------------------------------------------
+// 3x3 stencils. One thread per pixel of a 2-D grid.
+//   op 0: erosion (min), op 1: dilation (max), replicate border;
+//   op 2: Moore boundary (1 iff an in-image 8-neighbour differs);
+//   op 3: 'fill' (a 0 whose eight neighbours are all 1 becomes 1; outside = 0);
+//   op 4: 'remove' (a 1 whose four 4-neighbours are all 1 becomes 0; outside = 0).
+template <int OP>
+__global__ __launch_bounds__(kBlock) void k_stencil(const uint8_t* __restrict__ in, int32_t W, int32_t H,
+                                                    uint8_t* __restrict__ out) {
+  const int x = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
+  if (x >= W || y >= H) return;
+  const uint8_t v = in[(int64_t)y * W + x];
+  auto at = [&](int yy, int xx) -> int { return in[(int64_t)yy * W + xx]; };
+  uint8_t r = v;
+  if constexpr (OP == 0 || OP == 1) {
+    for (int j = -1; j <= 1; ++j)
+      for (int i = -1; i <= 1; ++i) {
+        const int u = at(min(max(y + j, 0), H - 1), min(max(x + i, 0), W - 1));
+        r = OP == 0 ? (uint8_t)min((int)r, u) : (uint8_t)max((int)r, u);
+      }
+  } else if constexpr (OP == 2) {
+    r = 0;
+    for (int j = -1; j <= 1; ++j)
+      for (int i = -1; i <= 1; ++i) {
+        const int yy = y + j, xx = x + i;
+        if ((i || j) && yy >= 0 && yy < H && xx >= 0 && xx < W && at(yy, xx) != v) r = 1;
+      }
+  } else if constexpr (OP == 3) {
+    if (!v) {
+      bool all = true;
+      for (int j = -1; j <= 1; ++j)
+        for (int i = -1; i <= 1; ++i) {
+          const int yy = y + j, xx = x + i;
+          if ((i || j) && (yy < 0 || yy >= H || xx < 0 || xx >= W || !at(yy, xx))) all = false;
+        }
+      r = all ? 1 : 0;
+    }
+  } else {
+    auto in_at = [&](int yy, int xx) -> int { return (yy < 0 || yy >= H || xx < 0 || xx >= W) ? 0 : at(yy, xx); };
+    if (v && in_at(y - 1, x) && in_at(y + 1, x) && in_at(y, x - 1) && in_at(y, x + 1)) r = 0;
+  }
+  out[(int64_t)y * W + x] = r;
+}
+
+// ---------------------------------------------------------------------------
+// Connected components by union-find. A link always points a larger root at
+// a smaller one, so a component's root ends as its smallest index.
+__device__ __forceinline__ int32_t uf_find(const int32_t* parent, int32_t a) {
+  int32_t p = __hip_atomic_load(&parent[a], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  while (p != a) {
+    a = p;
+    p = __hip_atomic_load(&parent[a], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  return a;
+}
+
+__device__ __forceinline__ void uf_union(int32_t* parent, int32_t a, int32_t b) {
+  for (;;) {
+    a = uf_find(parent, a);
+    b = uf_find(parent, b);
+    if (a == b) return;
+    if (a < b) { const int32_t t = a; a = b; b = t; }
+    // a > b, a was a root when found: make it point at b unless it moved meanwhile
+    const int32_t old = atomicMin(&parent[a], b);
+    if (old == a) return;
+    a = old;   // a was linked elsewhere concurrently: continue from there
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_cc_init(const uint8_t* __restrict__ B, int64_t N, int32_t* parent,
+                                                    int32_t* size) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
+    parent[i] = B[i] ? (int32_t)i : -1;
+    size[i] = 0;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_cc_merge(const uint8_t* __restrict__ B, int32_t W, int32_t H,
+                                                     int32_t* parent) {
+  const int x = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
+  if (x >= W || y >= H) return;
+  const int32_t i = y * W + x;
+  if (!B[i]) return;
+  // the four neighbours before this pixel in raster order (8-connectivity)
+  if (x > 0 && B[i - 1]) uf_union(parent, i, i - 1);
+  if (y > 0) {
+    const int32_t u = i - W;
+    if (x > 0 && B[u - 1]) uf_union(parent, i, u - 1);
+    if (B[u]) uf_union(parent, i, u);
+    if (x + 1 < W && B[u + 1]) uf_union(parent, i, u + 1);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_cc_flatten(int64_t N, int32_t* parent, int32_t* size) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
+    if (parent[i] < 0) continue;
+    const int32_t r = uf_find(parent, (int32_t)i);
+    parent[i] = r;
+    atomicAdd(&size[r], 1);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Paper filter: components in ascending (size, root) order are dropped while
+// the dropped total stays <= floor(0.04 * total). With cnt[s] the number of
+// components of size s (s <= budget), everything below the first size s* that
+// no longer fits whole is dropped, and of size s* the first m by root.
+struct DropRule {
+  long long total;    // boundary pixels
+  long long budget;   // floor(drop_frac * total)
+  int32_t s_star;     // sizes < s_star dropped; 0: none
+  int32_t m;          // components of size s_star dropped (smallest roots first)
+};
+
+// cnt[s] += 1 for every component of size s; total = all boundary pixels.
+__global__ __launch_bounds__(kBlock) void k_drop_count(const int32_t* __restrict__ parent,
+                                                       const int32_t* __restrict__ size, int64_t N,
+                                                       unsigned long long* total, int32_t* cnt) {
+  __shared__ unsigned long long part;
+  if (threadIdx.x == 0) part = 0;
+  __syncthreads();
+  unsigned long long mine = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
+    if (parent[i] != (int32_t)i) continue;   // roots only
+    const int32_t s = size[i];
+    mine += (unsigned long long)s;
+    atomicAdd(&cnt[s], 1);
+  }
+  atomicAdd(&part, mine);
+  __syncthreads();
+  if (threadIdx.x == 0) atomicAdd(total, part);
+}
+
+// One block: the budget floor(drop_frac * total) (the rule's comparison in
+// fp64), then a walk over sizes 1..budget in order, a block-wide scan per
+// chunk of 1024 sizes, to the first size that does not fit whole.
+__global__ __launch_bounds__(1024) void k_drop_find(const int32_t* __restrict__ cnt,
+                                                    const unsigned long long* __restrict__ total, double drop_frac,
+                                                    DropRule* rule) {
+  __shared__ unsigned long long sc[1024];
+  __shared__ int done;
+  __shared__ unsigned long long base_s;
+  const unsigned long long t = *total;
+  const long long bud = (long long)floor(drop_frac * (double)t);
+  if (threadIdx.x == 0) {
+    done = 0;
+    base_s = 0;
+    rule->total = (long long)t;
+    rule->budget = bud;
+    rule->s_star = (int32_t)(bud + 1);   // every size <= budget fits: the first size > budget stops the walk
+    rule->m = 0;
+  }
+  __syncthreads();
+  for (long long s0 = 1; s0 <= bud; s0 += 1024) {
+    const long long s = s0 + threadIdx.x;
+    const unsigned long long w = s <= bud ? (unsigned long long)cnt[s] * (unsigned long long)s : 0ull;
+    sc[threadIdx.x] = w;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+      const unsigned long long a = threadIdx.x >= off ? sc[threadIdx.x - off] : 0ull;
+      __syncthreads();
+      sc[threadIdx.x] += a;
+      __syncthreads();
+    }
+    const unsigned long long below = base_s + sc[threadIdx.x] - w;   // pixels of all sizes < s
+    // s is the first size that does not fit whole: below fits, below + w does not
+    if (s <= bud && below + w > (unsigned long long)bud && below <= (unsigned long long)bud) {
+      // exactly one thread can see this (the running total crosses once)
+      rule->s_star = (int32_t)s;
+      rule->m = (int32_t)(((unsigned long long)bud - below) / (unsigned long long)s);
+      done = 1;
+    }
+    __syncthreads();
+    if (done) break;
+    if (threadIdx.x == 1023) base_s += sc[1023];
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Device-wide exclusive scan of 0/1 flags in three launches: per-block
+// counts, a scan of the counts in one block, then per-block prefix and
+// scatter. Flag sources:
+//   kind 0 (roots of size s*):  rank[i] = number of such roots before i
+//   kind 1 (list):              out[pos] = i for border columns and kept pixels
+struct ScanCtx {
+  const uint8_t* B;       // boundary map after refinement
+  const int32_t* parent;  // flattened: root of each boundary pixel, -1 elsewhere
+  const int32_t* size;    // size at roots
+  const DropRule* rule;   // paper filter (nullptr: configured filter)
+  int64_t min_cc;
+  int32_t W;
+  int64_t N;
+  int32_t* rank;          // kind 0 output
+  uint32_t* out;          // kind 1 output
+  uint8_t* refined;       // kind 1 optional output: kept map
+  long long* count;       // kind 1: list length
+};
+
+__device__ __forceinline__ bool kept(const ScanCtx& c, int64_t i) {
+  const int32_t r = c.parent[i];
+  if (r < 0) return false;
+  const int32_t s = c.size[r];
+  if (!c.rule) return s >= c.min_cc;
+  if (s < c.rule->s_star) return false;
+  if (s == c.rule->s_star) return c.rank[r] >= c.rule->m;
+  return true;
+}
+
+template <int KIND>
+__device__ __forceinline__ bool flag(const ScanCtx& c, int64_t i) {
+  if constexpr (KIND == 0) {
+    return c.parent[i] == (int32_t)i && c.size[i] == c.rule->s_star;
+  } else {
+    const int x = (int)(i % c.W);
+    return x == 0 || x == c.W - 1 || kept(c, i);
+  }
+}
+
+template <int KIND>
+__global__ __launch_bounds__(kBlock) void k_scan_count(ScanCtx c, uint32_t* bsum) {
+  __shared__ uint32_t s;
+  if (threadIdx.x == 0) s = 0;
+  __syncthreads();
+  const int64_t i0 = (int64_t)blockIdx.x * kScanPer;
+  uint32_t m = 0;
+  for (int j = threadIdx.x; j < kScanPer; j += kBlock) {
+    const int64_t i = i0 + j;
+    if (i < c.N && flag<KIND>(c, i)) ++m;
+  }
+  atomicAdd(&s, m);
+  __syncthreads();
+  if (threadIdx.x == 0) bsum[blockIdx.x] = s;
+}
+
+// exclusive scan of nb block counts in place (one block of 1024 threads)
+__global__ __launch_bounds__(1024) void k_scan_top(uint32_t* bsum, int64_t nb, long long* total) {
+  __shared__ uint32_t sc[1024];
+  __shared__ uint32_t base;
+  if (threadIdx.x == 0) base = 0;
+  __syncthreads();
+  for (int64_t b0 = 0; b0 < nb; b0 += 1024) {
+    const int64_t b = b0 + threadIdx.x;
+    const uint32_t v = b < nb ? bsum[b] : 0u;
+    sc[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+      const uint32_t a = threadIdx.x >= off ? sc[threadIdx.x - off] : 0u;
+      __syncthreads();
+      sc[threadIdx.x] += a;
+      __syncthreads();
+    }
+    if (b < nb) bsum[b] = base + sc[threadIdx.x] - v;
+    __syncthreads();
+    if (threadIdx.x == 1023) base += sc[1023];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && total) *total = (long long)base;
+}
+
+template <int KIND>
+__global__ __launch_bounds__(kBlock) void k_scan_apply(ScanCtx c, const uint32_t* bsum) {
+  // thread t owns elements i0 + 4t .. i0 + 4t + 3 (in order)
+  __shared__ uint32_t sc[kBlock];
+  const int64_t i0 = (int64_t)blockIdx.x * kScanPer;
+  constexpr int per = kScanPer / kBlock;
+  bool f[per];
+  uint32_t m = 0;
+#pragma unroll
+  for (int j = 0; j < per; ++j) {
+    const int64_t i = i0 + (int64_t)threadIdx.x * per + j;
+    f[j] = i < c.N && flag<KIND>(c, i);
+    m += f[j];
+  }
+  sc[threadIdx.x] = m;
+  __syncthreads();
+  for (int off = 1; off < kBlock; off <<= 1) {
+    const uint32_t a = threadIdx.x >= off ? sc[threadIdx.x - off] : 0u;
+    __syncthreads();
+    sc[threadIdx.x] += a;
+    __syncthreads();
+  }
+  uint32_t pos = bsum[blockIdx.x] + sc[threadIdx.x] - m;
+#pragma unroll
+  for (int j = 0; j < per; ++j) {
+    const int64_t i = i0 + (int64_t)threadIdx.x * per + j;
+    if (i >= c.N) break;
+    if constexpr (KIND == 0) {
+      if (f[j]) c.rank[i] = (int32_t)pos;
+    } else {
+      if (f[j]) c.out[pos] = (uint32_t)i;
+      if (c.refined) c.refined[i] = kept(c, i) ? 1 : 0;
+    }
+    pos += f[j];
+  }
+}
+
+int fail(int st, const char* fmt, ...) {
+  char buf[256];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  return sbs::report_error(st, buf);
+}
+
+size_t a256(size_t v) { return (v + 255) / 256 * 256; }
+
+struct Layout {
+  size_t L8, lab, lab2, B, B2, parent, size, cnt, bsum, hist, lut, misc, end;
+};
+
+Layout layout(int64_t N) {
+  Layout o{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) { const size_t at = off; off += a256(bytes); return at; };
+  o.L8 = take(N);
+  o.lab = take(N);
+  o.lab2 = take(N);
+  o.B = take(N);
+  o.B2 = take(N);
+  o.parent = take((size_t)N * 4);
+  o.size = take((size_t)N * 4);
+  o.cnt = take(((size_t)N + 1) * 4);
+  o.bsum = take(((size_t)(N + kScanPer - 1) / kScanPer + 1) * 4);
+  o.hist = take(256 * 8);
+  o.lut = take(256);
+  o.misc = take(1024);
+  o.end = off;
+  return o;
+}
+
+int grid_for(int64_t n) {
+  const int64_t g = (n + kBlock - 1) / kBlock;
+  return (int)(g < 1 ? 1 : (g > 8192 ? 8192 : g));
+}
+
+}  // namespace sbs_front
+
+using namespace sbs_front;
+
+extern "C" {
+
+int sbs_lightness(const uint8_t* img, int32_t W, int32_t H, int32_t C, int64_t pitch, uint8_t* out_l8, void* stream) {
+  if (W < 1 || H < 1 || (int64_t)W * H > INT32_MAX || (C != 1 && C != 3) || pitch < (int64_t)W * C)
+    return fail(SBS_ERR_INVALID_ARG, "bad image geometry");
+  if (!img || !out_l8) return fail(SBS_ERR_INVALID_ARG, "NULL pointer");
+  hipStream_t s = (hipStream_t)stream;
+  hipLaunchKernelGGL(k_light, dim3(grid_for((int64_t)W * H)), dim3(kBlock), 0, s, img, W, H, C, pitch, out_l8);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(SBS_ERR_HIP, "lightness: %s", hipGetErrorString(e));
+  return SBS_OK;
+}
+
+size_t sbs_boundaries_workspace_bytes(int32_t W, int32_t H) {
+  if (W < 1 || H < 1 || (int64_t)W * H > INT32_MAX) return 0;
+  return layout((int64_t)W * H).end;
+}
+
+int sbs_boundaries(const uint8_t* img, int32_t W, int32_t H, int32_t C, int64_t pitch, int32_t K, int32_t mode,
+                   int32_t min_cc, uint32_t* out_idx, int64_t* out_count, uint8_t* out_refined, uint8_t* out_labels,
+                   void* workspace, size_t workspace_bytes, void* stream) {
+  if (W < 1 || H < 1 || (int64_t)W * H > INT32_MAX || (C != 1 && C != 3) || pitch < (int64_t)W * C)
+    return fail(SBS_ERR_INVALID_ARG, "bad image geometry");
+  if (!img || !out_idx || !out_count || !workspace) return fail(SBS_ERR_INVALID_ARG, "NULL pointer");
+  if (K < 1 || K > kMaxK) return fail(SBS_ERR_INVALID_ARG, "K must be in [1, %d]", kMaxK);
+  if (mode != 0 && mode != 1) return fail(SBS_ERR_INVALID_ARG, "mode must be 0 (configured) or 1 (paper)");
+  if (mode == 0 && min_cc < 0) return fail(SBS_ERR_INVALID_ARG, "min_cc < 0");
+  if (H > 4 * 65535) return fail(SBS_ERR_UNSUPPORTED, "H > %d", 4 * 65535);   // 2-D stencil grid: 4 rows per block
+  const int64_t N = (int64_t)W * H;
+  const Layout Lo = layout(N);
+  if (workspace_bytes < Lo.end) return fail(SBS_ERR_INVALID_ARG, "workspace too small");
+  hipStream_t s = (hipStream_t)stream;
+  char* base = (char*)workspace;
+  uint8_t* L8 = (uint8_t*)(base + Lo.L8);
+  uint8_t* lab = (uint8_t*)(base + Lo.lab);
+  uint8_t* lab2 = (uint8_t*)(base + Lo.lab2);
+  uint8_t* B = (uint8_t*)(base + Lo.B);
+  uint8_t* B2 = (uint8_t*)(base + Lo.B2);
+  int32_t* parent = (int32_t*)(base + Lo.parent);
+  int32_t* size = (int32_t*)(base + Lo.size);
+  int32_t* cnt = (int32_t*)(base + Lo.cnt);
+  uint32_t* bsum = (uint32_t*)(base + Lo.bsum);
+  unsigned long long* hist = (unsigned long long*)(base + Lo.hist);
+  uint8_t* lut = (uint8_t*)(base + Lo.lut);
+  char* misc = base + Lo.misc;
+  int32_t* passes = (int32_t*)misc;
+  unsigned long long* total = (unsigned long long*)(misc + 128);
+  DropRule* rule = (DropRule*)(misc + 192);
+  const int g = grid_for(N);
+  const dim3 g2((W + 63) / 64, (H + 3) / 4);
+
+  // Clear the small counters with kernels (no memset nodes if the caller captures the stream).
+  hipLaunchKernelGGL(k_fill, dim3(1), dim3(kBlock), 0, s, (uint8_t*)hist, (int64_t)(256 * 8), (uint8_t)0);
+  hipLaunchKernelGGL(k_fill, dim3(1), dim3(kBlock), 0, s, (uint8_t*)misc, (int64_t)1024, (uint8_t)0);
+  hipLaunchKernelGGL(k_light, dim3(g), dim3(kBlock), 0, s, img, W, H, C, pitch, L8);
+  hipLaunchKernelGGL(k_hist, dim3(g), dim3(kBlock), 0, s, L8, N, hist);
+  hipLaunchKernelGGL(k_kmeans, dim3(1), dim3(256), 0, s, hist, K, lut, passes);
+  hipLaunchKernelGGL(k_label, dim3(g), dim3(kBlock), 0, s, L8, N, lut, lab);
+  const uint8_t* labels = lab;
+  if (mode == 0) {
+    hipLaunchKernelGGL(k_stencil<0>, g2, dim3(kBlock), 0, s, lab, W, H, lab2);   // erode
+    hipLaunchKernelGGL(k_stencil<1>, g2, dim3(kBlock), 0, s, lab2, W, H, lab);   // dilate: open
+    hipLaunchKernelGGL(k_stencil<1>, g2, dim3(kBlock), 0, s, lab, W, H, lab2);   // dilate
+    hipLaunchKernelGGL(k_stencil<0>, g2, dim3(kBlock), 0, s, lab2, W, H, lab);   // erode: close
+    hipLaunchKernelGGL(k_stencil<2>, g2, dim3(kBlock), 0, s, lab, W, H, B);      // boundary
+  } else {
+    hipLaunchKernelGGL(k_stencil<2>, g2, dim3(kBlock), 0, s, lab, W, H, B2);     // boundary
+    hipLaunchKernelGGL(k_stencil<3>, g2, dim3(kBlock), 0, s, B2, W, H, B);       // fill
+    hipLaunchKernelGGL(k_stencil<4>, g2, dim3(kBlock), 0, s, B, W, H, B2);       // remove
+    B = B2;
+  }
+  if (out_labels) {
+    const hipError_t ce = hipMemcpyAsync(out_labels, labels, (size_t)N, hipMemcpyDeviceToDevice, s);
+    if (ce != hipSuccess) return fail(SBS_ERR_HIP, "boundaries: %s", hipGetErrorString(ce));
+  }
+  hipLaunchKernelGGL(k_cc_init, dim3(g), dim3(kBlock), 0, s, B, N, parent, size);
+  hipLaunchKernelGGL(k_cc_merge, g2, dim3(kBlock), 0, s, B, W, H, parent);
+  hipLaunchKernelGGL(k_cc_flatten, dim3(g), dim3(kBlock), 0, s, N, parent, size);
+
+  const int64_t nb = (N + kScanPer - 1) / kScanPer;
+  ScanCtx c{};
+  c.B = B; c.parent = parent; c.size = size; c.rule = nullptr; c.min_cc = min_cc; c.W = W; c.N = N;
+  c.rank = cnt;   // the rank array reuses cnt: ranks are written after k_drop_find has read the counts
+  c.out = out_idx; c.refined = out_refined; c.count = (long long*)out_count;
+  if (mode == 1) {
+    hipLaunchKernelGGL(k_fill, dim3(g), dim3(kBlock), 0, s, (uint8_t*)cnt, (int64_t)(N + 1) * 4, (uint8_t)0);
+    hipLaunchKernelGGL(k_drop_count, dim3(g), dim3(kBlock), 0, s, parent, size, N, total, cnt);
+    hipLaunchKernelGGL(k_drop_find, dim3(1), dim3(1024), 0, s, cnt, total, 0.04, rule);
+    c.rule = rule;
+    // rank of each root of size s* among those roots, in raster order
+    hipLaunchKernelGGL(k_scan_count<0>, dim3((unsigned)nb), dim3(kBlock), 0, s, c, bsum);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, bsum, nb, (long long*)nullptr);
+    hipLaunchKernelGGL(k_scan_apply<0>, dim3((unsigned)nb), dim3(kBlock), 0, s, c, bsum);
+  }
+  hipLaunchKernelGGL(k_scan_count<1>, dim3((unsigned)nb), dim3(kBlock), 0, s, c, bsum);
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, bsum, nb, (long long*)out_count);
+  hipLaunchKernelGGL(k_scan_apply<1>, dim3((unsigned)nb), dim3(kBlock), 0, s, c, bsum);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(SBS_ERR_HIP, "boundaries: %s", hipGetErrorString(e));
+  return SBS_OK;
+}
+
+}  // extern "C"

@@ -245,8 +245,12 @@ typedef __attribute__((address_space(3))) u32x4 lds_u32x4;
 
 // The pixels one lane needs from one padded row: its four left columns, and
 // the DC + 4 right columns that pair with them over the chunk (right index
-// c + DC - k pairs with left column c at disparity d0 + k; index 0 is loaded
-// only to keep the loads 16-byte aligned).
+// c + DC - k pairs with left column c at disparity d0 + k; index 0 is never
+// used). The right columns of lane l are the 4-word blocks l .. l + DC/4 of
+// the wave's span; lane l loads only block l + DC/4 and takes the lower
+// blocks from lanes l - 1, l - 2, ... with DPP wave shifts, while lane 0
+// loads the blocks below the span itself (spread_row). That halves the
+// load traffic for DC = 8.
 template <int DC>
 struct RowRegs {
   uint32_t L[4];
@@ -258,11 +262,35 @@ __device__ __forceinline__ void load_row(const uint32_t* lrow, const uint32_t* r
   // lrow, rrow: the wave's row bases (uniform); lo: this lane's word offset
   const u32x4 lv = *(g_uint4*)(lrow + lo);
   o.L[0] = lv.x; o.L[1] = lv.y; o.L[2] = lv.z; o.L[3] = lv.w;
+  const u32x4 t = *(g_uint4*)(rrow + lo + DC);
+  o.R[DC] = t.x; o.R[DC + 1] = t.y; o.R[DC + 2] = t.z; o.R[DC + 3] = t.w;
 #pragma unroll
-  for (int q = 0; q < DC / 4 + 1; ++q) {
-    const u32x4 t = *(g_uint4*)(rrow + lo + 4 * q);
-    o.R[4 * q + 0] = t.x; o.R[4 * q + 1] = t.y; o.R[4 * q + 2] = t.z; o.R[4 * q + 3] = t.w;
+  for (int q = 0; q < DC / 4; ++q) {
+    o.R[4 * q + 0] = __builtin_nondeterministic_value(0u);
+    o.R[4 * q + 1] = __builtin_nondeterministic_value(0u);
+    o.R[4 * q + 2] = __builtin_nondeterministic_value(0u);
+    o.R[4 * q + 3] = __builtin_nondeterministic_value(0u);
   }
+  if (lo == 0) {
+#pragma unroll
+    for (int q = 0; q < DC / 4; ++q) {
+      const u32x4 b = *(g_uint4*)(rrow + 4 * q);
+      o.R[4 * q + 0] = b.x; o.R[4 * q + 1] = b.y; o.R[4 * q + 2] = b.z; o.R[4 * q + 3] = b.w;
+    }
+  }
+}
+
+// Completes the right columns once the loads of load_row have arrived: block
+// q of lane l is block q + 1 of lane l - 1 (DPP wave_shr:1; lane 0 keeps its
+// own load).
+template <int DC>
+__device__ __forceinline__ void spread_row(RowRegs<DC>& o) {
+#pragma unroll
+  for (int q = DC / 4 - 1; q >= 0; --q)
+#pragma unroll
+    for (int w = (q == 0 ? 1 : 0); w < 4; ++w)
+      o.R[4 * q + w] = (uint32_t)__builtin_amdgcn_update_dpp((int)o.R[4 * q + w], (int)o.R[4 * q + 4 + w], 0x138, 0xf, 0xf,
+                                                             false);
 }
 
 // Accumulators per lane: kPack == false keeps one 32-bit sum per (column,
@@ -282,7 +310,8 @@ struct Acc {
 
 // Adds one padded row to the accumulators.
 template <int DC, bool kPack>
-__device__ __forceinline__ void add_row(const RowRegs<DC>& a, Acc<DC, kPack>& acc) {
+__device__ __forceinline__ void add_row(RowRegs<DC>& a, Acc<DC, kPack>& acc) {
+  spread_row<DC>(a);
 #pragma unroll
   for (int c = 0; c < kColsPerLane; ++c)
 #pragma unroll
@@ -298,7 +327,9 @@ __device__ __forceinline__ void add_row(const RowRegs<DC>& a, Acc<DC, kPack>& ac
 // Moves the window down one row: padded row `ex` leaves, `en` enters. The
 // leaving row is taken off first, so no partial sum exceeds a full window.
 template <int DC, bool kPack>
-__device__ __forceinline__ void slide_row(const RowRegs<DC>& en, const RowRegs<DC>& ex, Acc<DC, kPack>& acc) {
+__device__ __forceinline__ void slide_row(RowRegs<DC>& en, RowRegs<DC>& ex, Acc<DC, kPack>& acc) {
+  spread_row<DC>(en);
+  spread_row<DC>(ex);
 #pragma unroll
   for (int c = 0; c < kColsPerLane; ++c)
 #pragma unroll
@@ -550,7 +581,6 @@ __device__ __forceinline__ void tile_item_impl(const FrameDev& f, int tile, int 
   entries_row(yb);
 }
 
-// Ordered and unordered lists take separate instances (fewer live registers in each).
 // Ordered and unordered lists, packed and 32-bit accumulators take separate
 // instances (fewer live registers in each).
 template <int DC>

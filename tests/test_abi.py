@@ -68,3 +68,25 @@ def test_injected_launch_failure_reported(monkeypatch):
     assert "injected" in sbs.lib().sbs_last_error().decode()
     monkeypatch.delenv("SBS_TEST_FAIL")
     assert _call(W=0) == 1
+
+
+def _front(W=16, H=8, C=3, pitch=None, K=4, mode=0, min_cc=50, ptr=1, ws=None):
+    lib = sbs.lib()
+    p = ctypes.c_void_p(ptr) if ptr else None
+    need = lib.sbs_boundaries_workspace_bytes(W, H)
+    return lib.sbs_boundaries(p, W, H, C, W * C if pitch is None else pitch, K, mode, min_cc, p, p, None, None, p,
+                              need if ws is None else ws, None)
+
+
+@pytest.mark.parametrize("kw", [dict(W=0), dict(H=0), dict(C=2), dict(pitch=10), dict(K=0), dict(K=65),
+                                dict(mode=2), dict(min_cc=-1), dict(ptr=0), dict(ws=16)])
+def test_front_end_invalid_arguments_rejected_on_host(kw):
+    assert _front(**kw) == 1
+    assert sbs.lib().sbs_last_error().decode() != ""
+
+
+def test_front_end_workspace_bytes():
+    lib = sbs.lib()
+    assert lib.sbs_boundaries_workspace_bytes(0, 5) == 0
+    assert lib.sbs_boundaries_workspace_bytes(100, 50) >= 100 * 50 * 13
+    assert lib.sbs_lightness(None, 4, 4, 3, 12, None, None) == 1
