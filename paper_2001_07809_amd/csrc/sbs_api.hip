@@ -112,18 +112,32 @@ std::string plan_key(const sbs_frame& f) {
   return o.str();
 }
 
-Plan default_plan(const sbs_frame& f) {
+// Default plan. items16 = work items of one launch with 16-disparity chunks;
+// 16-disparity chunks (half the key updates, row loads and warm-up rows per
+// disparity) once a launch holds at least four such items per wavefront slot
+// of the chip, 8-disparity chunks (twice the items) below that.
+Plan default_plan(const sbs_frame& f, int64_t items16) {
   Plan p;
-  p.chunk = 8;
+  p.chunk = items16 >= 4LL * 256 * 16 ? 16 : 8;
   p.ty = f.H >= 1024 ? 128 : 64;   // tall frames: spread each tile's window warm-up over more rows
   p.wpc = 16;
   return p;
 }
 
-Plan choose_plan(const sbs_frame& f) {
+// Work items of frame f with 16-disparity chunks and the default tile shape.
+int64_t items16_of(const sbs_frame& f) {
+  if (f.n <= 0) return 0;
+  const int r = (f.block - 1) / 2;
+  const int lpad = (r + 3) & ~3;
+  const int txo = (kSpan - lpad - r) & ~3;
+  const int ty = f.H >= 1024 ? 128 : 64;
+  return (int64_t)((f.W + txo - 1) / txo) * ((f.H + ty - 1) / ty) * ((f.dmax + 16) / 16);
+}
+
+Plan choose_plan(const sbs_frame& f, int64_t items16) {
   std::lock_guard<std::mutex> lk(g_mu);
   if (g_forced) {
-    Plan p = default_plan(f);
+    Plan p = default_plan(f, items16);
     if (g_forced_plan.cpl) p.cpl = g_forced_plan.cpl;
     if (g_forced_plan.chunk) p.chunk = g_forced_plan.chunk;
     if (g_forced_plan.ty) p.ty = g_forced_plan.ty;
@@ -132,7 +146,7 @@ Plan choose_plan(const sbs_frame& f) {
   }
   auto it = g_tuned.find(plan_key(f));
   if (it != g_tuned.end()) return it->second;
-  return default_plan(f);
+  return default_plan(f, items16);
 }
 
 // ---------------------------------------------------------------- validation + layout
@@ -288,7 +302,13 @@ int run(const sbs_frame* frames, int nframes, void* workspace, size_t ws_bytes, 
   // One plan per call (from the first frame with work): the persistent kernel is one instance.
   int lead = 0;
   while (lead < nframes && frames[lead].n == 0) ++lead;
-  const Plan plan = choose_plan(frames[lead]);
+  // Items of one launch: all frames for the batched kernel, one frame otherwise.
+  int64_t items16 = 0;
+  if (mode == kBatched)
+    for (int i = 0; i < nframes; ++i) items16 += items16_of(frames[i]);
+  else if (lead < nframes)
+    items16 = items16_of(frames[lead]);
+  const Plan plan = choose_plan(frames[lead], items16);
 
   std::vector<FrameDev> host((size_t)nframes);
   size_t off = kHeaderBytes + table_bytes(nframes);
@@ -554,7 +574,7 @@ int sbs_get_plan(const sbs_frame* frame, sbs_plan* plan) {
   if (!frame || !plan) return fail(SBS_ERR_INVALID_ARG, "NULL argument");
   int st = validate(*frame, 0);
   if (st != SBS_OK) return st;
-  Plan p = choose_plan(*frame);
+  Plan p = choose_plan(*frame, items16_of(*frame));   // as a single-frame call would plan it
   plan->cols_per_lane = p.cpl;
   plan->chunk = p.chunk;
   plan->tile_rows = p.ty;

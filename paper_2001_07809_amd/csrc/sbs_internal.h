@@ -9,7 +9,8 @@ namespace sbs {
 constexpr int kWave = 64;
 constexpr int kColsPerLane = 4;            // CAD columns owned by one lane
 constexpr int kSpan = kWave * kColsPerLane;  // CAD columns per tile (256)
-constexpr int kMaxChunk = 16;              // largest disparity chunk a kernel instance handles
+constexpr int kMaxChunk = 16;         // largest disparity chunk a kernel instance handles
+constexpr int kGroup = 8;             // disparities whose prefix sums share the LDS at once
 constexpr int kDescPerLaunch = 8;          // descriptors carried by one upload kernel
 constexpr uint32_t kUnsorted = 1u;         // FrameDev::state bit
 constexpr int kQueues = 8;                 // one work queue per XCD; tile t's items go to queue t % 8

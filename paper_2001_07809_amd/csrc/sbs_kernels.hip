@@ -49,6 +49,8 @@ __device__ __forceinline__ uint32_t load_px(const uint8_t* row, int x, int C) {
 // compiler emit global_load instead of flat_load).
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(1))) const u32x4 g_uint4;
+typedef unsigned int u32x3 __attribute__((ext_vector_type(3)));
+typedef __attribute__((address_space(1))) const u32x3 g_uint3;
 typedef __attribute__((address_space(1))) const int32_t g_int32;
 typedef __attribute__((address_space(1))) const uint32_t g_uint32;
 typedef __attribute__((address_space(1))) const uint64_t g_uint64;
@@ -234,11 +236,15 @@ __device__ __forceinline__ void pin_step(uint32_t (&v)[kColsPerLane][N]) {
 // unordered lists, the current row's listed pixels. pre[k][4 + j] is the
 // inclusive prefix sum over window columns 0..j; pre[k][0..3] stay zero, so a
 // window that starts at column 0 needs no special case.
-template <int DC>
 struct TileLds {
-  uint32_t pre[DC][kSpan + 4] __attribute__((aligned(16)));
-  int16_t eo[kSpan];           // unordered lists: listed pixels of the row (output column offset)
-  int32_t es[kSpan];           //                  and their representative slots
+  uint32_t pre[kGroup][kSpan + 4] __attribute__((aligned(16)));   // one group of 8 disparities at a time
+  union {
+    struct {
+      int16_t eo[kSpan];       // unordered lists: listed pixels of the row (output column offset)
+      int32_t es[kSpan];       //                  and their representative slots
+    };
+    uint32_t tp[128];          // ordered lists: list range of each row of the tile, packed
+  };
 };
 
 typedef __attribute__((address_space(3))) u32x4 lds_u32x4;
@@ -264,16 +270,20 @@ __device__ __forceinline__ void load_row(const uint32_t* lrow, const uint32_t* r
   o.L[0] = lv.x; o.L[1] = lv.y; o.L[2] = lv.z; o.L[3] = lv.w;
   const u32x4 t = *(g_uint4*)(rrow + lo + DC);
   o.R[DC] = t.x; o.R[DC + 1] = t.y; o.R[DC + 2] = t.z; o.R[DC + 3] = t.w;
+  o.R[0] = 0u;   // never used
 #pragma unroll
   for (int q = 0; q < DC / 4; ++q) {
-    o.R[4 * q + 0] = __builtin_nondeterministic_value(0u);
+    if (q > 0) o.R[4 * q + 0] = __builtin_nondeterministic_value(0u);
     o.R[4 * q + 1] = __builtin_nondeterministic_value(0u);
     o.R[4 * q + 2] = __builtin_nondeterministic_value(0u);
     o.R[4 * q + 3] = __builtin_nondeterministic_value(0u);
   }
   if (lo == 0) {
+    // block 0 without its unused first word
+    const u32x3 b0 = *(g_uint3*)(rrow + 1);
+    o.R[1] = b0.x; o.R[2] = b0.y; o.R[3] = b0.z;
 #pragma unroll
-    for (int q = 0; q < DC / 4; ++q) {
+    for (int q = 1; q < DC / 4; ++q) {
       const u32x4 b = *(g_uint4*)(rrow + 4 * q);
       o.R[4 * q + 0] = b.x; o.R[4 * q + 1] = b.y; o.R[4 * q + 2] = b.z; o.R[4 * q + 3] = b.w;
     }
@@ -350,7 +360,7 @@ __device__ __forceinline__ void slide_row(RowRegs<DC>& en, RowRegs<DC>& ex, Acc<
 // One work item: tile `tile` (row-major over the frame's ntx x nty tiles),
 // disparity chunk `chunk` (disparities chunk*DC .. +DC-1).
 template <int DC, bool kSorted, bool kPack>
-__device__ __forceinline__ void tile_item_impl(const FrameDev& f, int tile, int chunk, TileLds<DC>& sm) {
+__device__ __forceinline__ void tile_item_impl(const FrameDev& f, int tile, int chunk, TileLds& sm) {
   const int lane = threadIdx.x;
   const int tx = tile % f.ntx, tyi = tile / f.ntx;
   const int W = f.W, H = f.H, r = f.r;
@@ -364,7 +374,11 @@ __device__ __forceinline__ void tile_item_impl(const FrameDev& f, int tile, int 
   // Rows of this tile (up to 128, two 64-bit masks) holding a listed pixel
   // in [x0, x1). For ordered lists lane l keeps the list ranges of rows
   // y0 + l and y0 + 64 + l in registers.
-  int tpa0 = 0, tpa1 = 0, tpb0 = 0, tpb1 = 0;
+  // Ordered lists: lane l keeps the list range of rows y0 + l and y0 + 64 + l
+  // packed as (first - tbase) << 8 | count, tbase being the first list slot
+  // of the tile's first row (count <= txo < 256; first - tbase < ty * W <= 2^24).
+  const int tbase = kSorted ? f.tptr[(int64_t)y0 * f.tpw + tx] : 0;
+  uint32_t tpa = 0, tpb = 0;
   auto row_active = [&](int y, int& t0, int& t1) -> bool {
     if (y >= y1) return false;
     if (sorted) {
@@ -383,8 +397,21 @@ __device__ __forceinline__ void tile_item_impl(const FrameDev& f, int tile, int 
     }
     return a;
   };
-  const bool acta = lane < f.ty && row_active(y0 + lane, tpa0, tpa1);
-  const bool actb = lane + 64 < f.ty && row_active(y0 + 64 + lane, tpb0, tpb1);
+  int ta0 = 0, ta1 = 0, tb0 = 0, tb1 = 0;
+  const bool acta = lane < f.ty && row_active(y0 + lane, ta0, ta1);
+  const bool actb = lane + 64 < f.ty && row_active(y0 + 64 + lane, tb0, tb1);
+  if constexpr (kSorted) {
+    tpa = (uint32_t)(ta0 - tbase) << 8 | (uint32_t)(ta1 - ta0);
+    tpb = (uint32_t)(tb0 - tbase) << 8 | (uint32_t)(tb1 - tb0);
+    sm.tp[lane] = tpa;
+    sm.tp[64 + lane] = tpb;
+  }
+  // list range [first, first + count) of row y (uniform), from LDS
+  auto row_range = [&](int y, int& first, int& count) {
+    const uint32_t v = __builtin_amdgcn_readfirstlane(sm.tp[y - y0]);
+    first = tbase + (int)(v >> 8);
+    count = (int)(v & 0xFFu);
+  };
   const uint64_t rows_a = __builtin_amdgcn_ballot_w64(acta);
   const uint64_t rows_b = __builtin_amdgcn_ballot_w64(actb);
   if ((rows_a | rows_b) == 0) return;
@@ -430,6 +457,33 @@ __device__ __forceinline__ void tile_item_impl(const FrameDev& f, int tile, int 
 #pragma unroll
     for (int j = 0; j < Acc<DC, kPack>::N; ++j) acc.v[c][j] = 0;
 
+  int e0 = 0, cnt = 0;
+  uint32_t pf_cur = 0, pf_next = 0;        // ordered lists: first 64 list entries of the row
+  int32_t mv[kColsPerLane];                // unordered lists: pixel map of the next active row
+  const uint32_t mlo = kColsPerLane * (uint32_t)lane;   // this lane's first window column
+  // Deferred key update of the previous active row: lane l < pend_cnt
+  // holds the best of entry pend_e0 + l (ordered lists) or of slot
+  // pend_slot (unordered lists).
+  uint32_t pend_best = 0xFFFFFFFFu;
+  int pend_e0 = 0, pend_cnt = 0;
+  int32_t pend_slot = -1;
+  auto load_next = [&](int y) {            // list data of active row y (y < 0: none)
+    if (y < 0) return;
+    if constexpr (kSorted) {
+      int t0, n0;
+      row_range(y, t0, n0);
+      if ((int)lane < n0) pf_next = *(g_uint32*)(f.idx + t0 + lane);
+    } else {
+      const int32_t* mrow = f.map + (int64_t)y * W + x0 - lpad;   // window column j -> image column x0 - lpad + j
+#pragma unroll
+      for (int c = 0; c < kColsPerLane; ++c) {
+        const int o = (int)mlo + c - lpad;
+        mv[c] = (o >= 0 && x0 + o < x1) ? *(g_int32*)(mrow + mlo + c) : -1;
+      }
+    }
+  };
+  load_next(ya);   // in flight during the warm-up
+
   // Window of output row ya: padded rows ya .. ya + 2r (an odd count), in
   // pairs with the next row's loads in flight, then the last row.
   {
@@ -445,66 +499,47 @@ __device__ __forceinline__ void tile_item_impl(const FrameDev& f, int tile, int 
     add_row<DC, kPack>(A, acc);
   }
 
-  // Each active row y takes three steps around the vertical update of the
-  // main loop:
-  //   prefix_row(y)  the window's prefix sums for the chunk's disparities to LDS;
-  //   (vertical update y -> y + 1: the one point where the wave waits for its
-  //    loads, issued one row earlier)
+  // Row step y (y > ya first moves the window down from y - 1):
+  //   slide          the vertical update: the one point where the wave waits
+  //                  for memory, for the loads issued one step earlier;
+  //   key update     of the previous active row, deferred to here so that it
+  //                  is a full step old at the next wait;
   //   take_row(y)    the row's listed pixels from what that wait delivered,
   //                  then the loads for the next step and the next active row;
-  //   entries_row(y) window sums of the row's listed pixels as differences of
-  //                  two prefix entries, folded into their keys.
-  // Loaded values are only used after the wait of the vertical update, so no
-  // other step waits for memory and the key updates, the last memory
-  // operations of a row, are not waited for until the next row's update.
-  int e0 = 0, cnt = 0;
-  uint32_t pf_cur = 0, pf_next = 0;        // ordered lists: first 64 list entries of the row
-  int32_t mv[kColsPerLane];                // unordered lists: pixel map of the next active row
-  const uint32_t mlo = kColsPerLane * (uint32_t)lane;   // this lane's first window column
-  auto load_next = [&](int y) {            // list data of active row y (y < 0: none)
-    if (y < 0) return;
-    if constexpr (kSorted) {
-      const int i = y - y0;
-      const int t0 = i < 64 ? __builtin_amdgcn_readlane(tpa0, i) : __builtin_amdgcn_readlane(tpb0, i - 64);
-      const int t1 = i < 64 ? __builtin_amdgcn_readlane(tpa1, i) : __builtin_amdgcn_readlane(tpb1, i - 64);
-      if ((int)lane < t1 - t0) pf_next = *(g_uint32*)(f.idx + t0 + lane);
-    } else {
-      const int32_t* mrow = f.map + (int64_t)y * W + x0 - lpad;   // window column j -> image column x0 - lpad + j
+  //   per group of 8 disparities: prefix sums of the window to LDS, then the
+  //                  window sums of the row's listed pixels as differences of
+  //                  two prefix entries, folded into a running best.
+  // Loaded values are only used after the wait of the slide, and the only
+  // memory operations issued after the loads are rare (rows with more than
+  // 64 listed pixels in the tile).
+  // prefix sums of disparities d0 + g .. d0 + g + 7 to LDS
+  auto prefix_group = [&](int g) {
 #pragma unroll
-      for (int c = 0; c < kColsPerLane; ++c) {
-        const int o = (int)mlo + c - lpad;
-        mv[c] = (o >= 0 && x0 + o < x1) ? *(g_int32*)(mrow + mlo + c) : -1;
-      }
-    }
-  };
-  auto prefix_row = [&]() {
+    for (int k0 = 0; k0 < kGroup; k0 += 4) {
+      // t: the lane's column total, then (after the wave scan) the prefix at
+      // its last column; the three columns before follow by subtraction, so
+      // no in-lane prefixes stay live across the scan.
+      uint32_t t[4];
 #pragma unroll
-    for (int k0 = 0; k0 < DC; k0 += 4) {
-      uint32_t q[4][4], t[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        q[i][0] = acc.get(0, k0 + i);
-        q[i][1] = q[i][0] + acc.get(1, k0 + i);
-        q[i][2] = q[i][1] + acc.get(2, k0 + i);
-        q[i][3] = q[i][2] + acc.get(3, k0 + i);
-        t[i] = q[i][3];
-      }
+      for (int i = 0; i < 4; ++i)
+        t[i] = acc.get(0, g + k0 + i) + acc.get(1, g + k0 + i) + acc.get(2, g + k0 + i) + acc.get(3, g + k0 + i);
       wave_incl_scan4(t[0], t[1], t[2], t[3]);
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const uint32_t excl = t[i] - q[i][3];
         u32x4 o;
-        o.x = excl + q[i][0]; o.y = excl + q[i][1]; o.z = excl + q[i][2]; o.w = excl + q[i][3];
+        o.w = t[i];
+        o.z = o.w - acc.get(3, g + k0 + i);
+        o.y = o.z - acc.get(2, g + k0 + i);
+        o.x = o.y - acc.get(1, g + k0 + i);
         *(lds_u32x4*)&sm.pre[k0 + i][4 + kColsPerLane * lane] = o;
       }
     }
+    __syncthreads();
   };
   auto take_row = [&](int y) {
     cnt = 0;
     if constexpr (kSorted) {
-      const int i = y - y0;
-      e0 = i < 64 ? __builtin_amdgcn_readlane(tpa0, i) : __builtin_amdgcn_readlane(tpb0, i - 64);
-      cnt = (i < 64 ? __builtin_amdgcn_readlane(tpa1, i) : __builtin_amdgcn_readlane(tpb1, i - 64)) - e0;
+      row_range(y, e0, cnt);
       pf_cur = pf_next;
     } else {
 #pragma unroll
@@ -520,30 +555,54 @@ __device__ __forceinline__ void tile_item_impl(const FrameDev& f, int tile, int 
       }
     }
   };
-  // Window sums of one listed pixel at output offset o (0 <= o < txo; window
-  // columns o + lpad - r .. o + lpad + r), folded into key `slot`.
-  auto entry = [&](int o, int slot) {
+  // Best (cost << 8 | d) over group g of the listed pixel at output offset o
+  // (0 <= o < txo; window columns o + lpad - r .. o + lpad + r).
+  auto group_best = [&](int g, int o, uint32_t best) -> uint32_t {
     const int ih = 4 + o + lpad + r, il = 3 + o + lpad - r;
-    uint32_t best = 0xFFFFFFFFu;
 #pragma unroll
-    for (int k = 0; k < DC; ++k) {
+    for (int k = 0; k < kGroup; ++k) {
       const uint32_t s = sm.pre[k][ih] - sm.pre[k][il];
-      best = min(best, ((s << 8) | (uint32_t)(d0 + k)) | kill[k]);
+      best = min(best, ((s << 8) | (uint32_t)(d0 + g + k)) | kill[g + k]);
     }
-    // a global (not flat) atomic: it counts only against the vector-memory counter
-    __hip_atomic_fetch_min((g_uint32_rw*)(f.keys + slot), best, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return best;
+  };
+  // a global (not flat) atomic: it counts only against the vector-memory counter
+  auto key_min = [&](int32_t slot, uint32_t v) {
+    __hip_atomic_fetch_min((g_uint32_rw*)(f.keys + slot), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  };
+  auto flush = [&]() {
+    if constexpr (kSorted) {
+      if ((int)lane < pend_cnt) key_min(pend_e0 + (int)lane, pend_best);
+      pend_cnt = 0;
+    } else {
+      if (pend_slot >= 0) key_min(pend_slot, pend_best);
+      pend_slot = -1;
+    }
   };
   auto entries_row = [&](int y) {
-    __syncthreads();
-    if constexpr (kSorted) {
-      const uint32_t rowbase = (uint32_t)y * (uint32_t)W + (uint32_t)x0;
-      if ((int)lane < cnt) entry((int)(pf_cur - rowbase), e0 + (int)lane);
-      // rows with more than 64 listed pixels in the tile: the rest loaded here
-      for (int e = (int)lane + kWave; e < cnt; e += kWave) entry((int)(*(g_uint32*)(f.idx + e0 + e) - rowbase), e0 + e);
-    } else {
-      for (int e = lane; e < cnt; e += kWave) entry(sm.eo[e], sm.es[e]);
+    const uint32_t rowbase = (uint32_t)y * (uint32_t)W + (uint32_t)x0;
+    int o0 = 0, slot0 = -1;
+    if ((int)lane < cnt) {
+      if constexpr (kSorted) { o0 = (int)(pf_cur - rowbase); slot0 = e0 + (int)lane; }
+      else { o0 = sm.eo[lane]; slot0 = sm.es[lane]; }
     }
-    __syncthreads();   // LDS free for the next row
+    uint32_t best0 = 0xFFFFFFFFu;
+#pragma unroll
+    for (int g = 0; g < DC; g += kGroup) {
+      prefix_group(g);
+      if (slot0 >= 0) best0 = group_best(g, o0, best0);
+      // rows with more than 64 listed pixels in the tile: one key update per group
+      for (int e = (int)lane + kWave; e < cnt; e += kWave) {
+        int o, slot;
+        if constexpr (kSorted) { o = (int)(*(g_uint32*)(f.idx + e0 + e) - rowbase); slot = e0 + e; }
+        else { o = sm.eo[e]; slot = sm.es[e]; }
+        key_min(slot, group_best(g, o, 0xFFFFFFFFu));
+      }
+      __syncthreads();   // LDS free for the next group / row
+    }
+    pend_best = best0;
+    if constexpr (kSorted) { pend_e0 = e0; pend_cnt = cnt; }
+    else pend_slot = slot0;
   };
 
   // Walk down the rows. The loads for the step y -> y + 1 (padded row
@@ -555,58 +614,84 @@ __device__ __forceinline__ void tile_item_impl(const FrameDev& f, int tile, int 
   const uint32_t* lout = lp0 + (int64_t)ya * lpw;
   const uint32_t* rout = rp0 + (int64_t)ya * rpw;
   RowRegs<DC> En, Ex;
-  load_next(ya);
   load_row<DC>(lin, rin, lo, En);
   load_row<DC>(lout, rout, lo, Ex);
-  for (int y = ya; y < yb; ++y) {
-    const bool act = is_active(y);
-    if (act) prefix_row();
-    pin_step(acc.v);
-    slide_row<DC, kPack>(En, Ex, acc);
-    pin_step(acc.v);
-    if (act) {
-      take_row(y);
-      load_next(next_active(y));
+  for (int y = ya;; ++y) {
+    if (y > ya) {
+      pin_step(acc.v);
+      slide_row<DC, kPack>(En, Ex, acc);
+      pin_step(acc.v);
+      flush();
+      lin += lpw; rin += rpw; lout += lpw; rout += rpw;
+      load_row<DC>(lin, rin, lo, En);
+      load_row<DC>(lout, rout, lo, Ex);
     }
-    lin += lpw; rin += rpw; lout += lpw; rout += rpw;
-    load_row<DC>(lin, rin, lo, En);
-    load_row<DC>(lout, rout, lo, Ex);
-    if (act) entries_row(y);
-    // R[0] only pads the loads to 16 bytes; keeping it live stops its
-    // register from being reused while the load is still in flight.
-    asm volatile("" ::"v"(En.R[0]), "v"(Ex.R[0]));
+    if (is_active(y)) {
+      take_row(y);
+      if (y < yb) load_next(next_active(y));
+      pin_step(acc.v);
+      entries_row(y);
+    }
+    if (y == yb) break;
   }
-  prefix_row();
-  take_row(yb);
-  entries_row(yb);
+  flush();
 }
 
 // Ordered and unordered lists, packed and 32-bit accumulators take separate
 // instances (fewer live registers in each).
+// 16-disparity chunks exist only with packed accumulators (the host uses
+// 8-disparity chunks for frames whose window sums need 32 bits).
+template <bool kPack>
+__device__ __forceinline__ void tile_item8(const FrameDev& f, int tile, int chunk8, bool unsorted, TileLds& sm) {
+  if (unsorted) tile_item_impl<8, false, kPack>(f, tile, chunk8, sm);
+  else tile_item_impl<8, true, kPack>(f, tile, chunk8, sm);
+}
+
+// The same as an out-of-line call: inside the 16-disparity kernels its
+// registers then do not add to those of the 16-disparity instance (it serves
+// the less common frames there).
+template <bool kPack>
+__device__ __noinline__ void tile_item8_call(const FrameDev& f, int tile, int chunk8, bool unsorted, TileLds& sm) {
+  tile_item8<kPack>(f, tile, chunk8, unsorted, sm);
+}
+
+// A 16-disparity item of an ordered list with packed accumulators runs as
+// one pass; any other frame runs its 16 disparities as two 8-disparity
+// passes (same work decomposition, fewer registers).
 template <int DC>
-__device__ __forceinline__ void tile_item(const FrameDev& f, int tile, int chunk, TileLds<DC>& sm) {
+__device__ __forceinline__ void tile_item(const FrameDev& f, int tile, int chunk, TileLds& sm) {
   const bool unsorted = *(g_uint32*)f.state & kUnsorted;
-  if (f.pack) {
-    if (unsorted) tile_item_impl<DC, false, true>(f, tile, chunk, sm);
-    else tile_item_impl<DC, true, true>(f, tile, chunk, sm);
-  } else {
-    if (unsorted) tile_item_impl<DC, false, false>(f, tile, chunk, sm);
-    else tile_item_impl<DC, true, false>(f, tile, chunk, sm);
+  if (DC == 16 && f.pack && !unsorted) {
+    tile_item_impl<16, true, true>(f, tile, chunk, sm);
+    return;
+  }
+  constexpr int kParts = DC / 8;
+#pragma unroll 1
+  for (int h = 0; h < kParts; ++h) {
+    const int c8 = kParts * chunk + h;
+    if (c8 * 8 > f.dmax) break;
+    if constexpr (DC == 8) {
+      if (f.pack) tile_item8<true>(f, tile, c8, unsorted, sm);
+      else tile_item8<false>(f, tile, c8, unsorted, sm);
+    } else {
+      if (f.pack) tile_item8_call<true>(f, tile, c8, unsorted, sm);
+      else tile_item8_call<false>(f, tile, c8, unsorted, sm);
+    }
   }
 }
 
 template <int DC>
-__device__ __forceinline__ void zero_lds_front(TileLds<DC>& sm) {
-  if (threadIdx.x < DC * 4) sm.pre[threadIdx.x >> 2][threadIdx.x & 3] = 0u;
+__device__ __forceinline__ void zero_lds_front(TileLds& sm) {
+  if (threadIdx.x < kGroup * 4) sm.pre[threadIdx.x >> 2][threadIdx.x & 3] = 0u;
   __syncthreads();
 }
 
 // Occupancy target: four wavefronts per SIMD (128 VGPRs) for the 8-disparity
 // chunk, two for the 16-disparity chunk.
 template <int DC>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(DC == 8 ? 4 : 2, 8))) void k_tile_grid(
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_tile_grid(
     const FrameDev* __restrict__ table, int fi) {
-  __shared__ TileLds<DC> sm;
+  __shared__ TileLds sm;
   zero_lds_front<DC>(sm);
   const FrameDev& f = table[fi];
   const uint32_t item = blockIdx.x;
@@ -618,9 +703,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(DC == 8 ? 4 
 // Workgroup w starts on queue w % 8 (the XCD the hardware places it on) and,
 // once that queue is empty, takes items from the others.
 template <int DC>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(DC == 8 ? 4 : 2, 8))) void k_tile_persistent(
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_tile_persistent(
     const FrameDev* __restrict__ table, int nframes, QueueTotals totals, WsHeader* hdr) {
-  __shared__ TileLds<DC> sm;
+  __shared__ TileLds sm;
   __shared__ long long next_item;
   zero_lds_front<DC>(sm);
   const int home = blockIdx.x % kQueues;

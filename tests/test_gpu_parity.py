@@ -292,3 +292,40 @@ def test_saturated_sums_at_the_16_bit_accumulator_limit(torch, sbs):
             exp = oracle.sad(L, R, idx, block, 20)
             assert exp[1].max() >= block * 255 * C // 2, "inputs must drive column sums near the limit"
             assert_parity(run_gpu(torch, sbs, L, R, idx, block, 20), exp, f"C{C} b{block} saturated")
+
+
+def test_chunk16_all_instances(torch, sbs):
+    """16-disparity chunks: ordered + packed frames run the 16-wide instance;
+    unordered lists and 32-bit accumulators run two 8-wide passes per item.
+    Partial last chunks (dmax + 1 not a multiple of 16, dmax < 8), 128-row
+    tiles, single-frame and batched persistent launches."""
+    rng = np.random.default_rng(12)
+    cases = []
+    for (H, W, C, block, dmax, order) in [(150, 260, 3, 15, 40, "sorted"), (150, 260, 3, 15, 40, "shuffled"),
+                                          (140, 300, 3, 127, 20, "sorted"), (90, 200, 1, 9, 5, "sorted"),
+                                          (90, 200, 1, 9, 127, "shuffled")]:
+        shape = (H, W, C) if C == 3 else (H, W)
+        L = rng.integers(0, 256, shape, dtype=np.uint8)
+        R = np.roll(L, 3, axis=1)
+        R[::7] = rng.integers(0, 256, R[::7].shape, dtype=np.uint8)
+        idx = np.sort(rng.choice(H * W, H * W // 5, replace=False)).astype(np.uint32)
+        if order == "shuffled":
+            idx = np.concatenate([rng.permutation(idx), idx[:17]])
+        cases.append((L, R, idx, block, dmax))
+    try:
+        for rows in (32, 128):
+            sbs.set_plan(chunk=16, tile_rows=rows)
+            for (L, R, idx, block, dmax) in cases:
+                exp = oracle.sad(L, R, idx, block, dmax)
+                assert_parity(run_gpu(torch, sbs, L, R, idx, block, dmax), exp, f"chunk16 rows {rows} b{block} d{dmax}")
+            frames = [(dev(torch, L), dev(torch, R), dev(torch, idx.view(np.int32)), block, dmax)
+                      for (L, R, idx, block, dmax) in cases]
+            runner = sbs.BatchRunner(frames)
+            runner.run()
+            torch.cuda.synchronize()
+            for i, (L, R, idx, block, dmax) in enumerate(cases):
+                exp = oracle.sad(L, R, idx, block, dmax)
+                got = (runner.disp[i].cpu().numpy(), runner.cost[i].cpu().numpy().view(np.uint32))
+                assert_parity(got, exp, f"chunk16 batched rows {rows} frame {i}")
+    finally:
+        sbs.set_plan()
