@@ -92,6 +92,10 @@ def main():
     ap.add_argument("--serve", action="store_true",
                     help="serving mode: 2000 mixed-resolution requests, continuous batching, p50/p99 latency")
     ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--single", action="store_true",
+                    help="single-frame workloads (384x288 gray, 1390x1110 RGB, 4096x2304 RGB): median/min of 20 runs")
+    ap.add_argument("--oracle-detail", action="store_true",
+                    help="oracle timings on the host: all threads and 1 thread, brute force and summed-area tables")
     ap.add_argument("--paper", action="store_true",
                     help="the paper's whole chain (Table 3 setting) per frame: stage times and Eq. 3 on synthetic GT")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -130,6 +134,12 @@ def main():
         return
     if args.paper:
         paper_main(args)
+        return
+    if args.single:
+        single_main(args)
+        return
+    if args.oracle_detail:
+        oracle_detail_main(args)
         return
 
     spec = scenes.PRESETS[args.workload]
@@ -308,6 +318,91 @@ def main():
 
 SERVE_CLASSES = [("serve_vga", 1000), ("serve_fhd", 600), ("serve_uhd", 400)]
 SERVE_FRACS = (0.12, 0.16, 0.20, 0.24)
+
+
+def single_main(args):
+    """One frame per call on the device (the single-frame entry point), per
+    workload: 3 warm-ups, then the median and min of 20 timed calls (HIP
+    events around each call on the current stream)."""
+    import numpy as np
+    import torch
+
+    import paper_2001_07809_amd as sbs
+    import scenes
+
+    out = {"metric": "single-frame boundary-px x disparity SAD evals/s", "workloads": {}}
+    for name in ("tsukuba_gray", "middlebury_rgb", "uhd_rgb"):
+        spec = scenes.PRESETS[name]
+        f = scenes.make_frame(spec)
+        idx = scenes.contour_list(f.rid, spec.frac, spec.seed)
+        L = torch.from_numpy(f.left).cuda()
+        R = torch.from_numpy(f.right).cuda()
+        I = torch.from_numpy(idx.view(np.int32)).cuda()
+        times = []
+        for it in range(3 + 20):
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record()
+            sbs.sad_disparity(L, R, I, spec.block, spec.dmax)
+            b.record()
+            torch.cuda.synchronize()
+            if it >= 3:
+                times.append(a.elapsed_time(b))
+        evals = idx.size * (spec.dmax + 1)
+        med, mn = float(np.median(times)), float(min(times))
+        rec = {"size": f"{spec.W}x{spec.H}x{spec.C}", "block": spec.block, "dmax": spec.dmax, "n": int(idx.size),
+               "median_ms": round(med, 4), "min_ms": round(mn, 4), "evals_per_s_median": evals / (med * 1e-3)}
+        log(f"single {name}: {rec}")
+        out["workloads"][name] = rec
+    print(json.dumps(out), flush=True)
+
+
+def oracle_detail_main(args):
+    """The oracle on the host: brute force on all hardware threads and on one,
+    and the summed-area-table variant, on the three single-frame workloads
+    (the 4096x2304 frame on a random sample of its list)."""
+    import platform
+
+    import numpy as np
+
+    import oracle
+    import scenes
+
+    cpu = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    cpu = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    nthreads = os.cpu_count() or 1
+    out = {"metric": "oracle evals/s on the host", "cpu": cpu, "nproc": nthreads, "machine": platform.machine(),
+           "build": "g++ -O2 -fopenmp (no intrinsics)", "workloads": {}}
+    rng = np.random.default_rng(7)
+    for name in ("tsukuba_gray", "middlebury_rgb", "uhd_rgb"):
+        spec = scenes.PRESETS[name]
+        f = scenes.make_frame(spec)
+        idx = scenes.contour_list(f.rid, spec.frac, spec.seed)
+        sample = idx if name != "uhd_rgb" else np.sort(rng.choice(idx, 20000, replace=False)).astype(np.uint32)
+        rec = {"n_full": int(idx.size), "n_timed": int(sample.size)}
+        for label, threads in (("all_threads", nthreads), ("one_thread", 1)):
+            sub = sample if threads > 1 else sample[: max(1, sample.size // 8)]
+            t0 = time.time()
+            oracle.sad(f.left, f.right, sub, spec.block, spec.dmax, threads=threads)
+            dt = time.time() - t0
+            rec[label] = {"threads": threads, "entries": int(sub.size), "seconds": round(dt, 3),
+                          "evals_per_s": sub.size * (spec.dmax + 1) / dt}
+        if name != "uhd_rgb":
+            t0 = time.time()
+            oracle.sad_sat(f.left, f.right, idx, spec.block, spec.dmax)
+            dt = time.time() - t0
+            rec["summed_area_tables"] = {"threads": 1, "entries": int(idx.size), "seconds": round(dt, 3),
+                                         "evals_per_s": idx.size * (spec.dmax + 1) / dt}
+        log(f"oracle {name}: {rec}")
+        out["workloads"][name] = rec
+    print(json.dumps(out), flush=True)
 
 
 def paper_main(args):
