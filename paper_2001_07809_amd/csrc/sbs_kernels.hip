@@ -55,6 +55,7 @@ typedef __attribute__((address_space(1))) const int32_t g_int32;
 typedef __attribute__((address_space(1))) const uint32_t g_uint32;
 typedef __attribute__((address_space(1))) const uint64_t g_uint64;
 typedef __attribute__((address_space(1))) uint32_t g_uint32_rw;
+typedef __attribute__((address_space(1))) u32x4 g_uint4_rw;
 
 // ---------------------------------------------------------------------------
 // Descriptor upload: the descriptors travel inside the kernel argument, so a
@@ -96,18 +97,18 @@ __global__ __launch_bounds__(256) void k_check(const FrameDev* __restrict__ tabl
 // a 4-byte-aligned source row read 12 (RGB) or 4 (gray) bytes with aligned
 // dword loads; border groups and unaligned rows read pixel by pixel with
 // clamped coordinates.
-__device__ __forceinline__ uint4 pack_group(const uint8_t* row, int ic0, int W, int C, bool aligned) {
-  uint4 o;
+__device__ __forceinline__ u32x4 pack_group(const uint8_t* row, int ic0, int W, int C, bool aligned) {
+  u32x4 o;
   if (aligned && ic0 >= 0 && ic0 + 3 < W) {
     if (C == 3) {
-      const uint32_t* q = (const uint32_t*)(row + (int64_t)ic0 * 3);
-      const uint32_t a = q[0], b = q[1], c = q[2];
+      const u32x3 q = *(g_uint3*)(row + (int64_t)ic0 * 3);   // one 12-byte load
+      const uint32_t a = q.x, b = q.y, c = q.z;
       o.x = a & 0xFFFFFFu;
       o.y = (a >> 24) | ((b & 0xFFFFu) << 8);
       o.z = (b >> 16) | ((c & 0xFFu) << 16);
       o.w = c >> 8;
     } else {
-      const uint32_t a = *(const uint32_t*)(row + ic0);
+      const uint32_t a = *(g_uint32*)(row + ic0);
       o.x = a & 0xFFu; o.y = (a >> 8) & 0xFFu; o.z = (a >> 16) & 0xFFu; o.w = a >> 24;
     }
   } else {
@@ -128,8 +129,8 @@ __global__ __launch_bounds__(256) void k_prep(const FrameDev* __restrict__ table
     const uint8_t* lrow = f.left + (int64_t)y * f.pitch;
     const uint8_t* rrow = f.right + (int64_t)y * f.pitch;
     const bool la = ((uintptr_t)lrow & 3) == 0, ra = ((uintptr_t)rrow & 3) == 0;
-    uint4* lo = (uint4*)(f.lp + (int64_t)v * f.lpw);
-    uint4* ro = (uint4*)(f.rp + (int64_t)v * f.rpw);
+    g_uint4_rw* lo = (g_uint4_rw*)(f.lp + (int64_t)v * f.lpw);
+    g_uint4_rw* ro = (g_uint4_rw*)(f.rp + (int64_t)v * f.rpw);
     for (int g = threadIdx.x; g < (f.lpw >> 2); g += blockDim.x) lo[g] = pack_group(lrow, 4 * g - f.lpad, W, C, la);
     for (int g = threadIdx.x; g < (f.rpw >> 2); g += blockDim.x) ro[g] = pack_group(rrow, 4 * g - f.rpad, W, C, ra);
     if (unsorted && v >= r && v < r + H) {
