@@ -253,6 +253,12 @@ int sbs_lightness(const uint8_t* img, int32_t W, int32_t H, int32_t C, int64_t p
  *       8-connected components, ties by smallest raster index, while the
  *       dropped total stays <= floor(0.04 * all boundary pixels)
  *   -> list = left and right border columns plus the kept pixels, ascending.
+ *   frac >= 0 (a benchmark knob, not the paper's): instead exactly
+ *   llround(frac * W * H) pixels (at most W*H), ranked as (1) border columns by
+ *   raster index, (2) kept pixels by component size descending, then raster
+ *   index, (3) the other pixels by chessboard distance to (1)+(2) ascending,
+ *   then h(i) = SplitMix64's output function of (i xor seed), then raster
+ *   index; still ascending raster indices. frac < 0: no fraction control.
  *   img          device, HWC u8, rows `pitch` bytes apart; C = 1 or 3
  *   K            clusters, 1..64
  *   out_idx      device, capacity W*H u32: raster indices y*W + x, ascending
@@ -269,8 +275,8 @@ int sbs_lightness(const uint8_t* img, int32_t W, int32_t H, int32_t C, int64_t p
  */
 size_t sbs_boundaries_workspace_bytes(int32_t W, int32_t H);
 int sbs_boundaries(const uint8_t* img, int32_t W, int32_t H, int32_t C, int64_t pitch, int32_t K, int32_t mode,
-                   int32_t min_cc, uint32_t* out_idx, int64_t* out_count, uint8_t* out_refined, uint8_t* out_labels,
-                   void* workspace, size_t workspace_bytes, void* stream);
+                   int32_t min_cc, double frac, uint64_t seed, uint32_t* out_idx, int64_t* out_count,
+                   uint8_t* out_refined, uint8_t* out_labels, void* workspace, size_t workspace_bytes, void* stream);
 
 #ifdef __cplusplus
 }

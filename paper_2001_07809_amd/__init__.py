@@ -102,7 +102,8 @@ def lib():
         "sbs_kernel_times": ([ctypes.POINTER(ctypes.c_float), I32], I32),
         "sbs_lightness": ([V, I32, I32, I32, I64, V, V], ctypes.c_int),
         "sbs_boundaries_workspace_bytes": ([I32, I32], SZ),
-        "sbs_boundaries": ([V, I32, I32, I32, I64, I32, I32, I32, V, V, V, V, V, SZ, V], ctypes.c_int),
+        "sbs_boundaries": ([V, I32, I32, I32, I64, I32, I32, I32, ctypes.c_double, ctypes.c_uint64, V, V, V, V, V,
+                            SZ, V], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -282,9 +283,11 @@ def lightness(img, stream=None):
     return out
 
 
-def boundaries(img, K: int = 4, mode: int = 0, min_cc: int = 50, with_maps: bool = False, stream=None):
+def boundaries(img, K: int = 4, mode: int = 0, min_cc: int = 50, frac: float = -1.0, seed: int = 0,
+               with_maps: bool = False, stream=None):
     """Ascending int32 device list of refined boundary pixels (plus border
-    columns) of a device image. With ``with_maps`` also returns the kept
+    columns) of a device image; with ``frac >= 0`` exactly round(frac*W*H)
+    pixels by the fixed ranking. With ``with_maps`` also returns the kept
     boundary map and the label image [H, W] u8."""
     torch = _torch()
     W, H, C, pitch = _image_args(img)
@@ -295,7 +298,8 @@ def boundaries(img, K: int = 4, mode: int = 0, min_cc: int = 50, with_maps: bool
     labels = torch.empty((H, W), dtype=torch.uint8, device=dev) if with_maps else None
     nb = int(lib().sbs_boundaries_workspace_bytes(W, H))
     ws = torch.empty(max(nb, 256), dtype=torch.uint8, device=dev)
-    _check(lib().sbs_boundaries(img.data_ptr(), W, H, C, pitch, K, mode, min_cc, out.data_ptr(), count.data_ptr(),
+    _check(lib().sbs_boundaries(img.data_ptr(), W, H, C, pitch, K, mode, min_cc, float(frac), seed & (2**64 - 1),
+                                out.data_ptr(), count.data_ptr(),
                                 None if refined is None else refined.data_ptr(),
                                 None if labels is None else labels.data_ptr(), ws.data_ptr(), ws.numel(),
                                 _stream_handle(stream)))

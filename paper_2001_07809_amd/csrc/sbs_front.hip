@@ -23,6 +23,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 
@@ -348,6 +350,27 @@ __global__ __launch_bounds__(1024) void k_drop_find(const int32_t* __restrict__ 
 // scatter. Flag sources:
 //   kind 0 (roots of size s*):  rank[i] = number of such roots before i
 //   kind 1 (list):              out[pos] = i for border columns and kept pixels
+// Fraction control (a benchmark knob, not the paper's): exactly `want`
+// pixels ranked as (1) border columns by raster index, (2) kept pixels by
+// component size descending, then raster index, (3) all other pixels by
+// chessboard distance to (1)+(2) ascending, then h(i) = mix64(i ^ seed), then
+// raster index. The selection is threshold-based: a radix select finds the
+// key of the want-th pixel within the class it falls in, ties at that key go
+// by raster order (a device-wide scan).
+struct RadixSel {
+  unsigned long long prefix;   // key bits found so far (top digits first)
+  long long need;              // rank (1-based) of the wanted key among the candidates
+  long long below;             // candidates with a smaller key (of the digits fixed so far)
+};
+
+struct FracState {
+  long long want, n0, n1;
+  int32_t mode;                // 0: border only, 1: + kept pixels, 2: + other pixels
+  RadixSel s1;                 // kept pixels: key ~size (size descending)
+  RadixSel s2;                 // other pixels: key distance
+  RadixSel s3;                 // other pixels at distance s2.prefix: key h(i)
+};
+
 struct ScanCtx {
   const uint8_t* B;       // boundary map after refinement
   const int32_t* parent;  // flattened: root of each boundary pixel, -1 elsewhere
@@ -360,6 +383,10 @@ struct ScanCtx {
   uint32_t* out;          // kind 1 output
   uint8_t* refined;       // kind 1 optional output: kept map
   long long* count;       // kind 1: list length
+  const FracState* fc;    // fraction control (nullptr: list = border columns + kept pixels)
+  const int32_t* dist;    // chessboard distance to border + kept pixels
+  int32_t* frank;         // kinds 2, 3 output: rank of a tie in raster order
+  unsigned long long seed;
 };
 
 __device__ __forceinline__ bool kept(const ScanCtx& c, int64_t i) {
@@ -372,13 +399,57 @@ __device__ __forceinline__ bool kept(const ScanCtx& c, int64_t i) {
   return true;
 }
 
+// SplitMix64's output function (Steele, Lea and Flood; constants as
+// published by Vigna), on the raster index xor the seed.
+__device__ __forceinline__ unsigned long long mix64(unsigned long long z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ bool border(const ScanCtx& c, int64_t i) {
+  const int x = (int)(i % c.W);
+  return x == 0 || x == c.W - 1;
+}
+
+__device__ __forceinline__ int32_t comp_size(const ScanCtx& c, int64_t i) { return c.size[c.parent[i]]; }
+
+__device__ __forceinline__ bool selected(const ScanCtx& c, int64_t i) {
+  const bool b = border(c, i);
+  if (!c.fc) return b || kept(c, i);
+  const FracState& f = *c.fc;
+  if (f.mode == 0) {
+    if (!b) return false;
+    const int64_t y = i / c.W;
+    const int64_t rank0 = c.W == 1 ? y : 2 * y + ((i % c.W) == c.W - 1 ? 1 : 0);
+    return rank0 < f.want;
+  }
+  if (b) return true;
+  const bool k = kept(c, i);
+  if (f.mode == 1) {
+    if (!k) return false;
+    const uint32_t key = ~(uint32_t)comp_size(c, i);
+    const uint32_t kstar = (uint32_t)f.s1.prefix;
+    return key < kstar || (key == kstar && c.frank[i] < f.s1.need - f.s1.below);
+  }
+  if (k) return true;
+  const uint32_t d = (uint32_t)c.dist[i], dstar = (uint32_t)f.s2.prefix;
+  if (d != dstar) return d < dstar;
+  const unsigned long long h = mix64((unsigned long long)i ^ c.seed);
+  return h < f.s3.prefix || (h == f.s3.prefix && c.frank[i] < f.s3.need - f.s3.below);
+}
+
 template <int KIND>
 __device__ __forceinline__ bool flag(const ScanCtx& c, int64_t i) {
   if constexpr (KIND == 0) {
     return c.parent[i] == (int32_t)i && c.size[i] == c.rule->s_star;
-  } else {
-    const int x = (int)(i % c.W);
-    return x == 0 || x == c.W - 1 || kept(c, i);
+  } else if constexpr (KIND == 1) {
+    return selected(c, i);
+  } else if constexpr (KIND == 2) {   // kept, not border, size at the threshold
+    return !border(c, i) && kept(c, i) && ~(uint32_t)comp_size(c, i) == (uint32_t)c.fc->s1.prefix;
+  } else {                            // other pixels at the threshold distance and hash
+    return !border(c, i) && !kept(c, i) && (uint32_t)c.dist[i] == (uint32_t)c.fc->s2.prefix &&
+           mix64((unsigned long long)i ^ c.seed) == c.fc->s3.prefix;
   }
 }
 
@@ -452,11 +523,135 @@ __global__ __launch_bounds__(kBlock) void k_scan_apply(ScanCtx c, const uint32_t
     if (i >= c.N) break;
     if constexpr (KIND == 0) {
       if (f[j]) c.rank[i] = (int32_t)pos;
-    } else {
+    } else if constexpr (KIND == 1) {
       if (f[j]) c.out[pos] = (uint32_t)i;
       if (c.refined) c.refined[i] = kept(c, i) ? 1 : 0;
+    } else {
+      if (f[j]) c.frank[i] = (int32_t)pos;
     }
     pos += f[j];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Fraction control kernels.
+__global__ __launch_bounds__(kBlock) void k_fc_count(ScanCtx c, unsigned long long* n1) {
+  __shared__ unsigned long long part;
+  if (threadIdx.x == 0) part = 0;
+  __syncthreads();
+  unsigned long long mine = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < c.N; i += (int64_t)gridDim.x * blockDim.x)
+    mine += (!border(c, i) && kept(c, i)) ? 1ull : 0ull;
+  atomicAdd(&part, mine);
+  __syncthreads();
+  if (threadIdx.x == 0) atomicAdd(n1, part);
+}
+
+// Which class the want-th pixel falls in, and the rank wanted inside it.
+__global__ void k_fc_plan(FracState* f, const unsigned long long* n1, long long want, long long n0) {
+  f->want = want;
+  f->n0 = n0;
+  f->n1 = (long long)*n1;
+  f->s1 = RadixSel{0, 0, 0};
+  f->s2 = RadixSel{0, 0, 0};
+  f->s3 = RadixSel{0, 0, 0};
+  if (f->want <= f->n0) { f->mode = 0; return; }
+  if (f->want <= f->n0 + f->n1) { f->mode = 1; f->s1.need = f->want - f->n0; return; }
+  f->mode = 2;
+  f->s2.need = f->want - f->n0 - f->n1;
+}
+
+// The rank wanted at distance s2.prefix among the other pixels.
+__global__ void k_fc_after_dist(FracState* f) { f->s3 = RadixSel{0, f->s2.need - f->s2.below, 0}; }
+
+// Radix select, one 8-bit digit per pass from the top: per-block digit
+// histograms of the candidates whose higher digits match, then one block
+// picks the digit where the running count reaches `need`.
+template <int SEL>
+__device__ __forceinline__ bool rs_key(const ScanCtx& c, int64_t i, unsigned long long& key) {
+  if constexpr (SEL == 1) {
+    if (border(c, i) || !kept(c, i)) return false;
+    key = ~(uint32_t)comp_size(c, i);
+  } else if constexpr (SEL == 2) {
+    if (border(c, i) || kept(c, i)) return false;
+    key = (uint32_t)c.dist[i];
+  } else {
+    if (border(c, i) || kept(c, i) || (uint32_t)c.dist[i] != (uint32_t)c.fc->s2.prefix) return false;
+    key = mix64((unsigned long long)i ^ c.seed);
+  }
+  return true;
+}
+
+template <int SEL>
+__global__ __launch_bounds__(kBlock) void k_rs_hist(ScanCtx c, const RadixSel* rs, int shift, uint32_t* hist) {
+  __shared__ uint32_t h[256];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  const unsigned long long pre = rs->prefix;
+  const int hi = shift + 8;   // digits above this one must match the prefix
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < c.N; i += (int64_t)gridDim.x * blockDim.x) {
+    unsigned long long key;
+    if (!rs_key<SEL>(c, i, key)) continue;
+    if (hi < 64 && (key >> hi) != (pre >> hi)) continue;
+    atomicAdd(&h[(key >> shift) & 0xFF], 1u);
+  }
+  __syncthreads();
+  if (h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], h[threadIdx.x]);
+}
+
+__global__ __launch_bounds__(256) void k_rs_pick(RadixSel* rs, int shift, uint32_t* hist) {
+  __shared__ unsigned long long sc[256];
+  const int d = threadIdx.x;
+  const unsigned long long v = hist[d];
+  sc[d] = v;
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {
+    const unsigned long long a = d >= off ? sc[d - off] : 0ull;
+    __syncthreads();
+    sc[d] += a;
+    __syncthreads();
+  }
+  const long long need = rs->need, below = rs->below;
+  const long long before = below + (long long)(sc[d] - v);   // candidates with a smaller digit
+  __syncthreads();
+  if (need > 0 && before < need && need <= before + (long long)v) {
+    rs->prefix |= (unsigned long long)d << shift;
+    rs->below = before;
+  }
+  hist[d] = 0;   // ready for the next pass
+}
+
+// Chessboard distance to the border columns and kept pixels: per column the
+// vertical distance to the nearest such pixel, then per pixel the minimum
+// over columns x' of max(|x - x'|, that distance), searched outwards until
+// |x - x'| reaches the best found (the border columns bound it).
+constexpr int32_t kFar = 1 << 30;
+__global__ __launch_bounds__(kBlock) void k_dt_col(ScanCtx c, int32_t H, int32_t* g) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= c.W) return;
+  int last = -kFar;
+  for (int y = 0; y < H; ++y) {
+    const int64_t i = (int64_t)y * c.W + x;
+    if (border(c, i) || kept(c, i)) last = y;
+    g[i] = last < 0 ? kFar : y - last;
+  }
+  int next = kFar;
+  for (int y = H - 1; y >= 0; --y) {
+    const int64_t i = (int64_t)y * c.W + x;
+    if (border(c, i) || kept(c, i)) next = y;
+    if (next < kFar) g[i] = min(g[i], next - y);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_dt_row(ScanCtx c, const int32_t* g, int32_t* dist) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < c.N; i += (int64_t)gridDim.x * blockDim.x) {
+    const int x = (int)(i % c.W);
+    int d = g[i];
+    for (int k = 1; k < d; ++k) {
+      if (x - k >= 0) d = min(d, max(k, g[i - k]));
+      if (x + k < c.W) d = min(d, max(k, g[i + k]));
+    }
+    dist[i] = d;
   }
 }
 
@@ -472,7 +667,7 @@ int fail(int st, const char* fmt, ...) {
 size_t a256(size_t v) { return (v + 255) / 256 * 256; }
 
 struct Layout {
-  size_t L8, lab, lab2, B, B2, parent, size, cnt, bsum, hist, lut, misc, end;
+  size_t L8, lab, lab2, B, B2, parent, size, cnt, bsum, hist, g, dist, frank, rhist, lut, misc, end;
 };
 
 Layout layout(int64_t N) {
@@ -489,6 +684,10 @@ Layout layout(int64_t N) {
   o.cnt = take(((size_t)N + 1) * 4);
   o.bsum = take(((size_t)(N + kScanPer - 1) / kScanPer + 1) * 4);
   o.hist = take(256 * 8);
+  o.g = take((size_t)N * 4);
+  o.dist = take((size_t)N * 4);
+  o.frank = take((size_t)N * 4);
+  o.rhist = take(256 * 4);
   o.lut = take(256);
   o.misc = take(1024);
   o.end = off;
@@ -523,8 +722,8 @@ size_t sbs_boundaries_workspace_bytes(int32_t W, int32_t H) {
 }
 
 int sbs_boundaries(const uint8_t* img, int32_t W, int32_t H, int32_t C, int64_t pitch, int32_t K, int32_t mode,
-                   int32_t min_cc, uint32_t* out_idx, int64_t* out_count, uint8_t* out_refined, uint8_t* out_labels,
-                   void* workspace, size_t workspace_bytes, void* stream) {
+                   int32_t min_cc, double frac, uint64_t seed, uint32_t* out_idx, int64_t* out_count,
+                   uint8_t* out_refined, uint8_t* out_labels, void* workspace, size_t workspace_bytes, void* stream) {
   if (W < 1 || H < 1 || (int64_t)W * H > INT32_MAX || (C != 1 && C != 3) || pitch < (int64_t)W * C)
     return fail(SBS_ERR_INVALID_ARG, "bad image geometry");
   if (!img || !out_idx || !out_count || !workspace) return fail(SBS_ERR_INVALID_ARG, "NULL pointer");
@@ -532,6 +731,7 @@ int sbs_boundaries(const uint8_t* img, int32_t W, int32_t H, int32_t C, int64_t 
   if (mode != 0 && mode != 1) return fail(SBS_ERR_INVALID_ARG, "mode must be 0 (configured) or 1 (paper)");
   if (mode == 0 && min_cc < 0) return fail(SBS_ERR_INVALID_ARG, "min_cc < 0");
   if (H > 4 * 65535) return fail(SBS_ERR_UNSUPPORTED, "H > %d", 4 * 65535);   // 2-D stencil grid: 4 rows per block
+  if (!(frac < 0.0) && !(frac <= 1.0)) return fail(SBS_ERR_INVALID_ARG, "frac must be < 0 (off) or in [0, 1]");
   const int64_t N = (int64_t)W * H;
   const Layout Lo = layout(N);
   if (workspace_bytes < Lo.end) return fail(SBS_ERR_INVALID_ARG, "workspace too small");
@@ -552,6 +752,13 @@ int sbs_boundaries(const uint8_t* img, int32_t W, int32_t H, int32_t C, int64_t 
   int32_t* passes = (int32_t*)misc;
   unsigned long long* total = (unsigned long long*)(misc + 128);
   DropRule* rule = (DropRule*)(misc + 192);
+  FracState* fs = (FracState*)(misc + 256);
+  unsigned long long* n1 = (unsigned long long*)(misc + 512);
+  int32_t* gcol = (int32_t*)(base + Lo.g);
+  int32_t* dist = (int32_t*)(base + Lo.dist);
+  int32_t* frank = (int32_t*)(base + Lo.frank);
+  uint32_t* rhist = (uint32_t*)(base + Lo.rhist);
+  static_assert(sizeof(FracState) <= 256, "misc layout");
   const int g = grid_for(N);
   const dim3 g2((W + 63) / 64, (H + 3) / 4);
 
@@ -597,6 +804,35 @@ int sbs_boundaries(const uint8_t* img, int32_t W, int32_t H, int32_t C, int64_t 
     hipLaunchKernelGGL(k_scan_count<0>, dim3((unsigned)nb), dim3(kBlock), 0, s, c, bsum);
     hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, bsum, nb, (long long*)nullptr);
     hipLaunchKernelGGL(k_scan_apply<0>, dim3((unsigned)nb), dim3(kBlock), 0, s, c, bsum);
+  }
+  if (frac >= 0.0) {
+    const long long want = std::min<long long>((long long)N, std::llround(frac * (double)N));
+    const long long n0 = W == 1 ? H : 2LL * H;
+    hipLaunchKernelGGL(k_fill, dim3(1), dim3(kBlock), 0, s, (uint8_t*)rhist, (int64_t)(256 * 4), (uint8_t)0);
+    hipLaunchKernelGGL(k_fc_count, dim3(g), dim3(kBlock), 0, s, c, n1);
+    hipLaunchKernelGGL(k_fc_plan, dim3(1), dim3(1), 0, s, fs, n1, want, n0);
+    c.fc = fs; c.dist = dist; c.frank = frank; c.seed = (unsigned long long)seed;
+    for (int sh = 24; sh >= 0; sh -= 8) {      // kept pixels: size descending
+      hipLaunchKernelGGL(k_rs_hist<1>, dim3(g), dim3(kBlock), 0, s, c, &fs->s1, sh, rhist);
+      hipLaunchKernelGGL(k_rs_pick, dim3(1), dim3(256), 0, s, &fs->s1, sh, rhist);
+    }
+    hipLaunchKernelGGL(k_scan_count<2>, dim3((unsigned)nb), dim3(kBlock), 0, s, c, bsum);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, bsum, nb, (long long*)nullptr);
+    hipLaunchKernelGGL(k_scan_apply<2>, dim3((unsigned)nb), dim3(kBlock), 0, s, c, bsum);
+    hipLaunchKernelGGL(k_dt_col, dim3((W + kBlock - 1) / kBlock), dim3(kBlock), 0, s, c, H, gcol);
+    hipLaunchKernelGGL(k_dt_row, dim3(g), dim3(kBlock), 0, s, c, gcol, dist);
+    for (int sh = 24; sh >= 0; sh -= 8) {      // other pixels: distance
+      hipLaunchKernelGGL(k_rs_hist<2>, dim3(g), dim3(kBlock), 0, s, c, &fs->s2, sh, rhist);
+      hipLaunchKernelGGL(k_rs_pick, dim3(1), dim3(256), 0, s, &fs->s2, sh, rhist);
+    }
+    hipLaunchKernelGGL(k_fc_after_dist, dim3(1), dim3(1), 0, s, fs);
+    for (int sh = 56; sh >= 0; sh -= 8) {      // other pixels at that distance: hash
+      hipLaunchKernelGGL(k_rs_hist<3>, dim3(g), dim3(kBlock), 0, s, c, &fs->s3, sh, rhist);
+      hipLaunchKernelGGL(k_rs_pick, dim3(1), dim3(256), 0, s, &fs->s3, sh, rhist);
+    }
+    hipLaunchKernelGGL(k_scan_count<3>, dim3((unsigned)nb), dim3(kBlock), 0, s, c, bsum);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, bsum, nb, (long long*)nullptr);
+    hipLaunchKernelGGL(k_scan_apply<3>, dim3((unsigned)nb), dim3(kBlock), 0, s, c, bsum);
   }
   hipLaunchKernelGGL(k_scan_count<1>, dim3((unsigned)nb), dim3(kBlock), 0, s, c, bsum);
   hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, bsum, nb, (long long*)out_count);

@@ -70,16 +70,16 @@ def test_injected_launch_failure_reported(monkeypatch):
     assert _call(W=0) == 1
 
 
-def _front(W=16, H=8, C=3, pitch=None, K=4, mode=0, min_cc=50, ptr=1, ws=None):
+def _front(W=16, H=8, C=3, pitch=None, K=4, mode=0, min_cc=50, frac=-1.0, ptr=1, ws=None):
     lib = sbs.lib()
     p = ctypes.c_void_p(ptr) if ptr else None
     need = lib.sbs_boundaries_workspace_bytes(W, H)
-    return lib.sbs_boundaries(p, W, H, C, W * C if pitch is None else pitch, K, mode, min_cc, p, p, None, None, p,
-                              need if ws is None else ws, None)
+    return lib.sbs_boundaries(p, W, H, C, W * C if pitch is None else pitch, K, mode, min_cc, frac, 0, p, p, None,
+                              None, p, need if ws is None else ws, None)
 
 
 @pytest.mark.parametrize("kw", [dict(W=0), dict(H=0), dict(C=2), dict(pitch=10), dict(K=0), dict(K=65),
-                                dict(mode=2), dict(min_cc=-1), dict(ptr=0), dict(ws=16)])
+                                dict(mode=2), dict(min_cc=-1), dict(ptr=0), dict(ws=16), dict(frac=1.5)])
 def test_front_end_invalid_arguments_rejected_on_host(kw):
     assert _front(**kw) == 1
     assert sbs.lib().sbs_last_error().decode() != ""

@@ -104,3 +104,34 @@ def test_front_end_list_feeds_the_disparity_search(torch, sbs):
     idx = lst.cpu().numpy().view(np.uint32)
     ed, ec, _ = oracle.sad(f.left, f.right, idx, spec.block, spec.dmax)
     assert np.array_equal(d.cpu().numpy(), ed) and np.array_equal(c.cpu().numpy().view(np.uint32), ec)
+
+
+def test_fraction_control_matches_oracle(torch, sbs):
+    """Exactly round(f*W*H) pixels by the fixed ranking, for fractions that end
+    inside the border columns, inside the kept pixels and among the other
+    pixels (ranked by chessboard distance, then the seeded hash)."""
+    cases = [("tsukuba_gray", 4, 0, 50), ("middlebury_rgb", 4, 0, 50), ("middlebury_rgb", 10, 1, 50)]
+    for name, K, mode, min_cc in cases:
+        spec = scenes.PRESETS[name]
+        f = scenes.make_frame(spec)
+        H, W = f.left.shape[:2]
+        d = torch.from_numpy(np.ascontiguousarray(f.left)).cuda()
+        _, kept_map = oracle.boundaries(f.left, K=K, mode=mode, min_cc=min_cc, frac=-1.0, return_map=True)
+        kept_frac = kept_map[:, 1:-1].sum() / (W * H)
+        fracs = [0.0, 0.5 / W, 2.0 / W + kept_frac / 2, 2.0 / W + kept_frac + 0.01, 0.18, 0.24, 0.7, 1.0]
+        for frac in fracs:
+            for seed in (spec.seed, 12345):
+                got = sbs.boundaries(d, K=K, mode=mode, min_cc=min_cc, frac=frac, seed=seed).cpu().numpy().view(np.uint32)
+                exp = oracle.boundaries(f.left, K=K, mode=mode, min_cc=min_cc, frac=frac, seed=seed)
+                assert got.size == exp.size == min(W * H, int(np.floor(frac * (W * H) + 0.5))), f"{name} frac {frac}: sizes"
+                assert np.array_equal(got, exp), f"{name} K{K} mode {mode} frac {frac} seed {seed}: lists differ"
+
+
+def test_fraction_control_benchmark_frame(torch, sbs):
+    """The 4096x2304 frame at 18%: the list the oracle's front end would give."""
+    spec = scenes.PRESETS["uhd_rgb"]
+    f = scenes.make_frame(spec)
+    d = torch.from_numpy(np.ascontiguousarray(f.left)).cuda()
+    got = sbs.boundaries(d, K=4, mode=0, min_cc=50, frac=0.18, seed=spec.seed).cpu().numpy().view(np.uint32)
+    exp = oracle.boundaries(f.left, K=4, mode=0, min_cc=50, frac=0.18, seed=spec.seed)
+    assert np.array_equal(got, exp)
