@@ -92,6 +92,8 @@ def main():
     ap.add_argument("--serve", action="store_true",
                     help="serving mode: 2000 mixed-resolution requests, continuous batching, p50/p99 latency")
     ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-raw", action="store_true",
+                    help="with --serve: requests carry only their images; the lists come from the device front end")
     ap.add_argument("--single", action="store_true",
                     help="single-frame workloads (384x288 gray, 1390x1110 RGB, 4096x2304 RGB): median/min of 20 runs")
     ap.add_argument("--oracle-detail", action="store_true",
@@ -500,7 +502,11 @@ def serve_main(args):
             spec, entries = pools[name]
             Ld, Rd, lists = entries[used[k] % 8]
             used[k] += 1
-            reqs.append(Request(i, Ld, Rd, lists[fpick], spec.block, spec.dmax, float(arrivals[i]), name))
+            if args.serve_raw:
+                reqs.append(Request(i, Ld, Rd, None, spec.block, spec.dmax, float(arrivals[i]), name,
+                                    frac=SERVE_FRACS[fpick], K=4, seed=spec.seed + i))
+            else:
+                reqs.append(Request(i, Ld, Rd, lists[fpick], spec.block, spec.dmax, float(arrivals[i]), name))
         return reqs
 
     free, total = torch.cuda.mem_get_info()
@@ -532,7 +538,8 @@ def serve_main(args):
         "data": "synthetic",
         "dtype": "u8",
         "config": {"workload": f"{kinds.size} requests, mix " + "/".join(f"{c} {n}" for n, c in counts)
-                   + "; pools of 8 resident scenes x 4 list fractions per class",
+                   + ("; raw frames: lists from the device front end (K=4, open/close, CC>=50, fraction control)"
+                      if args.serve_raw else "; pools of 8 resident scenes x 4 list fractions per class"),
                    "classes": {n: {"W": pools[n][0].W, "H": pools[n][0].H, "block": pools[n][0].block,
                                    "dmax": pools[n][0].dmax} for n, _ in counts},
                    "budget_bytes": budget, "max_inflight_batches": 2, "max_batch": 64},

@@ -77,15 +77,38 @@ __global__ __launch_bounds__(kBlock) void k_fill(uint8_t* p, int64_t n, uint8_t 
 }
 
 // Histogram: per-block counts in LDS, then one global add per bin.
+// Adds 1 at h[v] for every active lane, one atomic per distinct v in the
+// wavefront (lanes with equal values are found by ballot). Pays off where
+// neighbouring pixels share values, as in images and distance maps.
+__device__ __forceinline__ void wave_count(uint32_t* h, uint32_t v, bool active) {
+  uint64_t pending = __builtin_amdgcn_ballot_w64(active);
+  const int lane = (int)(threadIdx.x & 63);
+  while (pending) {
+    const int leader = __builtin_ctzll(pending);
+    const uint32_t lv = (uint32_t)__builtin_amdgcn_readlane((int)v, leader);
+    const uint64_t same = __builtin_amdgcn_ballot_w64(active && v == lv);
+    if (lane == leader) atomicAdd(&h[lv], (uint32_t)__builtin_popcountll(same));
+    pending &= ~same;
+  }
+}
+
+// Histogram: per-wavefront counts in LDS (four copies, fewer colliding
+// atomics), then one global add per bin and block.
 __global__ __launch_bounds__(kBlock) void k_hist(const uint8_t* __restrict__ L8, int64_t N,
                                                  unsigned long long* __restrict__ hist) {
-  __shared__ uint32_t h[256];
-  h[threadIdx.x] = 0;
+  __shared__ uint32_t h[kBlock / 64][256];
+  for (int w = 0; w < kBlock / 64; ++w) h[w][threadIdx.x] = 0;
   __syncthreads();
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x)
-    atomicAdd(&h[L8[i]], 1u);
+  uint32_t* mine = h[threadIdx.x >> 6];
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x; i0 < N; i0 += stride) {   // uniform per wavefront
+    const int64_t i = i0 + threadIdx.x;
+    wave_count(mine, i < N ? L8[i] : 0u, i < N);
+  }
   __syncthreads();
-  if (h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], (unsigned long long)h[threadIdx.x]);
+  uint32_t t = 0;
+  for (int w = 0; w < kBlock / 64; ++w) t += h[w][threadIdx.x];
+  if (t) atomicAdd(&hist[threadIdx.x], (unsigned long long)t);
 }
 
 // K-means on the occupied bins, one block, thread b owns bin b. Centres are
@@ -211,13 +234,18 @@ __global__ __launch_bounds__(kBlock) void k_stencil(const uint8_t* __restrict__ 
 // ---------------------------------------------------------------------------
 // Connected components by union-find. A link always points a larger root at
 // a smaller one, so a component's root ends as its smallest index.
-__device__ __forceinline__ int32_t uf_find(const int32_t* parent, int32_t a) {
-  int32_t p = __hip_atomic_load(&parent[a], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  while (p != a) {
-    a = p;
-    p = __hip_atomic_load(&parent[a], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+// Root of a, halving the path on the way (each visited pixel is pointed at
+// its grandparent with an atomic minimum, so a link only ever moves towards
+// smaller indices of the same component).
+__device__ __forceinline__ int32_t uf_find(int32_t* parent, int32_t a) {
+  for (;;) {
+    const int32_t p = __hip_atomic_load(&parent[a], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (p == a) return a;
+    const int32_t pp = __hip_atomic_load(&parent[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (pp == p) return p;
+    atomicMin(&parent[a], pp);
+    a = pp;
   }
-  return a;
 }
 
 __device__ __forceinline__ void uf_union(int32_t* parent, int32_t a, int32_t b) {
@@ -258,12 +286,28 @@ __global__ __launch_bounds__(kBlock) void k_cc_merge(const uint8_t* __restrict__
   }
 }
 
+// Roots for every pixel, and component sizes at the roots: a run of lanes
+// with the same root (neighbours in a row mostly share it) adds its length
+// with one atomic.
 __global__ __launch_bounds__(kBlock) void k_cc_flatten(int64_t N, int32_t* parent, int32_t* size) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
-    if (parent[i] < 0) continue;
-    const int32_t r = uf_find(parent, (int32_t)i);
-    parent[i] = r;
-    atomicAdd(&size[r], 1);
+  const int lane = (int)(threadIdx.x & 63);
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x; i0 < N; i0 += stride) {   // uniform per wavefront
+    const int64_t i = i0 + threadIdx.x;
+    int32_t r = -1;
+    if (i < N && parent[i] >= 0) {
+      r = uf_find(parent, (int32_t)i);
+      parent[i] = r;
+    }
+    const int32_t prev = __shfl_up(r, 1, 64);
+    const bool start = r >= 0 && (lane == 0 || prev != r);
+    const uint64_t starts = __builtin_amdgcn_ballot_w64(start);
+    const uint64_t breaks = starts | __builtin_amdgcn_ballot_w64(r < 0);   // a run ends at a start or an empty lane
+    if (start) {
+      const uint64_t after = lane == 63 ? 0ull : (breaks >> (lane + 1));
+      const int len = after ? __builtin_ctzll(after) + 1 : 64 - lane;
+      atomicAdd(&size[r], len);
+    }
   }
 }
 
@@ -283,7 +327,10 @@ struct DropRule {
 __global__ __launch_bounds__(kBlock) void k_drop_count(const int32_t* __restrict__ parent,
                                                        const int32_t* __restrict__ size, int64_t N,
                                                        unsigned long long* total, int32_t* cnt) {
+  constexpr int kSmall = 1024;   // sizes below this are counted per block in LDS first
   __shared__ unsigned long long part;
+  __shared__ int32_t small[kSmall];
+  for (int j = threadIdx.x; j < kSmall; j += blockDim.x) small[j] = 0;
   if (threadIdx.x == 0) part = 0;
   __syncthreads();
   unsigned long long mine = 0;
@@ -291,10 +338,13 @@ __global__ __launch_bounds__(kBlock) void k_drop_count(const int32_t* __restrict
     if (parent[i] != (int32_t)i) continue;   // roots only
     const int32_t s = size[i];
     mine += (unsigned long long)s;
-    atomicAdd(&cnt[s], 1);
+    if (s < kSmall) atomicAdd(&small[s], 1);
+    else atomicAdd(&cnt[s], 1);
   }
   atomicAdd(&part, mine);
   __syncthreads();
+  for (int j = threadIdx.x; j < kSmall && j <= N; j += blockDim.x)
+    if (small[j]) atomicAdd(&cnt[j], small[j]);
   if (threadIdx.x == 0) atomicAdd(total, part);
 }
 
@@ -387,6 +437,7 @@ struct ScanCtx {
   const int32_t* dist;    // chessboard distance to border + kept pixels
   int32_t* frank;         // kinds 2, 3 output: rank of a tie in raster order
   unsigned long long seed;
+  const uint8_t* cls;     // fraction control: 0 border column, 1 kept, 2 other
 };
 
 __device__ __forceinline__ bool kept(const ScanCtx& c, int64_t i) {
@@ -425,7 +476,7 @@ __device__ __forceinline__ bool selected(const ScanCtx& c, int64_t i) {
     return rank0 < f.want;
   }
   if (b) return true;
-  const bool k = kept(c, i);
+  const bool k = c.cls[i] == 1;
   if (f.mode == 1) {
     if (!k) return false;
     const uint32_t key = ~(uint32_t)comp_size(c, i);
@@ -446,9 +497,9 @@ __device__ __forceinline__ bool flag(const ScanCtx& c, int64_t i) {
   } else if constexpr (KIND == 1) {
     return selected(c, i);
   } else if constexpr (KIND == 2) {   // kept, not border, size at the threshold
-    return !border(c, i) && kept(c, i) && ~(uint32_t)comp_size(c, i) == (uint32_t)c.fc->s1.prefix;
+    return c.cls[i] == 1 && ~(uint32_t)comp_size(c, i) == (uint32_t)c.fc->s1.prefix;
   } else {                            // other pixels at the threshold distance and hash
-    return !border(c, i) && !kept(c, i) && (uint32_t)c.dist[i] == (uint32_t)c.fc->s2.prefix &&
+    return c.cls[i] == 2 && (uint32_t)c.dist[i] == (uint32_t)c.fc->s2.prefix &&
            mix64((unsigned long long)i ^ c.seed) == c.fc->s3.prefix;
   }
 }
@@ -535,13 +586,17 @@ __global__ __launch_bounds__(kBlock) void k_scan_apply(ScanCtx c, const uint32_t
 
 // ---------------------------------------------------------------------------
 // Fraction control kernels.
-__global__ __launch_bounds__(kBlock) void k_fc_count(ScanCtx c, unsigned long long* n1) {
+// Class of every pixel (0 border column, 1 kept, 2 other) and the kept count.
+__global__ __launch_bounds__(kBlock) void k_fc_class(ScanCtx c, uint8_t* cls, unsigned long long* n1) {
   __shared__ unsigned long long part;
   if (threadIdx.x == 0) part = 0;
   __syncthreads();
   unsigned long long mine = 0;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < c.N; i += (int64_t)gridDim.x * blockDim.x)
-    mine += (!border(c, i) && kept(c, i)) ? 1ull : 0ull;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < c.N; i += (int64_t)gridDim.x * blockDim.x) {
+    const uint8_t k = border(c, i) ? 0 : (kept(c, i) ? 1 : 2);
+    cls[i] = k;
+    mine += k == 1 ? 1ull : 0ull;
+  }
   atomicAdd(&part, mine);
   __syncthreads();
   if (threadIdx.x == 0) atomicAdd(n1, part);
@@ -570,13 +625,13 @@ __global__ void k_fc_after_dist(FracState* f) { f->s3 = RadixSel{0, f->s2.need -
 template <int SEL>
 __device__ __forceinline__ bool rs_key(const ScanCtx& c, int64_t i, unsigned long long& key) {
   if constexpr (SEL == 1) {
-    if (border(c, i) || !kept(c, i)) return false;
+    if (c.cls[i] != 1) return false;
     key = ~(uint32_t)comp_size(c, i);
   } else if constexpr (SEL == 2) {
-    if (border(c, i) || kept(c, i)) return false;
+    if (c.cls[i] != 2) return false;
     key = (uint32_t)c.dist[i];
   } else {
-    if (border(c, i) || kept(c, i) || (uint32_t)c.dist[i] != (uint32_t)c.fc->s2.prefix) return false;
+    if (c.cls[i] != 2 || (uint32_t)c.dist[i] != (uint32_t)c.fc->s2.prefix) return false;
     key = mix64((unsigned long long)i ^ c.seed);
   }
   return true;
@@ -589,11 +644,18 @@ __global__ __launch_bounds__(kBlock) void k_rs_hist(ScanCtx c, const RadixSel* r
   __syncthreads();
   const unsigned long long pre = rs->prefix;
   const int hi = shift + 8;   // digits above this one must match the prefix
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < c.N; i += (int64_t)gridDim.x * blockDim.x) {
-    unsigned long long key;
-    if (!rs_key<SEL>(c, i, key)) continue;
-    if (hi < 64 && (key >> hi) != (pre >> hi)) continue;
-    atomicAdd(&h[(key >> shift) & 0xFF], 1u);
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x; i0 < c.N; i0 += stride) {   // uniform per wavefront
+    const int64_t i = i0 + threadIdx.x;
+    unsigned long long key = 0;
+    bool cand = i < c.N && rs_key<SEL>(c, i, key);
+    if (cand && hi < 64 && (key >> hi) != (pre >> hi)) cand = false;
+    const uint32_t digit = (uint32_t)((key >> shift) & 0xFF);
+    if constexpr (SEL == 3) {   // hash digits: spread out, plain atomics
+      if (cand) atomicAdd(&h[digit], 1u);
+    } else {                    // sizes and distances: runs of equal digits
+      wave_count(h, digit, cand);
+    }
   }
   __syncthreads();
   if (h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], h[threadIdx.x]);
@@ -626,32 +688,83 @@ __global__ __launch_bounds__(256) void k_rs_pick(RadixSel* rs, int shift, uint32
 // over columns x' of max(|x - x'|, that distance), searched outwards until
 // |x - x'| reaches the best found (the border columns bound it).
 constexpr int32_t kFar = 1 << 30;
-__global__ __launch_bounds__(kBlock) void k_dt_col(ScanCtx c, int32_t H, int32_t* g) {
+constexpr int kSegRows = 32;   // rows per column segment
+
+__device__ __forceinline__ bool in_set(const ScanCtx& c, int64_t i) { return c.cls[i] != 2; }
+
+// Per (column, 32-row segment): the last and first selected row in it.
+__global__ __launch_bounds__(kBlock) void k_dt_seg(ScanCtx c, int32_t H, int32_t nseg, int32_t* last, int32_t* first) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)nseg * c.W) return;
+  const int x = (int)(t % c.W), sg = (int)(t / c.W);
+  int lo = -1, fi = kFar;
+  for (int y = sg * kSegRows; y < min(H, (sg + 1) * kSegRows); ++y)
+    if (in_set(c, (int64_t)y * c.W + x)) { lo = y; if (fi == kFar) fi = y; }
+  last[t] = lo;
+  first[t] = fi;
+}
+
+// Per column: the nearest selected row above each segment and below it.
+__global__ __launch_bounds__(kBlock) void k_dt_carry(int32_t W, int32_t nseg, const int32_t* last, const int32_t* first,
+                                                     int32_t* up, int32_t* down) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  if (x >= c.W) return;
-  int last = -kFar;
-  for (int y = 0; y < H; ++y) {
-    const int64_t i = (int64_t)y * c.W + x;
-    if (border(c, i) || kept(c, i)) last = y;
-    g[i] = last < 0 ? kFar : y - last;
+  if (x >= W) return;
+  int u = -kFar;
+  for (int sg = 0; sg < nseg; ++sg) {
+    up[(int64_t)sg * W + x] = u;
+    const int l = last[(int64_t)sg * W + x];
+    if (l >= 0) u = l;
   }
-  int next = kFar;
-  for (int y = H - 1; y >= 0; --y) {
-    const int64_t i = (int64_t)y * c.W + x;
-    if (border(c, i) || kept(c, i)) next = y;
-    if (next < kFar) g[i] = min(g[i], next - y);
+  int d = kFar;
+  for (int sg = nseg - 1; sg >= 0; --sg) {
+    down[(int64_t)sg * W + x] = d;
+    const int f = first[(int64_t)sg * W + x];
+    if (f < kFar) d = f;
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_dt_row(ScanCtx c, const int32_t* g, int32_t* dist) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < c.N; i += (int64_t)gridDim.x * blockDim.x) {
-    const int x = (int)(i % c.W);
-    int d = g[i];
-    for (int k = 1; k < d; ++k) {
-      if (x - k >= 0) d = min(d, max(k, g[i - k]));
-      if (x + k < c.W) d = min(d, max(k, g[i + k]));
+// g = vertical distance to the nearest selected pixel of the column.
+__global__ __launch_bounds__(kBlock) void k_dt_col(ScanCtx c, int32_t H, int32_t nseg, const int32_t* up,
+                                                   const int32_t* down, int32_t* g) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)nseg * c.W) return;
+  const int x = (int)(t % c.W), sg = (int)(t / c.W);
+  const int y0 = sg * kSegRows, y1 = min(H, (sg + 1) * kSegRows);
+  int u = up[t];
+  for (int y = y0; y < y1; ++y) {
+    const int64_t i = (int64_t)y * c.W + x;
+    if (in_set(c, i)) u = y;
+    g[i] = u < 0 ? kFar : y - u;
+  }
+  int d = down[t];
+  for (int y = y1 - 1; y >= y0; --y) {
+    const int64_t i = (int64_t)y * c.W + x;
+    if (in_set(c, i)) d = y;
+    if (d < kFar) g[i] = min(g[i], d - y);
+  }
+}
+
+// One block per row; rows up to kRowLds pixels wide are searched in LDS.
+constexpr int kRowLds = 8192;
+__global__ __launch_bounds__(kBlock) void k_dt_row(ScanCtx c, int32_t H, const int32_t* g, int32_t* dist) {
+  __shared__ int32_t row[kRowLds];
+  const bool in_lds = c.W <= kRowLds;
+  for (int y = blockIdx.x; y < H; y += gridDim.x) {
+    const int32_t* grow = g + (int64_t)y * c.W;
+    if (in_lds) {
+      for (int x = threadIdx.x; x < c.W; x += blockDim.x) row[x] = grow[x];
+      __syncthreads();
     }
-    dist[i] = d;
+    const int32_t* src = in_lds ? row : grow;
+    for (int x = threadIdx.x; x < c.W; x += blockDim.x) {
+      int d = src[x];
+      for (int k = 1; k < d; ++k) {
+        if (x - k >= 0) d = min(d, max(k, src[x - k]));
+        if (x + k < c.W) d = min(d, max(k, src[x + k]));
+      }
+      dist[(int64_t)y * c.W + x] = d;
+    }
+    __syncthreads();
   }
 }
 
@@ -670,7 +783,10 @@ struct Layout {
   size_t L8, lab, lab2, B, B2, parent, size, cnt, bsum, hist, g, dist, frank, rhist, lut, misc, end;
 };
 
-Layout layout(int64_t N) {
+Layout layout(int32_t W, int32_t H) {
+  const int64_t N = (int64_t)W * H;
+  // `dist` first holds the column pass's four per-segment arrays
+  const int64_t seg_words = 4LL * ((H + kSegRows - 1) / kSegRows) * W;
   Layout o{};
   size_t off = 0;
   auto take = [&](size_t bytes) { const size_t at = off; off += a256(bytes); return at; };
@@ -685,7 +801,7 @@ Layout layout(int64_t N) {
   o.bsum = take(((size_t)(N + kScanPer - 1) / kScanPer + 1) * 4);
   o.hist = take(256 * 8);
   o.g = take((size_t)N * 4);
-  o.dist = take((size_t)N * 4);
+  o.dist = take((size_t)std::max<int64_t>(N, seg_words) * 4);
   o.frank = take((size_t)N * 4);
   o.rhist = take(256 * 4);
   o.lut = take(256);
@@ -718,7 +834,7 @@ int sbs_lightness(const uint8_t* img, int32_t W, int32_t H, int32_t C, int64_t p
 
 size_t sbs_boundaries_workspace_bytes(int32_t W, int32_t H) {
   if (W < 1 || H < 1 || (int64_t)W * H > INT32_MAX) return 0;
-  return layout((int64_t)W * H).end;
+  return layout(W, H).end;
 }
 
 int sbs_boundaries(const uint8_t* img, int32_t W, int32_t H, int32_t C, int64_t pitch, int32_t K, int32_t mode,
@@ -733,7 +849,7 @@ int sbs_boundaries(const uint8_t* img, int32_t W, int32_t H, int32_t C, int64_t 
   if (H > 4 * 65535) return fail(SBS_ERR_UNSUPPORTED, "H > %d", 4 * 65535);   // 2-D stencil grid: 4 rows per block
   if (!(frac < 0.0) && !(frac <= 1.0)) return fail(SBS_ERR_INVALID_ARG, "frac must be < 0 (off) or in [0, 1]");
   const int64_t N = (int64_t)W * H;
-  const Layout Lo = layout(N);
+  const Layout Lo = layout(W, H);
   if (workspace_bytes < Lo.end) return fail(SBS_ERR_INVALID_ARG, "workspace too small");
   hipStream_t s = (hipStream_t)stream;
   char* base = (char*)workspace;
@@ -809,9 +925,10 @@ int sbs_boundaries(const uint8_t* img, int32_t W, int32_t H, int32_t C, int64_t 
     const long long want = std::min<long long>((long long)N, std::llround(frac * (double)N));
     const long long n0 = W == 1 ? H : 2LL * H;
     hipLaunchKernelGGL(k_fill, dim3(1), dim3(kBlock), 0, s, (uint8_t*)rhist, (int64_t)(256 * 4), (uint8_t)0);
-    hipLaunchKernelGGL(k_fc_count, dim3(g), dim3(kBlock), 0, s, c, n1);
+    uint8_t* cls = lab2;   // free once the refinement is done
+    hipLaunchKernelGGL(k_fc_class, dim3(g), dim3(kBlock), 0, s, c, cls, n1);
     hipLaunchKernelGGL(k_fc_plan, dim3(1), dim3(1), 0, s, fs, n1, want, n0);
-    c.fc = fs; c.dist = dist; c.frank = frank; c.seed = (unsigned long long)seed;
+    c.fc = fs; c.dist = dist; c.frank = frank; c.seed = (unsigned long long)seed; c.cls = cls;
     for (int sh = 24; sh >= 0; sh -= 8) {      // kept pixels: size descending
       hipLaunchKernelGGL(k_rs_hist<1>, dim3(g), dim3(kBlock), 0, s, c, &fs->s1, sh, rhist);
       hipLaunchKernelGGL(k_rs_pick, dim3(1), dim3(256), 0, s, &fs->s1, sh, rhist);
@@ -819,8 +936,20 @@ int sbs_boundaries(const uint8_t* img, int32_t W, int32_t H, int32_t C, int64_t 
     hipLaunchKernelGGL(k_scan_count<2>, dim3((unsigned)nb), dim3(kBlock), 0, s, c, bsum);
     hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, bsum, nb, (long long*)nullptr);
     hipLaunchKernelGGL(k_scan_apply<2>, dim3((unsigned)nb), dim3(kBlock), 0, s, c, bsum);
-    hipLaunchKernelGGL(k_dt_col, dim3((W + kBlock - 1) / kBlock), dim3(kBlock), 0, s, c, H, gcol);
-    hipLaunchKernelGGL(k_dt_row, dim3(g), dim3(kBlock), 0, s, c, gcol, dist);
+    {
+      // segment summaries live in `dist` until the column pass is done
+      const int nseg = (H + kSegRows - 1) / kSegRows;
+      const int64_t ns = (int64_t)nseg * W;
+      int32_t* last = dist;
+      int32_t* first = dist + ns;
+      int32_t* up = dist + 2 * ns;
+      int32_t* down = dist + 3 * ns;
+      const unsigned gs = (unsigned)((ns + kBlock - 1) / kBlock);
+      hipLaunchKernelGGL(k_dt_seg, dim3(gs), dim3(kBlock), 0, s, c, H, nseg, last, first);
+      hipLaunchKernelGGL(k_dt_carry, dim3((W + kBlock - 1) / kBlock), dim3(kBlock), 0, s, W, nseg, last, first, up, down);
+      hipLaunchKernelGGL(k_dt_col, dim3(gs), dim3(kBlock), 0, s, c, H, nseg, up, down, gcol);
+    }
+    hipLaunchKernelGGL(k_dt_row, dim3(H < 16384 ? H : 16384), dim3(kBlock), 0, s, c, H, gcol, dist);
     for (int sh = 24; sh >= 0; sh -= 8) {      // other pixels: distance
       hipLaunchKernelGGL(k_rs_hist<2>, dim3(g), dim3(kBlock), 0, s, c, &fs->s2, sh, rhist);
       hipLaunchKernelGGL(k_rs_pick, dim3(1), dim3(256), 0, s, &fs->s2, sh, rhist);

@@ -14,6 +14,13 @@ inputs stay resident in HBM from arrival to completion). The server:
 * completes a request when its batch's HIP event has fired, and records its
   latency (completion minus arrival).
 
+A request may also come as a raw frame without a list (``idx=None``, with a
+boundary fraction ``frac``): the server then runs the front end on the batch's
+stream first (lightness, histogram K-means, refinement, components, fraction
+control) into a list of exactly round(frac * W * H) pixels, whose length is
+known on the host, so nothing waits for the device. One front-end workspace
+per stream serves the batch's frames in turn and counts against the budget.
+
 Each request's result depends only on its own frame: it is the same alone and
 in any mix (the GPU tests check this bit for bit).
 """
@@ -31,11 +38,14 @@ class Request:
     rid: int
     left: object            # torch.uint8 [H, W] or [H, W, 3] on the GPU
     right: object
-    idx: object             # torch.int32 [n] on the GPU
+    idx: object             # torch.int32 [n] on the GPU, or None: list from the front end
     block: int
     dmax: int
     arrival: float = 0.0    # seconds on the server clock
     klass: str = ""
+    frac: float = 0.18      # raw frames: boundary fraction of the list the front end makes
+    K: int = 4              # raw frames: front-end clusters
+    seed: int = 0           # raw frames: fraction-control seed
     disp: object = None
     cost: object = None
     t_admit: float = -1.0
@@ -51,6 +61,7 @@ class _Batch:
     event: object
     stream: object
     nbytes: int
+    keep: list = field(default_factory=list)   # buffers the batch's kernels use until its event fires
 
 
 class BudgetError(RuntimeError):
@@ -84,14 +95,25 @@ class Server:
     def _frame(self, r: Request, disp, cost):
         return sbs.make_frame(r.left, r.right, r.idx, r.block, r.dmax, disp, cost)
 
+    def list_length(self, r: Request) -> int:
+        if r.idx is not None:
+            return r.idx.numel()
+        import math
+        N = r.left.shape[0] * r.left.shape[1]
+        return min(N, int(math.floor(r.frac * N + 0.5)))   # the front end's round-half-away length
+
     def footprint(self, r: Request) -> int:
-        n = r.idx.numel()
-        f = sbs.Frame(r.left.data_ptr(), r.right.data_ptr(), *sbs._image_args(r.left)[:3],
-                      sbs._image_args(r.left)[3], r.idx.data_ptr(), n, r.block, r.dmax, 1, None)
+        n = self.list_length(r)
+        W, H, C, pitch = sbs._image_args(r.left)
+        f = sbs.Frame(r.left.data_ptr(), r.right.data_ptr(), W, H, C, pitch, 1, max(n, 1), r.block, r.dmax, 1, None)
         ws = sbs.workspace_bytes([f])
         if ws == 0:
             raise ValueError(f"request {r.rid}: invalid frame")
-        return ws + n * (5 if self.with_cost else 1) + 4096
+        extra = 0
+        if r.idx is None:
+            # its list, plus (conservatively) a whole front-end workspace
+            extra = 4 * n + int(sbs.lib().sbs_boundaries_workspace_bytes(W, H))
+        return ws + n * (5 if self.with_cost else 1) + extra + 4096
 
     def submit(self, r: Request):
         r.footprint = self.footprint(r)
@@ -129,18 +151,36 @@ class Server:
             return False
         self.waiting = self.waiting[len(take):]
         t = self.now()
-        frames = []
-        for r in take:
-            n = r.idx.numel()
-            r.disp = torch.empty(n, dtype=torch.uint8, device=self.device)
-            r.cost = torch.empty(n, dtype=torch.int32, device=self.device) if self.with_cost else None
-            r.t_admit = t
-            frames.append(self._frame(r, r.disp, r.cost))
-        desc = (sbs.Frame * len(frames))(*frames)
-        nbytes = int(sbs.lib().sbs_workspace_bytes(desc, len(frames)))
         stream = self.streams[self._next_stream]
         self._next_stream = (self._next_stream + 1) % len(self.streams)
         stream.wait_stream(torch.cuda.current_stream())   # inputs and outputs were made on the caller's stream
+        frames = []
+        keep = []
+        with torch.cuda.stream(stream):
+            raw = [r for r in take if r.idx is None]
+            if raw:
+                # lists of the raw frames, on this stream, one shared workspace
+                fw = max(int(sbs.lib().sbs_boundaries_workspace_bytes(*sbs._image_args(r.left)[:2])) for r in raw)
+                fws = torch.empty(max(fw, 256), dtype=torch.uint8, device=self.device)
+                cnt = torch.empty(1, dtype=torch.int64, device=self.device)
+                keep += [fws, cnt]
+                for r in raw:
+                    W, H, C, pitch = sbs._image_args(r.left)
+                    r.idx = torch.empty(self.list_length(r), dtype=torch.int32, device=self.device)
+                    if r.idx.numel() == 0:
+                        continue
+                    sbs._check(sbs.lib().sbs_boundaries(r.left.data_ptr(), W, H, C, pitch, r.K, 0, 50, float(r.frac),
+                                                        r.seed & (2**64 - 1), r.idx.data_ptr(), cnt.data_ptr(), None,
+                                                        None, fws.data_ptr(), fws.numel(),
+                                                        ctypes.c_void_p(stream.cuda_stream)))
+            for r in take:
+                n = r.idx.numel()
+                r.disp = torch.empty(n, dtype=torch.uint8, device=self.device)
+                r.cost = torch.empty(n, dtype=torch.int32, device=self.device) if self.with_cost else None
+                r.t_admit = t
+                frames.append(self._frame(r, r.disp, r.cost))
+        desc = (sbs.Frame * len(frames))(*frames)
+        nbytes = int(sbs.lib().sbs_workspace_bytes(desc, len(frames)))
         with torch.cuda.stream(stream):
             ws = torch.empty(max(nbytes, 1024), dtype=torch.uint8, device=self.device)
             ws[:1024].zero_()
@@ -150,7 +190,7 @@ class Server:
             ev.record(stream)
         self.in_use += total
         self.peak_in_use = max(self.peak_in_use, self.in_use)
-        self.inflight.append(_Batch(take, ws, desc, ev, stream, total))
+        self.inflight.append(_Batch(take, ws, desc, ev, stream, total, keep))
         self.batches += 1
         return True
 

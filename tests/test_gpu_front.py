@@ -92,6 +92,15 @@ def test_front_end_degenerate_shapes(torch, sbs):
     const = np.full((60, 70), 90, np.uint8)
     lst = check(torch, sbs, const, 5, 0, what="constant")
     assert lst.size == 2 * 60   # border columns only
+    # fraction control on the same shapes (a few rows, one column, one pixel)
+    for (H, W) in [(1, 1), (1, 37), (41, 1), (2, 2), (3, 5), (3, 200)]:
+        img = rng.integers(0, 256, (H, W, 3), dtype=np.uint8)
+        d = torch.from_numpy(img).cuda()
+        for mode in (0, 1):
+            for frac in (0.0, 0.3, 0.5, 1.0):
+                got = sbs.boundaries(d, K=3, mode=mode, min_cc=1, frac=frac, seed=9).cpu().numpy().view(np.uint32)
+                exp = oracle.boundaries(img, K=3, mode=mode, min_cc=1, frac=frac, seed=9)
+                assert np.array_equal(got, exp), f"{H}x{W} mode {mode} frac {frac}"
 
 
 def test_front_end_list_feeds_the_disparity_search(torch, sbs):

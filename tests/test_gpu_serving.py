@@ -78,3 +78,34 @@ def test_poisson_trace_and_budget(env):
     tiny = Server(budget_bytes=1 << 16)
     with pytest.raises(BudgetError):
         tiny.submit(_requests(env, 1, [0.0])[0])
+
+
+def test_raw_frames_through_the_device_front_end(env):
+    """Requests that carry only their images: the server makes each list on the
+    device (front end with fraction control) before the disparity search.
+    Results equal the oracle's front end + SAD, alone and mixed with requests
+    that bring their own lists."""
+    torch, sbs, Request, Server, BudgetError, pool = env
+    reqs = []
+    for i in range(12):
+        sp, f, idx = pool[i % len(pool)]
+        L, R = torch.from_numpy(f.left).cuda(), torch.from_numpy(f.right).cuda()
+        if i % 3 == 2:
+            reqs.append(Request(i, L, R, torch.from_numpy(idx.view(np.int32)).cuda(), sp.block, sp.dmax, 0.0, "list"))
+        else:
+            reqs.append(Request(i, L, R, None, sp.block, sp.dmax, 0.0, "raw", frac=0.1 + 0.01 * i, seed=100 + i))
+    srv = Server(budget_bytes=256 << 20, max_inflight=2, max_batch=4)
+    srv.run_trace(reqs)
+    for r in reqs:
+        if r.klass != "raw":
+            continue
+        sp = pool[r.rid % len(pool)][0]
+        Lh = r.left.cpu().numpy()
+        exp_idx = oracle.boundaries(Lh, K=4, mode=0, min_cc=50, frac=r.frac, seed=r.seed)
+        np.testing.assert_array_equal(r.idx.cpu().numpy().view(np.uint32), exp_idx)
+        d, c, _ = oracle.sad(Lh, r.right.cpu().numpy(), exp_idx, r.block, r.dmax)
+        np.testing.assert_array_equal(r.disp.cpu().numpy(), d)
+        np.testing.assert_array_equal(r.cost.cpu().numpy().view(np.uint32), c)
+        d1, c1 = sbs.sad_disparity(r.left, r.right, r.idx, r.block, r.dmax)
+        torch.cuda.synchronize()
+        assert torch.equal(r.disp, d1) and torch.equal(r.cost, c1)
