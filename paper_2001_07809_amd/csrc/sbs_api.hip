@@ -347,7 +347,7 @@ int run(const sbs_frame* frames, int nframes, void* workspace, size_t ws_bytes, 
     d.n = f.n;
     d.W = f.W; d.H = f.H; d.C = f.C;
     d.r = (f.block - 1) / 2;
-    d.pack = (int64_t)f.block * 255 * f.C <= 65535 ? 1 : 0;
+    d.pack = 2 * (int64_t)f.block * 255 * f.C <= 65535 ? 1 : 0;
     d.dmax = f.dmax;
     d.lpw = L.lpw; d.rpw = L.rpw; d.ph = L.ph; d.lpad = L.lpad; d.rpad = L.rpad; d.rbw = L.rbw;
     d.txo = L.txo;

@@ -43,7 +43,7 @@ struct FrameDev {
   int32_t ntx, nty;      // tiles per row / column
   int32_t nch, chunk;    // disparity chunks and their size
   int32_t tpw;           // entries per row of tptr (ntx + 1)
-  int32_t pack;          // 1: a window column's sum (<= block * 255 * C) fits in 16 bits
+  int32_t pack;          // 1: the sum of two window columns (<= 2 * block * 255 * C) fits in 16 bits
 };
 
 struct DescBatch {

@@ -50,6 +50,7 @@ __device__ __forceinline__ uint32_t load_px(const uint8_t* row, int x, int C) {
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(1))) const u32x4 g_uint4;
 typedef unsigned int u32x3 __attribute__((ext_vector_type(3)));
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
 typedef __attribute__((address_space(1))) const u32x3 g_uint3;
 typedef __attribute__((address_space(1))) const int32_t g_int32;
 typedef __attribute__((address_space(1))) const uint32_t g_uint32;
@@ -306,8 +307,8 @@ __device__ __forceinline__ void spread_row(RowRegs<DC>& o) {
 
 // Accumulators per lane: kPack == false keeps one 32-bit sum per (column,
 // disparity); kPack == true keeps disparities d0 + 2j and d0 + 2j + 1 of a
-// column in the low and high 16 bits of one register (usable while a window
-// column's sum, at most block * 255 * C, fits in 16 bits).
+// column in the low and high 16 bits of one register (usable while the sum of
+// two window columns, at most 2 * block * 255 * C, fits in 16 bits).
 template <int DC, bool kPack>
 struct Acc {
   static constexpr int N = kPack ? DC / 2 : DC;
@@ -316,6 +317,19 @@ struct Acc {
   __device__ __forceinline__ uint32_t get(int c, int k) const {
     if constexpr (kPack) return (k & 1) ? (v[c][k >> 1] >> 16) : (v[c][k >> 1] & 0xFFFFu);
     else return v[c][k];
+  }
+  // sums over the lane's four columns of disparities d0 + k and d0 + k + 1 (k even)
+  __device__ __forceinline__ void total2(int k, uint32_t& t0, uint32_t& t1) const {
+    if constexpr (kPack) {
+      // column pairs added as 16-bit halves (no carry out of a half), then widened
+      const u16x2 a = __builtin_bit_cast(u16x2, v[0][k >> 1]) + __builtin_bit_cast(u16x2, v[1][k >> 1]);
+      const u16x2 b = __builtin_bit_cast(u16x2, v[2][k >> 1]) + __builtin_bit_cast(u16x2, v[3][k >> 1]);
+      t0 = (uint32_t)a.x + (uint32_t)b.x;
+      t1 = (uint32_t)a.y + (uint32_t)b.y;
+    } else {
+      t0 = v[0][k] + v[1][k] + v[2][k] + v[3][k];
+      t1 = v[0][k + 1] + v[1][k + 1] + v[2][k + 1] + v[3][k + 1];
+    }
   }
 };
 
@@ -521,9 +535,8 @@ __device__ __forceinline__ void tile_item_impl(const FrameDev& f, int tile, int 
       // its last column; the three columns before follow by subtraction, so
       // no in-lane prefixes stay live across the scan.
       uint32_t t[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-        t[i] = acc.get(0, g + k0 + i) + acc.get(1, g + k0 + i) + acc.get(2, g + k0 + i) + acc.get(3, g + k0 + i);
+      acc.total2(g + k0, t[0], t[1]);
+      acc.total2(g + k0 + 2, t[2], t[3]);
       wave_incl_scan4(t[0], t[1], t[2], t[3]);
 #pragma unroll
       for (int i = 0; i < 4; ++i) {

@@ -277,11 +277,12 @@ def test_graph_capture_replays(torch, sbs):
 
 
 def test_saturated_sums_at_the_16_bit_accumulator_limit(torch, sbs):
-    """Blocks on both sides of the packed-accumulator bound (block * 255 * C <= 65535),
-    images at 0 and 255 so window column sums reach their maximum."""
+    """Blocks on both sides of the packed-accumulator bound (2 * block * 255 * C
+    <= 65535: two window columns added in 16-bit halves), images at 0 and 255
+    so window column sums reach their maximum."""
     rng = np.random.default_rng(21)
     H, W = 180, 140
-    for C, blocks in [(3, (41, 43, 83, 85, 87)), (1, (127,))]:
+    for C, blocks in [(3, (41, 43, 83, 85, 87)), (1, (125, 127))]:
         shape = (H, W, C) if C == 3 else (H, W)
         L = (rng.integers(0, 2, shape) * 255).astype(np.uint8)
         L[:, : W // 2] = 255
