@@ -23,8 +23,8 @@ hipError_t launch_put_desc(FrameDev* table, const FrameDev* host, int nframes, h
 hipError_t launch_prologue(const FrameDev* table, int f0, int nf, int max_rows, int max_tptr, WsHeader* hdr,
                            hipStream_t s);
 hipError_t launch_finalize(const FrameDev* table, int f0, int nf, hipStream_t s);
-hipError_t launch_tile_grid(const FrameDev* table, int fi, int64_t nitems, int chunk, hipStream_t s);
-hipError_t launch_tile_persistent(const FrameDev* table, int nframes, const QueueTotals& totals, int chunk,
+hipError_t launch_tile_grid(const FrameDev* table, int fi, int64_t nitems, int chunk, bool wide, hipStream_t s);
+hipError_t launch_tile_persistent(const FrameDev* table, int nframes, const QueueTotals& totals, int chunk, bool wide,
                                   int grid, WsHeader* hdr, hipStream_t s);
 hipError_t launch_ref(const uint8_t* L, const uint8_t* R, int W, int H, int C, int64_t pitch, const uint32_t* idx,
                       int64_t n, int r, int dmax, uint8_t* od, uint32_t* oc, uint32_t* err, hipStream_t s);
@@ -112,12 +112,21 @@ std::string plan_key(const sbs_frame& f) {
   return o.str();
 }
 
-// Work items of frame f with a given disparity chunk and tile height.
-int64_t items_of(const sbs_frame& f, int chunk, int ty) {
+bool packs(const sbs_frame& f) { return 2 * (int64_t)f.block * 255 * f.C <= 65535; }
+
+// Window columns per lane that frame f runs with under plan p: 8 needs
+// 8-disparity chunks, packed accumulators and row list ranges that fit the
+// tile kernel's packing (tile rows x W < 2^23); 4 otherwise.
+int cpl_of(const sbs_frame& f, int plan_cpl, int chunk, int ty) {
+  return plan_cpl == 8 && chunk == 8 && packs(f) && (int64_t)ty * f.W < (1LL << 23) ? 8 : 4;
+}
+
+// Work items of frame f with a given disparity chunk, tile height and lane width.
+int64_t items_of(const sbs_frame& f, int chunk, int ty, int cpl = 4) {
   if (f.n <= 0) return 0;
   const int r = (f.block - 1) / 2;
   const int lpad = (r + 3) & ~3;
-  const int txo = (kSpan - lpad - r) & ~3;
+  const int txo = (kWave * cpl_of(f, cpl, chunk, ty) - lpad - r) & ~3;
   return (int64_t)((f.W + txo - 1) / txo) * ((f.H + ty - 1) / ty) * ((f.dmax + chunk) / chunk);
 }
 
@@ -131,7 +140,7 @@ int64_t items_of(const sbs_frame& f, int chunk, int ty) {
 Plan default_plan(const sbs_frame* frames, int nframes) {
   auto items = [&](int chunk, int ty) {
     int64_t t = 0;
-    for (int i = 0; i < nframes; ++i) t += items_of(frames[i], chunk, ty);
+    for (int i = 0; i < nframes; ++i) t += items_of(frames[i], chunk, ty, 4);
     return t;
   };
   const int64_t want = 4LL * 256 * 16;
@@ -183,16 +192,20 @@ struct FrameLayout {
   int lpw, rpw, ph, lpad, rpad, rbw, txo, ntx, tpw;
 };
 
-FrameLayout frame_layout(const sbs_frame& f, size_t base) {
+// Layout of one frame's part of the workspace for tiles of `span` window
+// columns (64 x columns per lane); a tile's window columns start lpad >= r
+// columns left of its first output column.
+FrameLayout frame_layout(const sbs_frame& f, size_t base, int span) {
   FrameLayout L;
   const int r = (f.block - 1) / 2;
   // Left copy: image column c at c + lpad; right copy: at c + rpad. Both pads
   // are multiples of 4 so 4-pixel groups stay 16-byte aligned; rpad leaves room
-  // for the largest disparity chunk to the left of column 0.
+  // for the largest disparity chunk to the left of column 0. A tile reads
+  // `span` columns from its first window column on.
   L.lpad = (r + 3) & ~3;
   L.rpad = (L.lpad + f.dmax + kMaxChunk + 1 + 3) & ~3;
-  L.lpw = (int)align_up((size_t)f.W + kSpan, 64);
-  L.rpw = (int)align_up((size_t)f.W + kSpan + L.rpad, 64);
+  L.lpw = (int)align_up((size_t)f.W + span, 64);
+  L.rpw = (int)align_up((size_t)f.W + span + L.rpad, 64);
   L.ph = f.H + 2 * r;
   const int groups = (f.W + 63) / 64;
   L.rbw = (groups + 63) / 64;
@@ -203,7 +216,7 @@ FrameLayout frame_layout(const sbs_frame& f, size_t base) {
   L.lp_off = o; o = align_up(o + (size_t)L.lpw * (L.ph + 1) * 4, 256);
   L.rp_off = o; o = align_up(o + (size_t)L.rpw * (L.ph + 1) * 4, 256);
   L.rb_off = o; o = align_up(o + (size_t)f.H * L.rbw * 8, 256);
-  L.txo = (kSpan - L.lpad - r) & ~3;
+  L.txo = (span - L.lpad - r) & ~3;
   L.ntx = (f.W + L.txo - 1) / L.txo;
   L.tpw = L.ntx + 1;
   L.state_off = o; o = align_up(o + 4, 256);
@@ -214,9 +227,11 @@ FrameLayout frame_layout(const sbs_frame& f, size_t base) {
 
 size_t table_bytes(int nframes) { return align_up(sizeof(FrameDev) * (size_t)std::max(nframes, 1), 256); }
 
-size_t total_bytes(const sbs_frame* frames, int nframes) {
+// Workspace bytes for frames laid out with `spans[i]` window columns per
+// tile (NULL: the widest tiles, which bounds every plan).
+size_t total_bytes(const sbs_frame* frames, int nframes, const int* spans = nullptr) {
   size_t o = kHeaderBytes + table_bytes(nframes);
-  for (int i = 0; i < nframes; ++i) o = frame_layout(frames[i], o).end;
+  for (int i = 0; i < nframes; ++i) o = frame_layout(frames[i], o, spans ? spans[i] : kMaxSpan).end;
   return o;
 }
 
@@ -299,7 +314,19 @@ int run(const sbs_frame* frames, int nframes, void* workspace, size_t ws_bytes, 
   int cus = 0;
   int st = device_check(&cus);
   if (st != SBS_OK) return st;
-  const size_t need = total_bytes(frames, nframes);
+
+  // One plan per call (from the first frame with work): the persistent kernel is one instance.
+  int lead = 0;
+  while (lead < nframes && frames[lead].n == 0) ++lead;
+  // One launch covers all frames in the batched kernel, one frame otherwise.
+  const Plan plan = mode == kBatched ? choose_plan(frames, nframes, frames[lead])
+                                     : choose_plan(frames + lead, 1, frames[lead]);
+  std::vector<int> cpl((size_t)nframes), span((size_t)nframes);
+  for (int i = 0; i < nframes; ++i) {
+    cpl[(size_t)i] = cpl_of(frames[i], plan.cpl, plan.chunk, plan.ty);
+    span[(size_t)i] = kWave * cpl[(size_t)i];
+  }
+  const size_t need = total_bytes(frames, nframes, span.data());
   if (workspace) {
     if (ws_bytes < need)
       return fail(SBS_ERR_INVALID_ARG, "workspace of %zu bytes < %zu needed", ws_bytes, need);
@@ -312,13 +339,6 @@ int run(const sbs_frame* frames, int nframes, void* workspace, size_t ws_bytes, 
   WsHeader* hdr = (WsHeader*)base;
   FrameDev* table = (FrameDev*)(base + kHeaderBytes);
 
-  // One plan per call (from the first frame with work): the persistent kernel is one instance.
-  int lead = 0;
-  while (lead < nframes && frames[lead].n == 0) ++lead;
-  // One launch covers all frames in the batched kernel, one frame otherwise.
-  const Plan plan = mode == kBatched ? choose_plan(frames, nframes, frames[lead])
-                                     : choose_plan(frames + lead, 1, frames[lead]);
-
   std::vector<FrameDev> host((size_t)nframes);
   size_t off = kHeaderBytes + table_bytes(nframes);
   int64_t items = 0;
@@ -326,7 +346,7 @@ int run(const sbs_frame* frames, int nframes, void* workspace, size_t ws_bytes, 
   int max_rows = 1, max_tptr = 1;
   for (int i = 0; i < nframes; ++i) {
     const sbs_frame& f = frames[i];
-    FrameLayout L = frame_layout(f, off);
+    FrameLayout L = frame_layout(f, off, span[(size_t)i]);
     off = L.end;
     FrameDev& d = host[(size_t)i];
     std::memset(&d, 0, sizeof d);
@@ -347,7 +367,8 @@ int run(const sbs_frame* frames, int nframes, void* workspace, size_t ws_bytes, 
     d.n = f.n;
     d.W = f.W; d.H = f.H; d.C = f.C;
     d.r = (f.block - 1) / 2;
-    d.pack = 2 * (int64_t)f.block * 255 * f.C <= 65535 ? 1 : 0;
+    d.pack = packs(f) ? 1 : 0;
+    d.cpl = cpl[(size_t)i];
     d.dmax = f.dmax;
     d.lpw = L.lpw; d.rpw = L.rpw; d.ph = L.ph; d.lpad = L.lpad; d.rpad = L.rpad; d.rbw = L.rbw;
     d.txo = L.txo;
@@ -377,7 +398,7 @@ int run(const sbs_frame* frames, int nframes, void* workspace, size_t ws_bytes, 
       if (e != hipSuccess) return hip_fail(e, "prologue");
       hipEvent_t ev;
       timing_begin(s, &ev);
-      e = launch_tile_grid(table, i, host[(size_t)i].nitems, plan.chunk, s);
+      e = launch_tile_grid(table, i, host[(size_t)i].nitems, plan.chunk, cpl[(size_t)i] == 8, s);
       timing_end(s, ev);
       if (e != hipSuccess) return hip_fail(e, "tile kernel");
       e = launch_finalize(table, i, 1, s);
@@ -386,11 +407,13 @@ int run(const sbs_frame* frames, int nframes, void* workspace, size_t ws_bytes, 
   } else {
     e = launch_prologue(table, 0, nframes, max_rows, max_tptr, hdr, s);
     if (e != hipSuccess) return hip_fail(e, "prologue");
-    int64_t grid = (int64_t)cus * plan.wpc;
+    const bool wide = std::find(cpl.begin(), cpl.end(), 8) != cpl.end();
+    // wide launches hold at most 12 wavefronts per CU (3 per SIMD)
+    int64_t grid = (int64_t)cus * (wide ? std::min(plan.wpc, 12) : plan.wpc);
     if (grid > items) grid = items;
     hipEvent_t ev;
     timing_begin(s, &ev);
-    e = launch_tile_persistent(table, nframes, qt, plan.chunk, (int)std::max<int64_t>(grid, 1), hdr, s);
+    e = launch_tile_persistent(table, nframes, qt, plan.chunk, wide, (int)std::max<int64_t>(grid, 1), hdr, s);
     timing_end(s, ev);
     if (e != hipSuccess) return hip_fail(e, "persistent tile kernel");
     e = launch_finalize(table, 0, nframes, s);
@@ -463,7 +486,8 @@ int save_cache(const char* path) {
 }
 
 bool plan_valid(const Plan& p) {
-  return p.cpl == 4 && (p.chunk == 8 || p.chunk == 16) && p.ty >= 8 && p.ty <= 128 && p.wpc >= 1 && p.wpc <= 16;
+  return (p.cpl == 4 || (p.cpl == 8 && p.chunk == 8)) && (p.chunk == 8 || p.chunk == 16) && p.ty >= 8 &&
+         p.ty <= 128 && p.wpc >= 1 && p.wpc <= 16;
 }
 
 }  // namespace
@@ -616,14 +640,14 @@ int sbs_tune(const sbs_frame* frames, int32_t nframes, const char* cache_path) {
   hipEventCreate(&b);
   Plan best;
   float best_ms = 1e30f;
-  const int chunks[] = {8, 16};
+  const int shapes[][2] = {{4, 8}, {4, 16}, {8, 8}};   // (columns per lane, disparity chunk)
   const int rows[] = {32, 64, 128};
   const int wpcs[] = {4, 8, 16};
-  for (int ch : chunks)
+  for (const auto& sh : shapes)
     for (int ty : rows)
       for (int w : wpcs) {
         Plan p;
-        p.chunk = ch; p.ty = ty; p.wpc = w;
+        p.cpl = sh[0]; p.chunk = sh[1]; p.ty = ty; p.wpc = w;
         {
           std::lock_guard<std::mutex> lk(g_mu);
           g_forced = true;

@@ -7,10 +7,8 @@
 namespace sbs {
 
 constexpr int kWave = 64;
-constexpr int kColsPerLane = 4;            // CAD columns owned by one lane
-constexpr int kSpan = kWave * kColsPerLane;  // CAD columns per tile (256)
+constexpr int kMaxSpan = kWave * 8;        // window columns of a tile at 8 columns per lane (512)
 constexpr int kMaxChunk = 16;         // largest disparity chunk a kernel instance handles
-constexpr int kGroup = 8;             // disparities whose prefix sums share the LDS at once
 constexpr int kDescPerLaunch = 8;          // descriptors carried by one upload kernel
 constexpr uint32_t kUnsorted = 1u;         // FrameDev::state bit
 constexpr int kQueues = 8;                 // one work queue per XCD; tile t's items go to queue t % 8
@@ -44,6 +42,7 @@ struct FrameDev {
   int32_t nch, chunk;    // disparity chunks and their size
   int32_t tpw;           // entries per row of tptr (ntx + 1)
   int32_t pack;          // 1: the sum of two window columns (<= 2 * block * 255 * C) fits in 16 bits
+  int32_t cpl;           // window columns per lane: 4, or 8 (ordered lists, 8-disparity chunks, pack == 1)
 };
 
 struct DescBatch {

@@ -225,122 +225,174 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
 // Keeps the row loop's steps in program order: an empty instruction that
 // takes every accumulator as operand and clobbers memory, so neither the
 // arithmetic on the accumulators nor loads and LDS traffic move across it.
-template <int N>
-__device__ __forceinline__ void pin_step(uint32_t (&v)[kColsPerLane][N]) {
+template <int COLS, int N>
+__device__ __forceinline__ void pin_step(uint32_t (&v)[COLS][N]) {
 #pragma unroll
-  for (int c = 0; c < kColsPerLane; ++c)
+  for (int c = 0; c < COLS; ++c)
 #pragma unroll
     for (int k = 0; k < N; k += 4)
       asm volatile("" : "+v"(v[c][k]), "+v"(v[c][k + 1]), "+v"(v[c][k + 2]), "+v"(v[c][k + 3])::"memory");
 }
 
-// LDS of one work item: prefix sums for the chunk's DC disparities and, for
-// unordered lists, the current row's listed pixels. pre[k][4 + j] is the
-// inclusive prefix sum over window columns 0..j; pre[k][0..3] stay zero, so a
-// window that starts at column 0 needs no special case.
-struct TileLds {
-  uint32_t pre[kGroup][kSpan + 4] __attribute__((aligned(16)));   // one group of 8 disparities at a time
+// Tile geometry of one lane width: COLS window columns per lane, a span of
+// 64 * COLS window columns per wavefront, and G disparities whose prefix sums
+// share the LDS at once (8 for 4 columns per lane, 4 for 8, so the LDS of one
+// wavefront stays under 10 KB and 16 wavefronts fit a CU).
+template <int COLS>
+struct Geom {
+  static constexpr int kSpanC = kWave * COLS;
+  static constexpr int G = COLS == 8 ? 4 : 8;
+  static constexpr int kTpShift = COLS == 8 ? 9 : 8;   // row ranges: count < 2^kTpShift
+};
+
+// LDS of one work item: prefix sums for G disparities and, for unordered
+// lists (4 columns per lane only), the current row's listed pixels.
+// pre[k][4 + j] is the inclusive prefix sum over window columns 0..j;
+// pre[k][0..3] are zero (written at the start of every item), so a window
+// that starts at column 0 needs no special case.
+struct TileLds4 {
+  uint32_t pre[8][kWave * 4 + 4] __attribute__((aligned(16)));
   union {
     struct {
-      int16_t eo[kSpan];       // unordered lists: listed pixels of the row (output column offset)
-      int32_t es[kSpan];       //                  and their representative slots
+      int16_t eo[kWave * 4];   // unordered lists: listed pixels of the row (output column offset)
+      int32_t es[kWave * 4];   //                  and their representative slots
     };
     uint32_t tp[128];          // ordered lists: list range of each row of the tile, packed
   };
 };
+struct TileLds8 {
+  uint32_t pre[4][kWave * 8 + 4] __attribute__((aligned(16)));
+  uint32_t tp[128];
+};
+union TileLds {
+  TileLds4 n;
+  TileLds8 w;
+};
+template <int COLS> struct LdsOf;
+template <> struct LdsOf<4> { static __device__ __forceinline__ TileLds4& get(TileLds& s) { return s.n; } };
+template <> struct LdsOf<8> { static __device__ __forceinline__ TileLds8& get(TileLds& s) { return s.w; } };
 
 typedef __attribute__((address_space(3))) u32x4 lds_u32x4;
 
-// The pixels one lane needs from one padded row: its four left columns, and
-// the DC + 4 right columns that pair with them over the chunk (right index
-// c + DC - k pairs with left column c at disparity d0 + k; index 0 is never
-// used). The right columns of lane l are the 4-word blocks l .. l + DC/4 of
-// the wave's span; lane l loads only block l + DC/4 and takes the lower
-// blocks from lanes l - 1, l - 2, ... with DPP wave shifts, while lane 0
-// loads the blocks below the span itself (spread_row). That halves the
-// load traffic for DC = 8.
-template <int DC>
+// The tile kernels run one wavefront per workgroup, and one wavefront's LDS
+// operations complete in the order it issues them: a value one lane writes
+// is seen by any later read of another lane. Ordering LDS traffic between
+// phases of an item therefore needs only the compiler to keep the order (no
+// wait for the writes to finish).
+__device__ __forceinline__ void wave_lds_order() { asm volatile("" ::: "memory"); }
+
+// The pixels one lane needs from one padded row: its COLS left columns, and
+// the DC + COLS right columns that pair with them over the chunk (right
+// index c + DC - k pairs with left column c at disparity d0 + k; index 0 is
+// never used). Lane l's right words start at word COLS * l of the wave's
+// span, so its words 0 .. DC - 1 are words COLS .. DC + COLS - 1 of lane
+// l - 1: each lane loads only its top COLS words and takes the lower ones
+// from lane l - 1 with DPP wave shifts, while lane 0 loads the words below
+// the span itself (spread_row). The lower words are only written by those
+// loads (lane 0) and the shifts (other lanes): callers keep a RowRegs alive
+// across rows, so no lane needs them cleared.
+template <int DC, int COLS>
 struct RowRegs {
-  uint32_t L[4];
-  uint32_t R[DC + 4];
+  uint32_t L[COLS];
+  uint32_t R[DC + COLS];
 };
 
-template <int DC>
-__device__ __forceinline__ void load_row(const uint32_t* lrow, const uint32_t* rrow, uint32_t lo, RowRegs<DC>& o) {
+template <int DC, int COLS>
+__device__ __forceinline__ void load_row(const uint32_t* lrow, const uint32_t* rrow, uint32_t lo,
+                                         RowRegs<DC, COLS>& o) {
   // lrow, rrow: the wave's row bases (uniform); lo: this lane's word offset
-  const u32x4 lv = *(g_uint4*)(lrow + lo);
-  o.L[0] = lv.x; o.L[1] = lv.y; o.L[2] = lv.z; o.L[3] = lv.w;
-  const u32x4 t = *(g_uint4*)(rrow + lo + DC);
-  o.R[DC] = t.x; o.R[DC + 1] = t.y; o.R[DC + 2] = t.z; o.R[DC + 3] = t.w;
-  o.R[0] = 0u;   // never used
 #pragma unroll
-  for (int q = 0; q < DC / 4; ++q) {
-    if (q > 0) o.R[4 * q + 0] = __builtin_nondeterministic_value(0u);
-    o.R[4 * q + 1] = __builtin_nondeterministic_value(0u);
-    o.R[4 * q + 2] = __builtin_nondeterministic_value(0u);
-    o.R[4 * q + 3] = __builtin_nondeterministic_value(0u);
+  for (int b = 0; b < COLS / 4; ++b) {
+    const u32x4 lv = *(g_uint4*)(lrow + lo + 4 * b);
+    o.L[4 * b] = lv.x; o.L[4 * b + 1] = lv.y; o.L[4 * b + 2] = lv.z; o.L[4 * b + 3] = lv.w;
+  }
+#pragma unroll
+  for (int b = 0; b < COLS / 4; ++b) {
+    const u32x4 t = *(g_uint4*)(rrow + lo + DC + 4 * b);
+    o.R[DC + 4 * b] = t.x; o.R[DC + 4 * b + 1] = t.y; o.R[DC + 4 * b + 2] = t.z; o.R[DC + 4 * b + 3] = t.w;
   }
   if (lo == 0) {
-    // block 0 without its unused first word
-    const u32x3 b0 = *(g_uint3*)(rrow + 1);
-    o.R[1] = b0.x; o.R[2] = b0.y; o.R[3] = b0.z;
+    // words 0 .. DC - 1 as whole aligned blocks. Word 0 is never used in the
+    // sums, but it is loaded and kept (spread_row) so that every load writes
+    // only live registers: a dead load destination that the compiler reused
+    // for other work would make it wait for the load, and with it for every
+    // load issued before it.
 #pragma unroll
-    for (int q = 1; q < DC / 4; ++q) {
+    for (int q = 0; q < DC / 4; ++q) {
       const u32x4 b = *(g_uint4*)(rrow + 4 * q);
       o.R[4 * q + 0] = b.x; o.R[4 * q + 1] = b.y; o.R[4 * q + 2] = b.z; o.R[4 * q + 3] = b.w;
     }
   }
 }
 
-// Completes the right columns once the loads of load_row have arrived: block
-// q of lane l is block q + 1 of lane l - 1 (DPP wave_shr:1; lane 0 keeps its
-// own load).
-template <int DC>
-__device__ __forceinline__ void spread_row(RowRegs<DC>& o) {
+// A RowRegs whose lower right words start with some value (they are only
+// read after load_row and spread_row have written them).
+template <int DC, int COLS>
+__device__ __forceinline__ void init_row(RowRegs<DC, COLS>& o) {
+#pragma unroll
+  for (int j = 0; j < DC; ++j) o.R[j] = __builtin_nondeterministic_value(0u);
+}
+
+// Completes the right columns once the loads of load_row have arrived: word
+// 1 <= j < DC of lane l is word j + COLS of lane l - 1 (DPP wave_shr:1; lane
+// 0 keeps its own load). Blocks of four go from the top down, so a source
+// word below DC has been completed before it is read.
+template <int DC, int COLS>
+__device__ __forceinline__ void spread_row(RowRegs<DC, COLS>& o) {
+  asm volatile("" ::"v"(o.R[0]));   // keeps word 0 live up to here (load_row)
 #pragma unroll
   for (int q = DC / 4 - 1; q >= 0; --q)
 #pragma unroll
     for (int w = (q == 0 ? 1 : 0); w < 4; ++w)
-      o.R[4 * q + w] = (uint32_t)__builtin_amdgcn_update_dpp((int)o.R[4 * q + w], (int)o.R[4 * q + 4 + w], 0x138, 0xf, 0xf,
-                                                             false);
+      o.R[4 * q + w] = (uint32_t)__builtin_amdgcn_update_dpp((int)o.R[4 * q + w], (int)o.R[4 * q + w + COLS], 0x138,
+                                                             0xf, 0xf, false);
 }
 
 // Accumulators per lane: kPack == false keeps one 32-bit sum per (column,
 // disparity); kPack == true keeps disparities d0 + 2j and d0 + 2j + 1 of a
 // column in the low and high 16 bits of one register (usable while the sum of
 // two window columns, at most 2 * block * 255 * C, fits in 16 bits).
-template <int DC, bool kPack>
+template <int DC, bool kPack, int COLS>
 struct Acc {
   static constexpr int N = kPack ? DC / 2 : DC;
-  uint32_t v[kColsPerLane][N];
-  // window column 4 lane + c, disparity d0 + k
+  uint32_t v[COLS][N];
+  // window column COLS * lane + c, disparity d0 + k
   __device__ __forceinline__ uint32_t get(int c, int k) const {
     if constexpr (kPack) return (k & 1) ? (v[c][k >> 1] >> 16) : (v[c][k >> 1] & 0xFFFFu);
     else return v[c][k];
   }
-  // sums over the lane's four columns of disparities d0 + k and d0 + k + 1 (k even)
+  // sums over the lane's columns of disparities d0 + k and d0 + k + 1 (k even)
   __device__ __forceinline__ void total2(int k, uint32_t& t0, uint32_t& t1) const {
     if constexpr (kPack) {
       // column pairs added as 16-bit halves (no carry out of a half), then widened
-      const u16x2 a = __builtin_bit_cast(u16x2, v[0][k >> 1]) + __builtin_bit_cast(u16x2, v[1][k >> 1]);
-      const u16x2 b = __builtin_bit_cast(u16x2, v[2][k >> 1]) + __builtin_bit_cast(u16x2, v[3][k >> 1]);
-      t0 = (uint32_t)a.x + (uint32_t)b.x;
-      t1 = (uint32_t)a.y + (uint32_t)b.y;
+      t0 = 0u;
+      t1 = 0u;
+#pragma unroll
+      for (int p = 0; p < COLS / 2; ++p) {
+        const u16x2 a = __builtin_bit_cast(u16x2, v[2 * p][k >> 1]) + __builtin_bit_cast(u16x2, v[2 * p + 1][k >> 1]);
+        t0 += (uint32_t)a.x;
+        t1 += (uint32_t)a.y;
+      }
     } else {
-      t0 = v[0][k] + v[1][k] + v[2][k] + v[3][k];
-      t1 = v[0][k + 1] + v[1][k + 1] + v[2][k + 1] + v[3][k + 1];
+      t0 = 0u;
+      t1 = 0u;
+#pragma unroll
+      for (int c = 0; c < COLS; ++c) {
+        t0 += v[c][k];
+        t1 += v[c][k + 1];
+      }
     }
   }
 };
 
 // Adds one padded row to the accumulators.
-template <int DC, bool kPack>
-__device__ __forceinline__ void add_row(RowRegs<DC>& a, Acc<DC, kPack>& acc) {
-  spread_row<DC>(a);
+template <int DC, bool kPack, int COLS>
+__device__ __forceinline__ void add_row(RowRegs<DC, COLS>& a, Acc<DC, kPack, COLS>& acc) {
+  spread_row<DC, COLS>(a);
 #pragma unroll
-  for (int c = 0; c < kColsPerLane; ++c)
+  for (int c = 0; c < COLS; ++c)
 #pragma unroll
-    for (int j = 0; j < Acc<DC, kPack>::N; ++j) {
+    for (int j = 0; j < Acc<DC, kPack, COLS>::N; ++j) {
       if constexpr (kPack)
         acc.v[c][j] = __builtin_amdgcn_sad_hi_u8(a.L[c], a.R[c + DC - 2 * j - 1],
                                                  __builtin_amdgcn_sad_u8(a.L[c], a.R[c + DC - 2 * j], acc.v[c][j]));
@@ -351,14 +403,14 @@ __device__ __forceinline__ void add_row(RowRegs<DC>& a, Acc<DC, kPack>& acc) {
 
 // Moves the window down one row: padded row `ex` leaves, `en` enters. The
 // leaving row is taken off first, so no partial sum exceeds a full window.
-template <int DC, bool kPack>
-__device__ __forceinline__ void slide_row(RowRegs<DC>& en, RowRegs<DC>& ex, Acc<DC, kPack>& acc) {
-  spread_row<DC>(en);
-  spread_row<DC>(ex);
+template <int DC, bool kPack, int COLS>
+__device__ __forceinline__ void slide_row(RowRegs<DC, COLS>& en, RowRegs<DC, COLS>& ex, Acc<DC, kPack, COLS>& acc) {
+  spread_row<DC, COLS>(en);
+  spread_row<DC, COLS>(ex);
 #pragma unroll
-  for (int c = 0; c < kColsPerLane; ++c)
+  for (int c = 0; c < COLS; ++c)
 #pragma unroll
-    for (int j = 0; j < Acc<DC, kPack>::N; ++j) {
+    for (int j = 0; j < Acc<DC, kPack, COLS>::N; ++j) {
       if constexpr (kPack) {
         const uint32_t out = __builtin_amdgcn_sad_hi_u8(ex.L[c], ex.R[c + DC - 2 * j - 1],
                                                         __builtin_amdgcn_sad_u8(ex.L[c], ex.R[c + DC - 2 * j], 0u));
@@ -372,32 +424,60 @@ __device__ __forceinline__ void slide_row(RowRegs<DC>& en, RowRegs<DC>& ex, Acc<
     }
 }
 
-// One work item: tile `tile` (row-major over the frame's ntx x nty tiles),
-// disparity chunk `chunk` (disparities chunk*DC .. +DC-1).
-template <int DC, bool kSorted, bool kPack>
-__device__ __forceinline__ void tile_item_impl(const FrameDev& f, int tile, int chunk, TileLds& sm) {
-  const int lane = threadIdx.x;
+// One pass over output columns [xs, xe) of tile `tile` (row-major over the
+// frame's ntx x nty tiles) for disparity chunk `chunk` (disparities
+// chunk*DC .. +DC-1), COLS window columns per lane. Ordered lists take the
+// whole tile in one pass; unordered lists may take a tile in several
+// narrower passes. The window columns of the pass start lpad >= r columns
+// left of xs.
+template <int DC, bool kSorted, bool kPack, int COLS>
+__device__ __forceinline__ void tile_item_impl(const FrameDev& f, int tile, int chunk, int xs, int xe, TileLds& smu) {
+  static_assert(COLS == 4 || (kSorted && kPack), "8 columns per lane: ordered lists, packed accumulators");
+  constexpr int kSpanC = Geom<COLS>::kSpanC;
+  constexpr int G = Geom<COLS>::G;
+  constexpr int kTpShift = Geom<COLS>::kTpShift;
+  constexpr int NB = kSorted ? COLS / 4 : 1;   // list entries of a row held in registers: 64 * NB
+  auto& sm = LdsOf<COLS>::get(smu);
+  // The lane index as an opaque value of this item: nothing derived from it
+  // is hoisted out of the persistent kernel's item loop (where it would stay
+  // live, in registers or spilled, across all items).
+  int lane = threadIdx.x;
+  asm volatile("" : "+v"(lane));
+  // The descriptor's fields as values of this item: the row loop's compiler
+  // barriers (pin_step) clobber memory, and fields read through `f` after
+  // them would be loaded again.
+  const uint32_t* const f_idx = f.idx;
+  uint32_t* const f_keys = f.keys;
+  // list entry k and key slot k: a scalar base plus an unsigned 32-bit byte
+  // offset (k < 2^30), which keeps the pointers in scalar registers
+  auto idx_at = [&](int k) -> uint32_t {
+    return *(g_uint32*)((const char*)f_idx + (uint32_t)k * 4u);
+  };
+  const int32_t* const f_map = f.map;
+  const int32_t* const f_tptr = f.tptr;
+  const uint64_t* const f_rowbits = f.rowbits;
+  const int f_tpw = f.tpw, f_rbw = f.rbw, f_ty = f.ty;
   const int tx = tile % f.ntx, tyi = tile / f.ntx;
   const int W = f.W, H = f.H, r = f.r;
-  const int x0 = tx * f.txo, y0 = tyi * f.ty;
-  const int x1 = min(x0 + f.txo, W), y1 = min(y0 + f.ty, H);
+  const int x0 = xs, y0 = tyi * f_ty;
+  const int x1 = xe, y1 = min(y0 + f_ty, H);
   const int d0 = chunk * DC;
   const int dcount = min(DC, f.dmax + 1 - d0);
   const int lpad = f.lpad;
   constexpr bool sorted = kSorted;
+  if (lane < G * 4) sm.pre[lane >> 2][lane & 3] = 0u;   // visible after the first prefix barrier
 
   // Rows of this tile (up to 128, two 64-bit masks) holding a listed pixel
-  // in [x0, x1). For ordered lists lane l keeps the list ranges of rows
-  // y0 + l and y0 + 64 + l in registers.
-  // Ordered lists: lane l keeps the list range of rows y0 + l and y0 + 64 + l
-  // packed as (first - tbase) << 8 | count, tbase being the first list slot
-  // of the tile's first row (count <= txo < 256; first - tbase < ty * W <= 2^24).
-  const int tbase = kSorted ? f.tptr[(int64_t)y0 * f.tpw + tx] : 0;
+  // in [x0, x1). Ordered lists: lane l keeps the list range of rows y0 + l
+  // and y0 + 64 + l, packed as (first - tbase) << kTpShift | count, tbase
+  // being the first list slot of the tile's first row (count <= txo;
+  // first - tbase < ty * W, which the host keeps below 2^(32 - kTpShift)).
+  const int tbase = kSorted ? f_tptr[(int64_t)y0 * f_tpw + tx] : 0;
   uint32_t tpa = 0, tpb = 0;
   auto row_active = [&](int y, int& t0, int& t1) -> bool {
     if (y >= y1) return false;
     if (sorted) {
-      const g_int32* tp = (g_int32*)(f.tptr + (int64_t)y * f.tpw + tx);
+      const g_int32* tp = (g_int32*)(f_tptr + (int64_t)y * f_tpw + tx);
       t0 = tp[0];
       t1 = tp[1];
       return t1 > t0;
@@ -405,7 +485,7 @@ __device__ __forceinline__ void tile_item_impl(const FrameDev& f, int tile, int 
     const int g0 = x0 >> 6, g1 = (x1 - 1) >> 6;
     bool a = false;
     for (int w = g0 >> 6; w <= (g1 >> 6); ++w) {
-      const uint64_t bits = *(g_uint64*)(f.rowbits + (int64_t)y * f.rbw + w);
+      const uint64_t bits = *(g_uint64*)(f_rowbits + (int64_t)y * f_rbw + w);
       const int lo = max(g0 - 64 * w, 0), hi = min(g1 - 64 * w, 63);
       const uint64_t m = (hi == 63 ? ~0ull : ((1ull << (hi + 1)) - 1)) & ~((1ull << lo) - 1);
       if (bits & m) a = true;
@@ -413,19 +493,19 @@ __device__ __forceinline__ void tile_item_impl(const FrameDev& f, int tile, int 
     return a;
   };
   int ta0 = 0, ta1 = 0, tb0 = 0, tb1 = 0;
-  const bool acta = lane < f.ty && row_active(y0 + lane, ta0, ta1);
-  const bool actb = lane + 64 < f.ty && row_active(y0 + 64 + lane, tb0, tb1);
+  const bool acta = lane < f_ty && row_active(y0 + lane, ta0, ta1);
+  const bool actb = lane + 64 < f_ty && row_active(y0 + 64 + lane, tb0, tb1);
   if constexpr (kSorted) {
-    tpa = (uint32_t)(ta0 - tbase) << 8 | (uint32_t)(ta1 - ta0);
-    tpb = (uint32_t)(tb0 - tbase) << 8 | (uint32_t)(tb1 - tb0);
+    tpa = (uint32_t)(ta0 - tbase) << kTpShift | (uint32_t)(ta1 - ta0);
+    tpb = (uint32_t)(tb0 - tbase) << kTpShift | (uint32_t)(tb1 - tb0);
     sm.tp[lane] = tpa;
     sm.tp[64 + lane] = tpb;
   }
   // list range [first, first + count) of row y (uniform), from LDS
   auto row_range = [&](int y, int& first, int& count) {
     const uint32_t v = __builtin_amdgcn_readfirstlane(sm.tp[y - y0]);
-    first = tbase + (int)(v >> 8);
-    count = (int)(v & 0xFFu);
+    first = tbase + (int)(v >> kTpShift);
+    count = (int)(v & ((1u << kTpShift) - 1u));
   };
   const uint64_t rows_a = __builtin_amdgcn_ballot_w64(acta);
   const uint64_t rows_b = __builtin_amdgcn_ballot_w64(actb);
@@ -452,11 +532,11 @@ __device__ __forceinline__ void tile_item_impl(const FrameDev& f, int tile, int 
   };
 
   // Row bases into the padded copies (the same for the whole wave): padded
-  // row q of the tile starts at lp0 + q * lpw and rp0 + q * rpw; lane l reads
-  // from word lo = 4 l on.
+  // row q of the pass starts at lp0 + q * lpw and rp0 + q * rpw (window
+  // column j is image column x0 - lpad + j); lane l reads from word lo = COLS * l on.
   const uint32_t* lp0 = f.lp + x0;
   const uint32_t* rp0 = f.rp + x0 - lpad - d0 - DC + f.rpad;
-  const uint32_t lo = kColsPerLane * (uint32_t)lane;
+  const uint32_t lo = COLS * (uint32_t)lane;
   const int64_t lpw = f.lpw, rpw = f.rpw;
 
   // Disparities beyond dmax (last chunk only) never win: their keys are forced to ~0.
@@ -464,22 +544,27 @@ __device__ __forceinline__ void tile_item_impl(const FrameDev& f, int tile, int 
 #pragma unroll
   for (int k = 0; k < DC; ++k) kill[k] = k < dcount ? 0u : 0xFFFFFFFFu;
 
-  // acc: per window column 4 lane + c and disparity d0 + k, the sum over the
-  // window's rows of the absolute differences (summed over channels).
-  Acc<DC, kPack> acc;
+  // acc: per window column COLS * lane + c and disparity d0 + k, the sum over
+  // the window's rows of the absolute differences (summed over channels).
+  Acc<DC, kPack, COLS> acc;
 #pragma unroll
-  for (int c = 0; c < kColsPerLane; ++c)
+  for (int c = 0; c < COLS; ++c)
 #pragma unroll
-    for (int j = 0; j < Acc<DC, kPack>::N; ++j) acc.v[c][j] = 0;
+    for (int j = 0; j < Acc<DC, kPack, COLS>::N; ++j) acc.v[c][j] = 0;
 
   int e0 = 0, cnt = 0;
-  uint32_t pf_cur = 0, pf_next = 0;        // ordered lists: first 64 list entries of the row
-  int32_t mv[kColsPerLane];                // unordered lists: pixel map of the next active row
-  const uint32_t mlo = kColsPerLane * (uint32_t)lane;   // this lane's first window column
-  // Deferred key update of the previous active row: lane l < pend_cnt
-  // holds the best of entry pend_e0 + l (ordered lists) or of slot
-  // pend_slot (unordered lists).
-  uint32_t pend_best = 0xFFFFFFFFu;
+  uint32_t pf_next[NB];                    // ordered lists: first 64 * NB list entries of the next active row
+  int ob[NB];                              //                their output offsets, once the row is taken
+#pragma unroll
+  for (int b = 0; b < NB; ++b) { pf_next[b] = 0u; ob[b] = 0; }
+  int32_t mv[COLS];                        // unordered lists: pixel map of the next active row
+  const uint32_t mlo = COLS * (uint32_t)lane;   // this lane's first window column
+  // Deferred key update of the previous active row: lane l + 64 b < pend_cnt
+  // holds the best of entry pend_e0 + l + 64 b in pend_best[b] (ordered
+  // lists), or of slot pend_slot (unordered lists).
+  uint32_t pend_best[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) pend_best[b] = 0xFFFFFFFFu;
   int pend_e0 = 0, pend_cnt = 0;
   int32_t pend_slot = -1;
   auto load_next = [&](int y) {            // list data of active row y (y < 0: none)
@@ -487,11 +572,13 @@ __device__ __forceinline__ void tile_item_impl(const FrameDev& f, int tile, int 
     if constexpr (kSorted) {
       int t0, n0;
       row_range(y, t0, n0);
-      if ((int)lane < n0) pf_next = *(g_uint32*)(f.idx + t0 + lane);
-    } else {
-      const int32_t* mrow = f.map + (int64_t)y * W + x0 - lpad;   // window column j -> image column x0 - lpad + j
 #pragma unroll
-      for (int c = 0; c < kColsPerLane; ++c) {
+      for (int b = 0; b < NB; ++b)
+        if ((int)lane + 64 * b < n0) pf_next[b] = idx_at(t0 + (int)lane + 64 * b);
+    } else {
+      const int32_t* mrow = f_map + (int64_t)y * W + x0 - lpad;   // window column j -> image column x0 - lpad + j
+#pragma unroll
+      for (int c = 0; c < COLS; ++c) {
         const int o = (int)mlo + c - lpad;
         mv[c] = (o >= 0 && x0 + o < x1) ? *(g_int32*)(mrow + mlo + c) : -1;
       }
@@ -503,15 +590,17 @@ __device__ __forceinline__ void tile_item_impl(const FrameDev& f, int tile, int 
   // pairs with the next row's loads in flight, then the last row.
   {
     const int last = ya + 2 * r;
-    RowRegs<DC> A, B;
-    load_row<DC>(lp0 + ya * lpw, rp0 + ya * rpw, lo, A);
+    RowRegs<DC, COLS> A, B;
+    init_row(A);
+    init_row(B);
+    load_row<DC, COLS>(lp0 + ya * lpw, rp0 + ya * rpw, lo, A);
     for (int q = ya; q < last; q += 2) {
-      load_row<DC>(lp0 + (q + 1) * lpw, rp0 + (q + 1) * rpw, lo, B);
-      add_row<DC, kPack>(A, acc);
-      load_row<DC>(lp0 + (q + 2) * lpw, rp0 + (q + 2) * rpw, lo, A);
-      add_row<DC, kPack>(B, acc);
+      load_row<DC, COLS>(lp0 + (q + 1) * lpw, rp0 + (q + 1) * rpw, lo, B);
+      add_row<DC, kPack, COLS>(A, acc);
+      load_row<DC, COLS>(lp0 + (q + 2) * lpw, rp0 + (q + 2) * rpw, lo, A);
+      add_row<DC, kPack, COLS>(B, acc);
     }
-    add_row<DC, kPack>(A, acc);
+    add_row<DC, kPack, COLS>(A, acc);
   }
 
   // Row step y (y > ya first moves the window down from y - 1):
@@ -521,48 +610,61 @@ __device__ __forceinline__ void tile_item_impl(const FrameDev& f, int tile, int 
   //                  is a full step old at the next wait;
   //   take_row(y)    the row's listed pixels from what that wait delivered,
   //                  then the loads for the next step and the next active row;
-  //   per group of 8 disparities: prefix sums of the window to LDS, then the
+  //   per group of G disparities: prefix sums of the window to LDS, then the
   //                  window sums of the row's listed pixels as differences of
   //                  two prefix entries, folded into a running best.
   // Loaded values are only used after the wait of the slide, and the only
   // memory operations issued after the loads are rare (rows with more than
-  // 64 listed pixels in the tile).
-  // prefix sums of disparities d0 + g .. d0 + g + 7 to LDS
+  // 64 * NB listed pixels in the tile).
+  // prefix sums of disparities d0 + g .. d0 + g + G - 1 to LDS
   auto prefix_group = [&](int g) {
 #pragma unroll
-    for (int k0 = 0; k0 < kGroup; k0 += 4) {
+    for (int k0 = 0; k0 < G; k0 += 4) {
       // t: the lane's column total, then (after the wave scan) the prefix at
-      // its last column; the three columns before follow by subtraction, so
-      // no in-lane prefixes stay live across the scan.
+      // its last column; the columns before follow by subtraction, so no
+      // in-lane prefixes stay live across the scan.
       uint32_t t[4];
       acc.total2(g + k0, t[0], t[1]);
       acc.total2(g + k0 + 2, t[2], t[3]);
       wave_incl_scan4(t[0], t[1], t[2], t[3]);
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        u32x4 o;
-        o.w = t[i];
-        o.z = o.w - acc.get(3, g + k0 + i);
-        o.y = o.z - acc.get(2, g + k0 + i);
-        o.x = o.y - acc.get(1, g + k0 + i);
-        *(lds_u32x4*)&sm.pre[k0 + i][4 + kColsPerLane * lane] = o;
+        uint32_t o[COLS];
+        o[COLS - 1] = t[i];
+#pragma unroll
+        for (int c = COLS - 1; c > 0; --c) o[c - 1] = o[c] - acc.get(c, g + k0 + i);
+#pragma unroll
+        for (int b = 0; b < COLS / 4; ++b) {
+          u32x4 w;
+          w.x = o[4 * b]; w.y = o[4 * b + 1]; w.z = o[4 * b + 2]; w.w = o[4 * b + 3];
+          *(lds_u32x4*)&sm.pre[k0 + i][4 + COLS * lane + 4 * b] = w;
+        }
       }
     }
-    __syncthreads();
+    wave_lds_order();
   };
   auto take_row = [&](int y) {
     cnt = 0;
     if constexpr (kSorted) {
       row_range(y, e0, cnt);
-      pf_cur = pf_next;
+      // Turned into offsets here, before load_next reuses pf_next: the load of
+      // the next row then writes the register this value occupied, and no
+      // copy of a value still in flight (which would wait for every
+      // outstanding load) is needed at the end of the step.
+      const uint32_t rowbase = (uint32_t)y * (uint32_t)W + (uint32_t)x0;
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        ob[b] = (int)(pf_next[b] - rowbase);
+        asm volatile("" : "+v"(ob[b])::"memory");
+      }
     } else {
 #pragma unroll
-      for (int c = 0; c < kColsPerLane; ++c) {
+      for (int c = 0; c < COLS; ++c) {
         const uint64_t b = __builtin_amdgcn_ballot_w64(mv[c] >= 0);
         if (mv[c] >= 0) {
           const int pos = cnt + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32),
                                                                __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0u));
-          sm.eo[pos] = (int16_t)(kColsPerLane * lane + c - lpad);
+          sm.eo[pos] = (int16_t)(COLS * lane + c - lpad);
           sm.es[pos] = mv[c];
         }
         cnt += __builtin_popcountll(b);
@@ -570,11 +672,11 @@ __device__ __forceinline__ void tile_item_impl(const FrameDev& f, int tile, int 
     }
   };
   // Best (cost << 8 | d) over group g of the listed pixel at output offset o
-  // (0 <= o < txo; window columns o + lpad - r .. o + lpad + r).
+  // (0 <= o < x1 - x0; window columns o + lpad - r .. o + lpad + r).
   auto group_best = [&](int g, int o, uint32_t best) -> uint32_t {
     const int ih = 4 + o + lpad + r, il = 3 + o + lpad - r;
 #pragma unroll
-    for (int k = 0; k < kGroup; ++k) {
+    for (int k = 0; k < G; ++k) {
       const uint32_t s = sm.pre[k][ih] - sm.pre[k][il];
       best = min(best, ((s << 8) | (uint32_t)(d0 + g + k)) | kill[g + k]);
     }
@@ -582,41 +684,52 @@ __device__ __forceinline__ void tile_item_impl(const FrameDev& f, int tile, int 
   };
   // a global (not flat) atomic: it counts only against the vector-memory counter
   auto key_min = [&](int32_t slot, uint32_t v) {
-    __hip_atomic_fetch_min((g_uint32_rw*)(f.keys + slot), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_min((g_uint32_rw*)((char*)f_keys + (uint32_t)slot * 4u), v, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
   };
   auto flush = [&]() {
     if constexpr (kSorted) {
-      if ((int)lane < pend_cnt) key_min(pend_e0 + (int)lane, pend_best);
+#pragma unroll
+      for (int b = 0; b < NB; ++b)
+        if ((int)lane + 64 * b < pend_cnt) key_min(pend_e0 + (int)lane + 64 * b, pend_best[b]);
       pend_cnt = 0;
     } else {
-      if (pend_slot >= 0) key_min(pend_slot, pend_best);
+      if (pend_slot >= 0) key_min(pend_slot, pend_best[0]);
       pend_slot = -1;
     }
   };
   auto entries_row = [&](int y) {
     const uint32_t rowbase = (uint32_t)y * (uint32_t)W + (uint32_t)x0;
-    int o0 = 0, slot0 = -1;
-    if ((int)lane < cnt) {
-      if constexpr (kSorted) { o0 = (int)(pf_cur - rowbase); slot0 = e0 + (int)lane; }
-      else { o0 = sm.eo[lane]; slot0 = sm.es[lane]; }
-    }
-    uint32_t best0 = 0xFFFFFFFFu;
+    bool has[NB];
+    int32_t slot0 = -1;
 #pragma unroll
-    for (int g = 0; g < DC; g += kGroup) {
+    for (int b = 0; b < NB; ++b) {
+      has[b] = (int)lane + 64 * b < cnt;
+      if constexpr (!kSorted)
+        if (has[b]) { ob[b] = sm.eo[lane]; slot0 = sm.es[lane]; }
+    }
+    uint32_t best[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) best[b] = 0xFFFFFFFFu;
+#pragma unroll
+    for (int g = 0; g < DC; g += G) {
       prefix_group(g);
-      if (slot0 >= 0) best0 = group_best(g, o0, best0);
-      // rows with more than 64 listed pixels in the tile: one key update per group
-      for (int e = (int)lane + kWave; e < cnt; e += kWave) {
+#pragma unroll
+      for (int b = 0; b < NB; ++b)
+        if (has[b]) best[b] = group_best(g, ob[b], best[b]);
+      // rows with more than 64 * NB listed pixels in the tile: one key update per group
+      for (int e = (int)lane + kWave * NB; e < cnt; e += kWave) {
         int o, slot;
-        if constexpr (kSorted) { o = (int)(*(g_uint32*)(f.idx + e0 + e) - rowbase); slot = e0 + e; }
+        if constexpr (kSorted) { o = (int)(idx_at(e0 + e) - rowbase); slot = e0 + e; }
         else { o = sm.eo[e]; slot = sm.es[e]; }
         key_min(slot, group_best(g, o, 0xFFFFFFFFu));
       }
-      __syncthreads();   // LDS free for the next group / row
+      wave_lds_order();   // LDS free for the next group / row
     }
-    pend_best = best0;
+#pragma unroll
+    for (int b = 0; b < NB; ++b) pend_best[b] = best[b];
     if constexpr (kSorted) { pend_e0 = e0; pend_cnt = cnt; }
-    else pend_slot = slot0;
+    else pend_slot = has[0] ? slot0 : -1;
   };
 
   // Walk down the rows. The loads for the step y -> y + 1 (padded row
@@ -627,26 +740,34 @@ __device__ __forceinline__ void tile_item_impl(const FrameDev& f, int tile, int 
   const uint32_t* rin = rp0 + (int64_t)(ya + 2 * r + 1) * rpw;
   const uint32_t* lout = lp0 + (int64_t)ya * lpw;
   const uint32_t* rout = rp0 + (int64_t)ya * rpw;
-  RowRegs<DC> En, Ex;
-  load_row<DC>(lin, rin, lo, En);
-  load_row<DC>(lout, rout, lo, Ex);
-  for (int y = ya;; ++y) {
-    if (y > ya) {
-      pin_step(acc.v);
-      slide_row<DC, kPack>(En, Ex, acc);
-      pin_step(acc.v);
-      flush();
-      lin += lpw; rin += rpw; lout += lpw; rout += rpw;
-      load_row<DC>(lin, rin, lo, En);
-      load_row<DC>(lout, rout, lo, Ex);
-    }
-    if (is_active(y)) {
-      take_row(y);
+  RowRegs<DC, COLS> En, Ex;
+  init_row(En);
+  init_row(Ex);
+  load_row<DC, COLS>(lin, rin, lo, En);
+  load_row<DC, COLS>(lout, rout, lo, Ex);
+  // Row ya (active by construction), then the steps y = ya + 1 .. yb. A
+  // step takes its row's listed pixels (loaded a full step earlier) before it
+  // issues the next step's loads, so the only waits are the slide's and a
+  // short one for that list data.
+  take_row(ya);
+  if (ya < yb) load_next(next_active(ya));
+  pin_step(acc.v);
+  entries_row(ya);
+  for (int y = ya + 1; y <= yb; ++y) {
+    const bool act = is_active(y);
+    pin_step(acc.v);
+    slide_row<DC, kPack, COLS>(En, Ex, acc);
+    pin_step(acc.v);
+    flush();
+    if (act) take_row(y);
+    lin += lpw; rin += rpw; lout += lpw; rout += rpw;
+    load_row<DC, COLS>(lin, rin, lo, En);
+    load_row<DC, COLS>(lout, rout, lo, Ex);
+    if (act) {
       if (y < yb) load_next(next_active(y));
       pin_step(acc.v);
       entries_row(y);
     }
-    if (y == yb) break;
   }
   flush();
 }
@@ -656,27 +777,57 @@ __device__ __forceinline__ void tile_item_impl(const FrameDev& f, int tile, int 
 // 16-disparity chunks exist only with packed accumulators (the host uses
 // 8-disparity chunks for frames whose window sums need 32 bits).
 template <bool kPack>
-__device__ __forceinline__ void tile_item8(const FrameDev& f, int tile, int chunk8, bool unsorted, TileLds& sm) {
-  if (unsorted) tile_item_impl<8, false, kPack>(f, tile, chunk8, sm);
-  else tile_item_impl<8, true, kPack>(f, tile, chunk8, sm);
+__device__ __forceinline__ void tile_item8(const FrameDev& f, int tile, int chunk8, bool unsorted, int xs, int xe,
+                                           TileLds& sm) {
+  if (unsorted) tile_item_impl<8, false, kPack, 4>(f, tile, chunk8, xs, xe, sm);
+  else tile_item_impl<8, true, kPack, 4>(f, tile, chunk8, xs, xe, sm);
 }
 
 // The same as an out-of-line call: inside the 16-disparity kernels its
 // registers then do not add to those of the 16-disparity instance (it serves
 // the less common frames there).
 template <bool kPack>
-__device__ __noinline__ void tile_item8_call(const FrameDev& f, int tile, int chunk8, bool unsorted, TileLds& sm) {
-  tile_item8<kPack>(f, tile, chunk8, unsorted, sm);
+__device__ __noinline__ void tile_item8_call(const FrameDev& f, int tile, int chunk8, bool unsorted, int xs, int xe,
+                                             TileLds& sm) {
+  tile_item8<kPack>(f, tile, chunk8, unsorted, xs, xe, sm);
 }
 
-// A 16-disparity item of an ordered list with packed accumulators runs as
-// one pass; any other frame runs its 16 disparities as two 8-disparity
-// passes (same work decomposition, fewer registers).
-template <int DC>
+// Items of a launch that has frames laid out with 8 columns per lane, other
+// than ordered lists of such frames: unordered lists of those frames run the
+// 4-column instance in passes of at most the 4-column width; frames with 4
+// columns per lane run the 8-disparity 4-column instances. Out of line, so
+// the wide instance's registers stay its own.
+__device__ __noinline__ void tile_item_wide_rest(const FrameDev& f, int tile, int chunk8, bool unsorted, int x0, int x1,
+                                                 TileLds& sm) {
+  if (f.cpl == 8) {
+    const int w4 = (Geom<4>::kSpanC - f.lpad - f.r) & ~3;
+#pragma unroll 1
+    for (int xs = x0; xs < x1; xs += w4) tile_item_impl<8, false, true, 4>(f, tile, chunk8, xs, min(xs + w4, x1), sm);
+    return;
+  }
+  if (f.pack) tile_item8<true>(f, tile, chunk8, unsorted, x0, x1, sm);
+  else tile_item8<false>(f, tile, chunk8, unsorted, x0, x1, sm);
+}
+
+// Dispatch of one work item. kWide launches (8-disparity chunks, some frames
+// laid out with 8 columns per lane): ordered lists of those frames run the
+// wide instance, everything else tile_item_wide_rest. Other launches (every
+// frame with 4 columns per lane): a 16-disparity item of an ordered list with
+// packed accumulators runs as one pass; any other frame runs its 16
+// disparities as two 8-disparity passes (same work decomposition, fewer
+// registers).
+template <int DC, bool kWide>
 __device__ __forceinline__ void tile_item(const FrameDev& f, int tile, int chunk, TileLds& sm) {
   const bool unsorted = *(g_uint32*)f.state & kUnsorted;
+  const int x0 = (tile % f.ntx) * f.txo, x1 = min(x0 + f.txo, f.W);
+  if constexpr (kWide) {
+    static_assert(DC == 8, "wide launches use 8-disparity chunks");
+    if (f.cpl == 8 && !unsorted) tile_item_impl<8, true, true, 8>(f, tile, chunk, x0, x1, sm);
+    else tile_item_wide_rest(f, tile, chunk, unsorted, x0, x1, sm);
+    return;
+  }
   if (DC == 16 && f.pack && !unsorted) {
-    tile_item_impl<16, true, true>(f, tile, chunk, sm);
+    tile_item_impl<16, true, true, 4>(f, tile, chunk, x0, x1, sm);
     return;
   }
   constexpr int kParts = DC / 8;
@@ -685,43 +836,35 @@ __device__ __forceinline__ void tile_item(const FrameDev& f, int tile, int chunk
     const int c8 = kParts * chunk + h;
     if (c8 * 8 > f.dmax) break;
     if constexpr (DC == 8) {
-      if (f.pack) tile_item8<true>(f, tile, c8, unsorted, sm);
-      else tile_item8<false>(f, tile, c8, unsorted, sm);
+      if (f.pack) tile_item8<true>(f, tile, c8, unsorted, x0, x1, sm);
+      else tile_item8<false>(f, tile, c8, unsorted, x0, x1, sm);
     } else {
-      if (f.pack) tile_item8_call<true>(f, tile, c8, unsorted, sm);
-      else tile_item8_call<false>(f, tile, c8, unsorted, sm);
+      if (f.pack) tile_item8_call<true>(f, tile, c8, unsorted, x0, x1, sm);
+      else tile_item8_call<false>(f, tile, c8, unsorted, x0, x1, sm);
     }
   }
 }
 
-template <int DC>
-__device__ __forceinline__ void zero_lds_front(TileLds& sm) {
-  if (threadIdx.x < kGroup * 4) sm.pre[threadIdx.x >> 2][threadIdx.x & 3] = 0u;
-  __syncthreads();
-}
-
-// Occupancy target: four wavefronts per SIMD (128 VGPRs) for the 8-disparity
-// chunk, two for the 16-disparity chunk.
-template <int DC>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_tile_grid(
+// Occupancy target: four wavefronts per SIMD (128 VGPRs); three (168 VGPRs)
+// for wide launches, whose 8-column instance needs the registers.
+template <int DC, bool kWide>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kWide ? 3 : 4, 8))) void k_tile_grid(
     const FrameDev* __restrict__ table, int fi) {
   __shared__ TileLds sm;
-  zero_lds_front<DC>(sm);
   const FrameDev& f = table[fi];
   const uint32_t item = blockIdx.x;
-  tile_item<DC>(f, (int)(item / (uint32_t)f.nch), (int)(item % (uint32_t)f.nch), sm);
+  tile_item<DC, kWide>(f, (int)(item / (uint32_t)f.nch), (int)(item % (uint32_t)f.nch), sm);
 }
 
 // Persistent form: one work queue per XCD. Tile t of a frame goes to queue
 // t % 8, so the disparity chunks of a tile run on one XCD and share its L2.
 // Workgroup w starts on queue w % 8 (the XCD the hardware places it on) and,
 // once that queue is empty, takes items from the others.
-template <int DC>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_tile_persistent(
+template <int DC, bool kWide>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kWide ? 3 : 4, 8))) void k_tile_persistent(
     const FrameDev* __restrict__ table, int nframes, QueueTotals totals, WsHeader* hdr) {
   __shared__ TileLds sm;
   __shared__ long long next_item;
-  zero_lds_front<DC>(sm);
   const int home = blockIdx.x % kQueues;
   for (int qi = 0; qi < kQueues; ++qi) {
     const int q = (home + qi) % kQueues;
@@ -729,7 +872,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
     for (;;) {
       if (threadIdx.x == 0) next_item = (long long)atomicAdd(&hdr->q[q].head, 1ull);
       __syncthreads();
-      const int64_t it = next_item;
+      // the same for every lane: read as a scalar, so the frame lookup and the
+      // descriptor loads below stay scalar
+      const uint64_t itv = (uint64_t)next_item;
+      const int64_t it = (int64_t)(((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(itv >> 32)) << 32) |
+                                   (uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)itv));
       __syncthreads();
       if (it >= total) break;
       // frame of this item: last frame with xbase[q] <= it
@@ -741,7 +888,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
       const FrameDev& f = table[lo];
       const uint32_t local = (uint32_t)(it - f.xbase[q]);
       const int tile = q + kQueues * (int)(local / (uint32_t)f.nch);
-      tile_item<DC>(f, tile, (int)(local % (uint32_t)f.nch), sm);
+      tile_item<DC, kWide>(f, tile, (int)(local % (uint32_t)f.nch), sm);
     }
   }
 }
@@ -834,20 +981,22 @@ hipError_t launch_finalize(const FrameDev* table, int f0, int nf, hipStream_t s)
   return hipGetLastError();
 }
 
-hipError_t launch_tile_grid(const FrameDev* table, int fi, int64_t nitems, int chunk, hipStream_t s) {
+hipError_t launch_tile_grid(const FrameDev* table, int fi, int64_t nitems, int chunk, bool wide, hipStream_t s) {
   if (nitems <= 0) return hipSuccess;
-  if (chunk == 8) hipLaunchKernelGGL(k_tile_grid<8>, dim3((unsigned)nitems), dim3(64), 0, s, table, fi);
-  else hipLaunchKernelGGL(k_tile_grid<16>, dim3((unsigned)nitems), dim3(64), 0, s, table, fi);
+  const dim3 g((unsigned)nitems), b(64);
+  if (wide) hipLaunchKernelGGL((k_tile_grid<8, true>), g, b, 0, s, table, fi);
+  else if (chunk == 8) hipLaunchKernelGGL((k_tile_grid<8, false>), g, b, 0, s, table, fi);
+  else hipLaunchKernelGGL((k_tile_grid<16, false>), g, b, 0, s, table, fi);
   return hipGetLastError();
 }
 
-hipError_t launch_tile_persistent(const FrameDev* table, int nframes, const QueueTotals& totals, int chunk,
+hipError_t launch_tile_persistent(const FrameDev* table, int nframes, const QueueTotals& totals, int chunk, bool wide,
                                   int grid, WsHeader* hdr, hipStream_t s) {
   hipLaunchKernelGGL(k_reset_head, dim3(1), dim3(64), 0, s, hdr);
-  if (chunk == 8)
-    hipLaunchKernelGGL(k_tile_persistent<8>, dim3(grid), dim3(64), 0, s, table, nframes, totals, hdr);
-  else
-    hipLaunchKernelGGL(k_tile_persistent<16>, dim3(grid), dim3(64), 0, s, table, nframes, totals, hdr);
+  const dim3 g(grid), b(64);
+  if (wide) hipLaunchKernelGGL((k_tile_persistent<8, true>), g, b, 0, s, table, nframes, totals, hdr);
+  else if (chunk == 8) hipLaunchKernelGGL((k_tile_persistent<8, false>), g, b, 0, s, table, nframes, totals, hdr);
+  else hipLaunchKernelGGL((k_tile_persistent<16, false>), g, b, 0, s, table, nframes, totals, hdr);
   return hipGetLastError();
 }
 

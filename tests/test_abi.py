@@ -56,6 +56,12 @@ def test_workspace_bytes_and_plans():
     assert sbs.workspace_bytes([f, f]) > nb
     with pytest.raises(sbs.SbsError):
         sbs.set_plan(chunk=12)
+    with pytest.raises(sbs.SbsError):
+        sbs.set_plan(cols_per_lane=8, chunk=16)   # 8 columns per lane only with 8-disparity chunks
+    with pytest.raises(sbs.SbsError):
+        sbs.set_plan(cols_per_lane=6)
+    sbs.set_plan(cols_per_lane=8, chunk=8)
+    assert sbs.get_plan(f)["cols_per_lane"] == 8
     sbs.set_plan(chunk=8, tile_rows=16)
     assert sbs.get_plan(f)["chunk"] == 8 and sbs.get_plan(f)["tile_rows"] == 16
     sbs.set_plan()

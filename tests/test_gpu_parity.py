@@ -70,6 +70,15 @@ def test_tiny_random_sweep(torch, sbs):
         what = f"trial {trial} W{W} H{H} C{C} b{block} d{dmax}"
         assert_parity(run_gpu(torch, sbs, L, R, idx, block, dmax), exp, what + " tiled")
         assert_parity(run_gpu(torch, sbs, L, R, idx, block, dmax, path="ref"), exp, what + " ref")
+        # ordered list, forced 8 columns per lane (and the unordered one under that plan)
+        srt = np.unique(idx)
+        try:
+            sbs.set_plan(cols_per_lane=8, chunk=8, tile_rows=int(rng.choice([8, 32, 128])))
+            assert_parity(run_gpu(torch, sbs, L, R, srt, block, dmax), oracle.sad(L, R, srt, block, dmax),
+                          what + " ordered, 8 columns per lane")
+            assert_parity(run_gpu(torch, sbs, L, R, idx, block, dmax), exp, what + " unordered, 8-column tiles")
+        finally:
+            sbs.set_plan()
 
 
 def test_tsukuba_shape_full_list(torch, sbs):
@@ -127,15 +136,15 @@ def test_plans_agree(torch, sbs):
     idx = scenes.contour_list(f.rid, 0.2, 1)
     base = None
     try:
-        for chunk in (8, 16):
-            for rows in (8, 16, 32, 64):
-                sbs.set_plan(chunk=chunk, tile_rows=rows)
+        for cpl, chunk in ((4, 8), (4, 16), (8, 8)):
+            for rows in (8, 16, 32, 64, 128):
+                sbs.set_plan(cols_per_lane=cpl, chunk=chunk, tile_rows=rows)
                 got = run_gpu(torch, sbs, f.left, f.right, idx, spec.block, spec.dmax)
                 if base is None:
                     base = got
                     exp = oracle.sad(f.left, f.right, idx, spec.block, spec.dmax)
                     assert_parity(got, exp, "plan base vs oracle")
-                assert_parity(got, base, f"plan chunk {chunk} rows {rows}")
+                assert_parity(got, base, f"plan cols {cpl} chunk {chunk} rows {rows}")
     finally:
         sbs.set_plan()
 
@@ -328,5 +337,58 @@ def test_chunk16_all_instances(torch, sbs):
                 exp = oracle.sad(L, R, idx, block, dmax)
                 got = (runner.disp[i].cpu().numpy(), runner.cost[i].cpu().numpy().view(np.uint32))
                 assert_parity(got, exp, f"chunk16 batched rows {rows} frame {i}")
+    finally:
+        sbs.set_plan()
+
+
+def test_eight_columns_per_lane(torch, sbs):
+    """Tiles of 512 window columns (8 per lane, 8-disparity chunks): ordered
+    lists take the wide instance, with up to 128 listed pixels of a tile row
+    in registers and the rest through the per-group path (dense rows); an
+    unordered list runs the same tiles as narrower 4-column passes; frames
+    whose window sums need 32 bits, and frames too wide for the packed row
+    ranges (tile rows x W >= 2^23), fall back to 4 columns in the same call."""
+    rng = np.random.default_rng(31)
+    cases = []
+    for (H, W, C, block, dmax, order) in [(150, 1100, 3, 31, 40, "sorted"), (150, 1100, 3, 31, 40, "shuffled"),
+                                          (97, 523, 1, 9, 127, "sorted"), (70, 61, 3, 15, 8, "sorted"),
+                                          (60, 900, 3, 45, 20, "sorted"), (33, 1300, 1, 3, 7, "dense"),
+                                          (20, 2000, 3, 1, 0, "sorted")]:
+        shape = (H, W, C) if C == 3 else (H, W)
+        L = rng.integers(0, 256, shape, dtype=np.uint8)
+        R = np.roll(L, 5, axis=1)
+        R[::5] = rng.integers(0, 256, R[::5].shape, dtype=np.uint8)
+        if order == "dense":   # whole rows listed: hundreds of entries per tile row
+            rows = rng.choice(H, 6, replace=False)
+            idx = np.sort(np.concatenate([np.arange(W) + y * W for y in rows])).astype(np.uint32)
+        else:
+            idx = np.sort(rng.choice(H * W, H * W // 5, replace=False)).astype(np.uint32)
+        if order == "shuffled":
+            idx = np.concatenate([rng.permutation(idx), idx[:23]])
+        cases.append((L, R, idx, block, dmax))
+    try:
+        for rows in (8, 32, 128):
+            sbs.set_plan(cols_per_lane=8, chunk=8, tile_rows=rows)
+            for (L, R, idx, block, dmax) in cases:
+                exp = oracle.sad(L, R, idx, block, dmax)
+                assert_parity(run_gpu(torch, sbs, L, R, idx, block, dmax), exp,
+                              f"8 cols rows {rows} {L.shape} b{block} d{dmax}")
+            frames = [(dev(torch, L), dev(torch, R), dev(torch, idx.view(np.int32)), block, dmax)
+                      for (L, R, idx, block, dmax) in cases]
+            runner = sbs.BatchRunner(frames)
+            runner.run()
+            torch.cuda.synchronize()
+            for i, (L, R, idx, block, dmax) in enumerate(cases):
+                exp = oracle.sad(L, R, idx, block, dmax)
+                got = (runner.disp[i].cpu().numpy(), runner.cost[i].cpu().numpy().view(np.uint32))
+                assert_parity(got, exp, f"8 cols batched rows {rows} frame {i}")
+        # tile rows x W >= 2^23: the frame runs with 4 columns per lane
+        H, W = 130, 66000
+        L = rng.integers(0, 256, (H, W), dtype=np.uint8)
+        R = np.roll(L, 2, axis=1)
+        idx = np.sort(rng.choice(H * W, 3000, replace=False)).astype(np.uint32)
+        sbs.set_plan(cols_per_lane=8, chunk=8, tile_rows=128)
+        exp = oracle.sad(L, R, idx, 3, 9)
+        assert_parity(run_gpu(torch, sbs, L, R, idx, 3, 9), exp, "wide frame fallback")
     finally:
         sbs.set_plan()
