@@ -164,10 +164,12 @@ int sbs_sad_disparity_per_frame(const sbs_frame* frames, int32_t nframes, void* 
  * "automatic". sbs_set_plan forces a plan for subsequent calls (all fields 0
  * restores automatic choice); sbs_get_plan reports the plan the library would
  * use for a frame. Valid cols_per_lane: 4, 8 (8 only with chunk 8); chunk:
- * 8, 16; tile_rows: 8..128; waves_per_cu: 1..16. A frame runs with 8 columns
+ * 8, 16; tile_rows: 8..256; waves_per_cu: 1..16. A frame runs with 8 columns
  * per lane only where its window sums allow packed 16-bit accumulators
- * (2 * block * 255 * C <= 65535) and tile_rows * W < 2^23; other frames of the
- * same call run with 4.
+ * (2 * block * 255 * C <= 65535) and min(n, (tile_rows - 1) * W) < 2^23;
+ * other frames of the same call run with 4. A frame whose
+ * min(n, (tile_rows - 1) * W) reaches 2^24 (2^23 at 8 columns per lane) runs
+ * with tile_rows halved until it does not.
  */
 typedef struct {
   int32_t cols_per_lane;

@@ -114,11 +114,25 @@ std::string plan_key(const sbs_frame& f) {
 
 bool packs(const sbs_frame& f) { return 2 * (int64_t)f.block * 255 * f.C <= 65535; }
 
+// The tile kernel packs a row's list range as (first - tile's first slot) <<
+// shift | count, with shift 8 (4 columns per lane) or 9 (8 columns per
+// lane); the offset is at most min(n, (tile rows - 1) x W).
+bool ranges_fit(const sbs_frame& f, int ty, int shift) {
+  return std::min<int64_t>(f.n, (int64_t)(ty - 1) * f.W) < (1LL << (32 - shift));
+}
+
 // Window columns per lane that frame f runs with under plan p: 8 needs
-// 8-disparity chunks, packed accumulators and row list ranges that fit the
-// tile kernel's packing (tile rows x W < 2^23); 4 otherwise.
+// 8-disparity chunks, packed accumulators and row list ranges that fit; 4
+// otherwise.
 int cpl_of(const sbs_frame& f, int plan_cpl, int chunk, int ty) {
-  return plan_cpl == 8 && chunk == 8 && packs(f) && (int64_t)ty * f.W < (1LL << 23) ? 8 : 4;
+  return plan_cpl == 8 && chunk == 8 && packs(f) && ranges_fit(f, ty, 9) ? 8 : 4;
+}
+
+// Tile rows of frame f under a plan of `ty` rows: halved until its row list
+// ranges fit (only very wide frames with very long lists need that).
+int ty_of(const sbs_frame& f, int ty, int cpl) {
+  while (ty > 1 && !ranges_fit(f, ty, cpl == 8 ? 9 : 8)) ty /= 2;
+  return ty;
 }
 
 // Work items of frame f with a given disparity chunk, tile height and lane width.
@@ -126,8 +140,10 @@ int64_t items_of(const sbs_frame& f, int chunk, int ty, int cpl = 4) {
   if (f.n <= 0) return 0;
   const int r = (f.block - 1) / 2;
   const int lpad = (r + 3) & ~3;
-  const int txo = (kWave * cpl_of(f, cpl, chunk, ty) - lpad - r) & ~3;
-  return (int64_t)((f.W + txo - 1) / txo) * ((f.H + ty - 1) / ty) * ((f.dmax + chunk) / chunk);
+  const int c = cpl_of(f, cpl, chunk, ty);
+  const int txo = (kWave * c - lpad - r) & ~3;
+  const int t = ty_of(f, ty, c);
+  return (int64_t)((f.W + txo - 1) / txo) * ((f.H + t - 1) / t) * ((f.dmax + chunk) / chunk);
 }
 
 // Default plan for the frames one launch covers: the largest items that
@@ -372,7 +388,7 @@ int run(const sbs_frame* frames, int nframes, void* workspace, size_t ws_bytes, 
     d.dmax = f.dmax;
     d.lpw = L.lpw; d.rpw = L.rpw; d.ph = L.ph; d.lpad = L.lpad; d.rpad = L.rpad; d.rbw = L.rbw;
     d.txo = L.txo;
-    d.ty = plan.ty;
+    d.ty = ty_of(f, plan.ty, cpl[(size_t)i]);
     d.ntx = L.ntx;
     d.nty = (f.H + d.ty - 1) / d.ty;
     d.chunk = plan.chunk;
@@ -487,7 +503,7 @@ int save_cache(const char* path) {
 
 bool plan_valid(const Plan& p) {
   return (p.cpl == 4 || (p.cpl == 8 && p.chunk == 8)) && (p.chunk == 8 || p.chunk == 16) && p.ty >= 8 &&
-         p.ty <= 128 && p.wpc >= 1 && p.wpc <= 16;
+         p.ty <= kMaxTileRows && p.wpc >= 1 && p.wpc <= 16;
 }
 
 }  // namespace
@@ -641,7 +657,7 @@ int sbs_tune(const sbs_frame* frames, int32_t nframes, const char* cache_path) {
   Plan best;
   float best_ms = 1e30f;
   const int shapes[][2] = {{4, 8}, {4, 16}, {8, 8}};   // (columns per lane, disparity chunk)
-  const int rows[] = {32, 64, 128};
+  const int rows[] = {32, 64, 128, 256};
   const int wpcs[] = {4, 8, 16};
   for (const auto& sh : shapes)
     for (int ty : rows)

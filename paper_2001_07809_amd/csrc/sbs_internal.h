@@ -9,6 +9,7 @@ namespace sbs {
 constexpr int kWave = 64;
 constexpr int kMaxSpan = kWave * 8;        // window columns of a tile at 8 columns per lane (512)
 constexpr int kMaxChunk = 16;         // largest disparity chunk a kernel instance handles
+constexpr int kMaxTileRows = 256;     // largest tile height (four 64-bit row masks)
 constexpr int kDescPerLaunch = 8;          // descriptors carried by one upload kernel
 constexpr uint32_t kUnsorted = 1u;         // FrameDev::state bit
 constexpr int kQueues = 8;                 // one work queue per XCD; tile t's items go to queue t % 8

@@ -257,17 +257,18 @@ struct TileLds4 {
       int16_t eo[kWave * 4];   // unordered lists: listed pixels of the row (output column offset)
       int32_t es[kWave * 4];   //                  and their representative slots
     };
-    uint32_t tp[128];          // ordered lists: list range of each row of the tile, packed
+    uint32_t tp[kMaxTileRows];   // ordered lists: list range of each row of the tile, packed
   };
 };
 struct TileLds8 {
   uint32_t pre[4][kWave * 8 + 4] __attribute__((aligned(16)));
-  uint32_t tp[128];
+  uint32_t tp[kMaxTileRows];
 };
 union TileLds {
   TileLds4 n;
   TileLds8 w;
 };
+static_assert(sizeof(TileLds) <= 9856, "LDS of one wavefront: 16 wavefronts per CU share 160 KB");
 template <int COLS> struct LdsOf;
 template <> struct LdsOf<4> { static __device__ __forceinline__ TileLds4& get(TileLds& s) { return s.n; } };
 template <> struct LdsOf<8> { static __device__ __forceinline__ TileLds8& get(TileLds& s) { return s.w; } };
@@ -467,13 +468,13 @@ __device__ __forceinline__ void tile_item_impl(const FrameDev& f, int tile, int 
   constexpr bool sorted = kSorted;
   if (lane < G * 4) sm.pre[lane >> 2][lane & 3] = 0u;   // visible after the first prefix barrier
 
-  // Rows of this tile (up to 128, two 64-bit masks) holding a listed pixel
-  // in [x0, x1). Ordered lists: lane l keeps the list range of rows y0 + l
-  // and y0 + 64 + l, packed as (first - tbase) << kTpShift | count, tbase
-  // being the first list slot of the tile's first row (count <= txo;
-  // first - tbase < ty * W, which the host keeps below 2^(32 - kTpShift)).
+  // Rows of this tile (up to kMaxTileRows = 256, four 64-bit masks) holding
+  // a listed pixel in [x0, x1). Ordered lists: row y0 + 64 m + l's list range
+  // goes to LDS (tp[64 m + l]), packed as (first - tbase) << kTpShift | count,
+  // tbase being the first list slot of the tile's first row (count <= txo;
+  // first - tbase <= min(n, (ty - 1) * W), which the host keeps below
+  // 2^(32 - kTpShift)).
   const int tbase = kSorted ? f_tptr[(int64_t)y0 * f_tpw + tx] : 0;
-  uint32_t tpa = 0, tpb = 0;
   auto row_active = [&](int y, int& t0, int& t1) -> bool {
     if (y >= y1) return false;
     if (sorted) {
@@ -492,14 +493,13 @@ __device__ __forceinline__ void tile_item_impl(const FrameDev& f, int tile, int 
     }
     return a;
   };
-  int ta0 = 0, ta1 = 0, tb0 = 0, tb1 = 0;
-  const bool acta = lane < f_ty && row_active(y0 + lane, ta0, ta1);
-  const bool actb = lane + 64 < f_ty && row_active(y0 + 64 + lane, tb0, tb1);
-  if constexpr (kSorted) {
-    tpa = (uint32_t)(ta0 - tbase) << kTpShift | (uint32_t)(ta1 - ta0);
-    tpb = (uint32_t)(tb0 - tbase) << kTpShift | (uint32_t)(tb1 - tb0);
-    sm.tp[lane] = tpa;
-    sm.tp[64 + lane] = tpb;
+  uint64_t rows[kMaxTileRows / 64];
+#pragma unroll
+  for (int m = 0; m < kMaxTileRows / 64; ++m) {
+    int t0 = 0, t1 = 0;
+    const bool act = (int)lane + 64 * m < f_ty && row_active(y0 + 64 * m + (int)lane, t0, t1);
+    if constexpr (kSorted) sm.tp[64 * m + lane] = (uint32_t)(t0 - tbase) << kTpShift | (uint32_t)(t1 - t0);
+    rows[m] = __builtin_amdgcn_ballot_w64(act);
   }
   // list range [first, first + count) of row y (uniform), from LDS
   auto row_range = [&](int y, int& first, int& count) {
@@ -507,26 +507,24 @@ __device__ __forceinline__ void tile_item_impl(const FrameDev& f, int tile, int 
     first = tbase + (int)(v >> kTpShift);
     count = (int)(v & ((1u << kTpShift) - 1u));
   };
-  const uint64_t rows_a = __builtin_amdgcn_ballot_w64(acta);
-  const uint64_t rows_b = __builtin_amdgcn_ballot_w64(actb);
-  if ((rows_a | rows_b) == 0) return;
-  const int ya = y0 + (rows_a ? __builtin_ctzll(rows_a) : 64 + __builtin_ctzll(rows_b));
-  const int yb = y0 + (rows_b ? 127 - __builtin_clzll(rows_b) : 63 - __builtin_clzll(rows_a));
-  auto is_active = [&](int y) -> bool {
-    const int i = y - y0;
-    return i < 64 ? ((rows_a >> i) & 1ull) : ((rows_b >> (i - 64)) & 1ull);
-  };
-  // first active row after y, or -1
+  int ya = -1, yb = -1;
+#pragma unroll
+  for (int m = 0; m < kMaxTileRows / 64; ++m)
+    if (ya < 0 && rows[m]) ya = y0 + 64 * m + __builtin_ctzll(rows[m]);
+#pragma unroll
+  for (int m = kMaxTileRows / 64 - 1; m >= 0; --m)
+    if (yb < 0 && rows[m]) yb = y0 + 64 * m + 63 - __builtin_clzll(rows[m]);
+  if (ya < 0) return;
+  // first active row after y, or -1 (the masks are only indexed by constants,
+  // so they stay in scalar registers)
   auto next_active = [&](int y) -> int {
     const int i = y - y0 + 1;
-    if (i < 64) {
-      const uint64_t m = rows_a >> i;
-      if (m) return y + 1 + __builtin_ctzll(m);
-      return rows_b ? y0 + 64 + __builtin_ctzll(rows_b) : -1;
-    }
-    if (i < 128) {
-      const uint64_t m = rows_b >> (i - 64);
-      if (m) return y + 1 + __builtin_ctzll(m);
+#pragma unroll
+    for (int m = 0; m < kMaxTileRows / 64; ++m) {
+      if (i >= 64 * (m + 1)) continue;
+      const int sh = i > 64 * m ? i - 64 * m : 0;
+      const uint64_t w = rows[m] >> sh;
+      if (w) return y0 + 64 * m + sh + __builtin_ctzll(w);
     }
     return -1;
   };
@@ -750,11 +748,12 @@ __device__ __forceinline__ void tile_item_impl(const FrameDev& f, int tile, int 
   // issues the next step's loads, so the only waits are the slide's and a
   // short one for that list data.
   take_row(ya);
-  if (ya < yb) load_next(next_active(ya));
+  int ynext = next_active(ya);   // the next active row (-1: none)
+  load_next(ynext);
   pin_step(acc.v);
   entries_row(ya);
   for (int y = ya + 1; y <= yb; ++y) {
-    const bool act = is_active(y);
+    const bool act = y == ynext;
     pin_step(acc.v);
     slide_row<DC, kPack, COLS>(En, Ex, acc);
     pin_step(acc.v);
@@ -764,7 +763,8 @@ __device__ __forceinline__ void tile_item_impl(const FrameDev& f, int tile, int 
     load_row<DC, COLS>(lin, rin, lo, En);
     load_row<DC, COLS>(lout, rout, lo, Ex);
     if (act) {
-      if (y < yb) load_next(next_active(y));
+      ynext = next_active(y);
+      load_next(ynext);
       pin_step(acc.v);
       entries_row(y);
     }

@@ -137,7 +137,7 @@ def test_plans_agree(torch, sbs):
     base = None
     try:
         for cpl, chunk in ((4, 8), (4, 16), (8, 8)):
-            for rows in (8, 16, 32, 64, 128):
+            for rows in (8, 16, 32, 64, 128, 256):
                 sbs.set_plan(cols_per_lane=cpl, chunk=chunk, tile_rows=rows)
                 got = run_gpu(torch, sbs, f.left, f.right, idx, spec.block, spec.dmax)
                 if base is None:
@@ -323,7 +323,7 @@ def test_chunk16_all_instances(torch, sbs):
             idx = np.concatenate([rng.permutation(idx), idx[:17]])
         cases.append((L, R, idx, block, dmax))
     try:
-        for rows in (32, 128):
+        for rows in (32, 128, 256):
             sbs.set_plan(chunk=16, tile_rows=rows)
             for (L, R, idx, block, dmax) in cases:
                 exp = oracle.sad(L, R, idx, block, dmax)
@@ -367,7 +367,7 @@ def test_eight_columns_per_lane(torch, sbs):
             idx = np.concatenate([rng.permutation(idx), idx[:23]])
         cases.append((L, R, idx, block, dmax))
     try:
-        for rows in (8, 32, 128):
+        for rows in (8, 32, 128, 256):
             sbs.set_plan(cols_per_lane=8, chunk=8, tile_rows=rows)
             for (L, R, idx, block, dmax) in cases:
                 exp = oracle.sad(L, R, idx, block, dmax)
@@ -390,5 +390,29 @@ def test_eight_columns_per_lane(torch, sbs):
         sbs.set_plan(cols_per_lane=8, chunk=8, tile_rows=128)
         exp = oracle.sad(L, R, idx, 3, 9)
         assert_parity(run_gpu(torch, sbs, L, R, idx, 3, 9), exp, "wide frame fallback")
+    finally:
+        sbs.set_plan()
+
+
+def test_long_list_on_a_wide_frame(torch, sbs):
+    """A list of 2^24 + entries on a 70000-column frame: with 256-row tiles a
+    row's list offset inside its tile would not fit the kernel's packed range
+    (24 bits), so the frame runs with 128-row tiles; outputs checked on a
+    sample against the oracle."""
+    rng = np.random.default_rng(41)
+    H, W = 300, 70000
+    L = rng.integers(0, 256, (H, W), dtype=np.uint8)
+    R = np.roll(L, 3, axis=1)
+    keep = rng.random(H * W) < 0.82
+    idx = np.flatnonzero(keep).astype(np.uint32)
+    assert idx.size >= (1 << 24)
+    try:
+        for cpl in (4, 8):
+            sbs.set_plan(cols_per_lane=cpl, chunk=8, tile_rows=256)
+            d, c = run_gpu(torch, sbs, L, R, idx, 3, 7)
+            pick = np.sort(rng.choice(idx.size, 3000, replace=False))
+            pick = np.concatenate([pick, np.arange(200), idx.size - 1 - np.arange(200)])
+            ed, ec, _ = oracle.sad(L, R, idx[pick], 3, 7)
+            assert_parity((d[pick], c[pick]), (ed, ec), f"long list, {cpl} columns per lane")
     finally:
         sbs.set_plan()
