@@ -139,7 +139,7 @@ int ty_of(const sbs_frame& f, int ty, int cpl) {
 int64_t items_of(const sbs_frame& f, int chunk, int ty, int cpl = 4) {
   if (f.n <= 0) return 0;
   const int r = (f.block - 1) / 2;
-  const int lpad = (r + 3) & ~3;
+  const int lpad = (r + 4) & ~3;
   const int c = cpl_of(f, cpl, chunk, ty);
   const int txo = (kWave * c - lpad - r) & ~3;
   const int t = ty_of(f, ty, c);
@@ -209,7 +209,7 @@ struct FrameLayout {
 };
 
 // Layout of one frame's part of the workspace for tiles of `span` window
-// columns (64 x columns per lane); a tile's window columns start lpad >= r
+// columns (64 x columns per lane); a tile's window columns start lpad > r
 // columns left of its first output column.
 FrameLayout frame_layout(const sbs_frame& f, size_t base, int span) {
   FrameLayout L;
@@ -218,7 +218,7 @@ FrameLayout frame_layout(const sbs_frame& f, size_t base, int span) {
   // are multiples of 4 so 4-pixel groups stay 16-byte aligned; rpad leaves room
   // for the largest disparity chunk to the left of column 0. A tile reads
   // `span` columns from its first window column on.
-  L.lpad = (r + 3) & ~3;
+  L.lpad = (r + 4) & ~3;
   L.rpad = (L.lpad + f.dmax + kMaxChunk + 1 + 3) & ~3;
   L.lpw = (int)align_up((size_t)f.W + span, 64);
   L.rpw = (int)align_up((size_t)f.W + span + L.rpad, 64);

@@ -247,11 +247,13 @@ struct Geom {
 
 // LDS of one work item: prefix sums for G disparities and, for unordered
 // lists (4 columns per lane only), the current row's listed pixels.
-// pre[k][4 + j] is the inclusive prefix sum over window columns 0..j;
-// pre[k][0..3] are zero (written at the start of every item), so a window
-// that starts at column 0 needs no special case.
+// pre[k][j] is the inclusive prefix sum over window columns 0..j. Windows
+// never start at column 0 (the left margin lpad exceeds r), so no zero entry
+// is needed, and a row is exactly 64 * COLS words: the same column of rows k
+// and k + 1 lies a multiple of 256 bytes apart, which lets one ds_read2st64
+// fetch both.
 struct TileLds4 {
-  uint32_t pre[8][kWave * 4 + 4] __attribute__((aligned(16)));
+  uint32_t pre[8][kWave * 4] __attribute__((aligned(16)));
   union {
     struct {
       int16_t eo[kWave * 4];   // unordered lists: listed pixels of the row (output column offset)
@@ -261,7 +263,7 @@ struct TileLds4 {
   };
 };
 struct TileLds8 {
-  uint32_t pre[4][kWave * 8 + 4] __attribute__((aligned(16)));
+  uint32_t pre[4][kWave * 8] __attribute__((aligned(16)));
   uint32_t tp[kMaxTileRows];
 };
 union TileLds {
@@ -429,7 +431,7 @@ __device__ __forceinline__ void slide_row(RowRegs<DC, COLS>& en, RowRegs<DC, COL
 // frame's ntx x nty tiles) for disparity chunk `chunk` (disparities
 // chunk*DC .. +DC-1), COLS window columns per lane. Ordered lists take the
 // whole tile in one pass; unordered lists may take a tile in several
-// narrower passes. The window columns of the pass start lpad >= r columns
+// narrower passes. The window columns of the pass start lpad > r columns
 // left of xs.
 template <int DC, bool kSorted, bool kPack, int COLS>
 __device__ __forceinline__ void tile_item_impl(const FrameDev& f, int tile, int chunk, int xs, int xe, TileLds& smu) {
@@ -466,7 +468,6 @@ __device__ __forceinline__ void tile_item_impl(const FrameDev& f, int tile, int 
   const int dcount = min(DC, f.dmax + 1 - d0);
   const int lpad = f.lpad;
   constexpr bool sorted = kSorted;
-  if (lane < G * 4) sm.pre[lane >> 2][lane & 3] = 0u;   // visible after the first prefix barrier
 
   // Rows of this tile (up to kMaxTileRows = 256, four 64-bit masks) holding
   // a listed pixel in [x0, x1). Ordered lists: row y0 + 64 m + l's list range
@@ -635,7 +636,7 @@ __device__ __forceinline__ void tile_item_impl(const FrameDev& f, int tile, int 
         for (int b = 0; b < COLS / 4; ++b) {
           u32x4 w;
           w.x = o[4 * b]; w.y = o[4 * b + 1]; w.z = o[4 * b + 2]; w.w = o[4 * b + 3];
-          *(lds_u32x4*)&sm.pre[k0 + i][4 + COLS * lane + 4 * b] = w;
+          *(lds_u32x4*)&sm.pre[k0 + i][COLS * lane + 4 * b] = w;
         }
       }
     }
@@ -672,7 +673,7 @@ __device__ __forceinline__ void tile_item_impl(const FrameDev& f, int tile, int 
   // Best (cost << 8 | d) over group g of the listed pixel at output offset o
   // (0 <= o < x1 - x0; window columns o + lpad - r .. o + lpad + r).
   auto group_best = [&](int g, int o, uint32_t best) -> uint32_t {
-    const int ih = 4 + o + lpad + r, il = 3 + o + lpad - r;
+    const int ih = o + lpad + r, il = o + lpad - r - 1;   // il >= 0: lpad > r
 #pragma unroll
     for (int k = 0; k < G; ++k) {
       const uint32_t s = sm.pre[k][ih] - sm.pre[k][il];
