@@ -288,12 +288,9 @@ __device__ __forceinline__ void wave_lds_order() { asm volatile("" ::: "memory")
 // the DC + COLS right columns that pair with them over the chunk (right
 // index c + DC - k pairs with left column c at disparity d0 + k; index 0 is
 // never used). Lane l's right words start at word COLS * l of the wave's
-// span, so its words 0 .. DC - 1 are words COLS .. DC + COLS - 1 of lane
-// l - 1: each lane loads only its top COLS words and takes the lower ones
-// from lane l - 1 with DPP wave shifts, while lane 0 loads the words below
-// the span itself (spread_row). The lower words are only written by those
-// loads (lane 0) and the shifts (other lanes): callers keep a RowRegs alive
-// across rows, so no lane needs them cleared.
+// span. Each lane loads all of them itself: neighbouring lanes read
+// overlapping words, which the L1 cache serves, and that costs less than
+// passing words between lanes with DPP shifts.
 template <int DC, int COLS>
 struct RowRegs {
   uint32_t L[COLS];
@@ -310,45 +307,20 @@ __device__ __forceinline__ void load_row(const uint32_t* lrow, const uint32_t* r
     o.L[4 * b] = lv.x; o.L[4 * b + 1] = lv.y; o.L[4 * b + 2] = lv.z; o.L[4 * b + 3] = lv.w;
   }
 #pragma unroll
-  for (int b = 0; b < COLS / 4; ++b) {
-    const u32x4 t = *(g_uint4*)(rrow + lo + DC + 4 * b);
-    o.R[DC + 4 * b] = t.x; o.R[DC + 4 * b + 1] = t.y; o.R[DC + 4 * b + 2] = t.z; o.R[DC + 4 * b + 3] = t.w;
-  }
-  if (lo == 0) {
-    // words 0 .. DC - 1 as whole aligned blocks. Word 0 is never used in the
-    // sums, but it is loaded and kept (spread_row) so that every load writes
-    // only live registers: a dead load destination that the compiler reused
-    // for other work would make it wait for the load, and with it for every
-    // load issued before it.
-#pragma unroll
-    for (int q = 0; q < DC / 4; ++q) {
-      const u32x4 b = *(g_uint4*)(rrow + 4 * q);
-      o.R[4 * q + 0] = b.x; o.R[4 * q + 1] = b.y; o.R[4 * q + 2] = b.z; o.R[4 * q + 3] = b.w;
-    }
+  for (int b = 0; b < (DC + COLS) / 4; ++b) {
+    const u32x4 t = *(g_uint4*)(rrow + lo + 4 * b);
+    o.R[4 * b] = t.x; o.R[4 * b + 1] = t.y; o.R[4 * b + 2] = t.z; o.R[4 * b + 3] = t.w;
   }
 }
 
-// A RowRegs whose lower right words start with some value (they are only
-// read after load_row and spread_row have written them).
+// Word 0 of the right columns is loaded (whole aligned blocks) but never used
+// in the sums; it is kept live up to the row's use so that every load writes
+// only live registers (a dead load destination that the compiler reused for
+// other work would make it wait for that load, and with it for every load
+// issued before it).
 template <int DC, int COLS>
-__device__ __forceinline__ void init_row(RowRegs<DC, COLS>& o) {
-#pragma unroll
-  for (int j = 0; j < DC; ++j) o.R[j] = __builtin_nondeterministic_value(0u);
-}
-
-// Completes the right columns once the loads of load_row have arrived: word
-// 1 <= j < DC of lane l is word j + COLS of lane l - 1 (DPP wave_shr:1; lane
-// 0 keeps its own load). Blocks of four go from the top down, so a source
-// word below DC has been completed before it is read.
-template <int DC, int COLS>
-__device__ __forceinline__ void spread_row(RowRegs<DC, COLS>& o) {
-  asm volatile("" ::"v"(o.R[0]));   // keeps word 0 live up to here (load_row)
-#pragma unroll
-  for (int q = DC / 4 - 1; q >= 0; --q)
-#pragma unroll
-    for (int w = (q == 0 ? 1 : 0); w < 4; ++w)
-      o.R[4 * q + w] = (uint32_t)__builtin_amdgcn_update_dpp((int)o.R[4 * q + w], (int)o.R[4 * q + w + COLS], 0x138,
-                                                             0xf, 0xf, false);
+__device__ __forceinline__ void keep_word0(const RowRegs<DC, COLS>& o) {
+  asm volatile("" ::"v"(o.R[0]));
 }
 
 // Accumulators per lane: kPack == false keeps one 32-bit sum per (column,
@@ -391,7 +363,7 @@ struct Acc {
 // Adds one padded row to the accumulators.
 template <int DC, bool kPack, int COLS>
 __device__ __forceinline__ void add_row(RowRegs<DC, COLS>& a, Acc<DC, kPack, COLS>& acc) {
-  spread_row<DC, COLS>(a);
+  keep_word0(a);
 #pragma unroll
   for (int c = 0; c < COLS; ++c)
 #pragma unroll
@@ -408,8 +380,8 @@ __device__ __forceinline__ void add_row(RowRegs<DC, COLS>& a, Acc<DC, kPack, COL
 // leaving row is taken off first, so no partial sum exceeds a full window.
 template <int DC, bool kPack, int COLS>
 __device__ __forceinline__ void slide_row(RowRegs<DC, COLS>& en, RowRegs<DC, COLS>& ex, Acc<DC, kPack, COLS>& acc) {
-  spread_row<DC, COLS>(en);
-  spread_row<DC, COLS>(ex);
+  keep_word0(en);
+  keep_word0(ex);
 #pragma unroll
   for (int c = 0; c < COLS; ++c)
 #pragma unroll
@@ -590,8 +562,6 @@ __device__ __forceinline__ void tile_item_impl(const FrameDev& f, int tile, int 
   {
     const int last = ya + 2 * r;
     RowRegs<DC, COLS> A, B;
-    init_row(A);
-    init_row(B);
     load_row<DC, COLS>(lp0 + ya * lpw, rp0 + ya * rpw, lo, A);
     for (int q = ya; q < last; q += 2) {
       load_row<DC, COLS>(lp0 + (q + 1) * lpw, rp0 + (q + 1) * rpw, lo, B);
@@ -740,8 +710,6 @@ __device__ __forceinline__ void tile_item_impl(const FrameDev& f, int tile, int 
   const uint32_t* lout = lp0 + (int64_t)ya * lpw;
   const uint32_t* rout = rp0 + (int64_t)ya * rpw;
   RowRegs<DC, COLS> En, Ex;
-  init_row(En);
-  init_row(Ex);
   load_row<DC, COLS>(lin, rin, lo, En);
   load_row<DC, COLS>(lout, rout, lo, Ex);
   // Row ya (active by construction), then the steps y = ya + 1 .. yb. A
