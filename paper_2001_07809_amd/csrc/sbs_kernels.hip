@@ -75,18 +75,37 @@ __global__ void k_reset_head(WsHeader* h) {
 }
 
 // Keys cleared, out-of-range entries answered, order checked.
+// Four list entries per thread and step: 16-byte loads and stores where the
+// caller's arrays allow them (idx 16-byte aligned; keys live in the
+// workspace), entry by entry otherwise.
 __global__ __launch_bounds__(256) void k_check(const FrameDev* __restrict__ table, int f0, WsHeader* hdr) {
   const FrameDev& f = table[f0 + blockIdx.y];
-  const int64_t N = (int64_t)f.W * f.H;
+  const int64_t N = (int64_t)f.W * f.H, n = f.n;
+  const uint32_t* idx = f.idx;
+  uint32_t* keys = f.keys;
+  const bool vec = ((uintptr_t)idx & 15u) == 0;
   bool unsorted = false;
-  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < f.n; k += (int64_t)gridDim.x * blockDim.x) {
-    const uint32_t p = f.idx[k];
-    f.keys[k] = 0xFFFFFFFFu;
-    if (k > 0 && f.idx[k - 1] > p) unsorted = true;
-    if ((int64_t)p >= N) {
-      f.out_disp[k] = 255;
-      if (f.out_cost) f.out_cost[k] = 0xFFFFFFFFu;
-      atomicOr(&hdr->error, 1u);
+  for (int64_t k = 4 * ((int64_t)blockIdx.x * blockDim.x + threadIdx.x); k < n; k += 4 * (int64_t)gridDim.x * blockDim.x) {
+    uint32_t p[4] = {0u, 0u, 0u, 0u};
+    if (vec && k + 3 < n) {
+      const u32x4 v = *(g_uint4*)(idx + k);
+      p[0] = v.x; p[1] = v.y; p[2] = v.z; p[3] = v.w;
+      *(g_uint4_rw*)(keys + k) = u32x4{0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu};
+    } else {
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (k + j < n) { p[j] = idx[k + j]; keys[k + j] = 0xFFFFFFFFu; }
+    }
+    if (k > 0 && idx[k - 1] > p[0]) unsorted = true;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if (k + j >= n) break;
+      if (j < 3 && k + j + 1 < n && p[j] > p[j + 1]) unsorted = true;
+      if ((int64_t)p[j] >= N) {
+        f.out_disp[k + j] = 255;
+        if (f.out_cost) f.out_cost[k + j] = 0xFFFFFFFFu;
+        atomicOr(&hdr->error, 1u);
+      }
     }
   }
   if (__builtin_amdgcn_ballot_w64(unsorted) && (threadIdx.x & 63) == 0) atomicOr(f.state, kUnsorted);
@@ -862,16 +881,52 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kWide ? 3 : 
   }
 }
 
+// Keys split into (disparity, cost), four entries per thread and step: one
+// 4-byte store of disparities and one 16-byte store of costs where the
+// caller's arrays allow them (out_disp 4-byte, out_cost and idx 16-byte
+// aligned). Entries out of range already hold 255 / ~0 from k_check; the
+// vector path writes those same values again.
 __global__ __launch_bounds__(256) void k_finalize(const FrameDev* __restrict__ table, int f0) {
   const FrameDev& f = table[f0 + blockIdx.y];
-  const int64_t N = (int64_t)f.W * f.H;
+  const int64_t N = (int64_t)f.W * f.H, n = f.n;
   const bool unsorted = (*f.state & kUnsorted) != 0;
-  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < f.n; k += (int64_t)gridDim.x * blockDim.x) {
-    const uint32_t p = f.idx[k];
-    if ((int64_t)p >= N) continue;
-    const uint32_t key = f.keys[unsorted ? (int64_t)f.map[p] : k];
-    f.out_disp[k] = (uint8_t)(key & 0xFFu);
-    if (f.out_cost) f.out_cost[k] = key >> 8;
+  const uint32_t* idx = f.idx;
+  const uint32_t* keys = f.keys;
+  uint8_t* od = f.out_disp;
+  uint32_t* oc = f.out_cost;
+  const bool vec = ((uintptr_t)idx & 15u) == 0 && ((uintptr_t)od & 3u) == 0 && ((uintptr_t)oc & 15u) == 0;
+  for (int64_t k = 4 * ((int64_t)blockIdx.x * blockDim.x + threadIdx.x); k < n; k += 4 * (int64_t)gridDim.x * blockDim.x) {
+    if (vec && k + 3 < n) {
+      const u32x4 v = *(g_uint4*)(idx + k);
+      const uint32_t p[4] = {v.x, v.y, v.z, v.w};
+      uint32_t key[4];
+      if (!unsorted) {
+        const u32x4 kv = *(g_uint4*)(keys + k);
+        key[0] = kv.x; key[1] = kv.y; key[2] = kv.z; key[3] = kv.w;
+      } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) key[j] = (int64_t)p[j] < N ? keys[f.map[p[j]]] : 0u;
+      }
+      uint32_t cost[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const bool out = (int64_t)p[j] >= N;   // (255, ~0) as k_check wrote them
+        cost[j] = out ? 0xFFFFFFFFu : key[j] >> 8;
+        key[j] = out ? 0xFFu : key[j] & 0xFFu;
+      }
+      *(__attribute__((address_space(1))) uint32_t*)(od + k) = key[0] | (key[1] << 8) | (key[2] << 16) | (key[3] << 24);
+      if (oc) *(g_uint4_rw*)(oc + k) = u32x4{cost[0], cost[1], cost[2], cost[3]};
+      continue;
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if (k + j >= n) break;
+      const uint32_t p = idx[k + j];
+      if ((int64_t)p >= N) continue;
+      const uint32_t key = keys[unsorted ? (int64_t)f.map[p] : k + j];
+      od[k + j] = (uint8_t)(key & 0xFFu);
+      if (oc) oc[k + j] = key >> 8;
+    }
   }
 }
 

@@ -416,3 +416,36 @@ def test_long_list_on_a_wide_frame(torch, sbs):
             assert_parity((d[pick], c[pick]), (ed, ec), f"long list, {cpl} columns per lane")
     finally:
         sbs.set_plan()
+
+
+def test_unaligned_caller_arrays(torch, sbs):
+    """List and outputs at offsets that rule out the 16- and 4-byte vector
+    paths of the list check and the finalize step (and at aligned offsets),
+    lengths with a ragged tail of 1..3 entries, out-of-range indices inside
+    and at the ends, ordered and unordered lists, with and without costs."""
+    rng = np.random.default_rng(43)
+    H, W = 70, 150
+    L = rng.integers(0, 256, (H, W, 3), dtype=np.uint8)
+    R = np.roll(L, 4, axis=1)
+    Ld, Rd = dev(torch, L), dev(torch, R)
+    for order in ("sorted", "shuffled"):
+        for n in (1, 2, 3, 4, 5, 999, 1002, 1003):
+            idx = np.sort(rng.choice(H * W, n, replace=False)).astype(np.uint32)
+            if order == "shuffled":
+                idx = rng.permutation(idx)
+            idx[rng.integers(0, n)] = H * W + 7          # out of range
+            if n > 2:
+                idx[0] = H * W
+                idx[-1] = 0xFFFFFFF0
+            exp = oracle.sad(L, R, idx, 9, 20)
+            for off_i, off_d, off_c in ((0, 0, 0), (1, 1, 1), (2, 3, 3), (3, 4, 2)):
+                ib = dev(torch, np.concatenate([np.zeros(off_i, np.uint32), idx]).view(np.int32))[off_i:]
+                out = torch.full((n + off_d,), 7, dtype=torch.uint8, device="cuda")[off_d:]
+                cost = torch.full((n + off_c,), 7, dtype=torch.int32, device="cuda")[off_c:]
+                d, c = sbs.sad_disparity(Ld, Rd, ib, 9, 20, out=out, cost=cost)
+                torch.cuda.synchronize()
+                what = f"{order} n {n} offsets {off_i},{off_d},{off_c}"
+                assert_parity((d.cpu().numpy(), c.cpu().numpy().view(np.uint32)), exp, what)
+                d2, c2 = sbs.sad_disparity(Ld, Rd, ib, 9, 20, out=out, with_cost=False)
+                torch.cuda.synchronize()
+                assert c2 is None and np.array_equal(d2.cpu().numpy(), exp[0]), what + " without costs"
