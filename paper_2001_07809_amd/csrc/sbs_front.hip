@@ -92,22 +92,35 @@ __device__ __forceinline__ void wave_count(uint32_t* h, uint32_t v, bool active)
   }
 }
 
-// Histogram: per-wavefront counts in LDS (four copies, fewer colliding
-// atomics), then one global add per bin and block.
+// Histogram: 16-byte loads (16 pixels per thread and step where the buffer
+// is 16-byte aligned), LDS atomic adds into 16 copies of the bins (lane l
+// uses copy l % 16; copies are 257 words apart, so equal values in different
+// copies fall in different banks), then one global add per bin and block.
+constexpr int kHistCopies = 16;
 __global__ __launch_bounds__(kBlock) void k_hist(const uint8_t* __restrict__ L8, int64_t N,
                                                  unsigned long long* __restrict__ hist) {
-  __shared__ uint32_t h[kBlock / 64][256];
-  for (int w = 0; w < kBlock / 64; ++w) h[w][threadIdx.x] = 0;
+  __shared__ uint32_t h[kHistCopies][257];
+  for (int i = threadIdx.x; i < kHistCopies * 257; i += blockDim.x) (&h[0][0])[i] = 0u;
   __syncthreads();
-  uint32_t* mine = h[threadIdx.x >> 6];
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x; i0 < N; i0 += stride) {   // uniform per wavefront
-    const int64_t i = i0 + threadIdx.x;
-    wave_count(mine, i < N ? L8[i] : 0u, i < N);
+  uint32_t* mine = h[threadIdx.x & (kHistCopies - 1)];
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, stride = (int64_t)gridDim.x * blockDim.x;
+  int64_t head = 0;
+  if (((uintptr_t)L8 & 15u) == 0) {
+    const int64_t nv = N >> 4;
+    for (int64_t v = tid; v < nv; v += stride) {
+      const uint4 q = *(const uint4*)(L8 + 16 * v);
+      const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) atomicAdd(&mine[(w[j] >> (8 * b)) & 0xFFu], 1u);
+    }
+    head = nv << 4;
   }
+  for (int64_t i = head + tid; i < N; i += stride) atomicAdd(&mine[L8[i]], 1u);
   __syncthreads();
   uint32_t t = 0;
-  for (int w = 0; w < kBlock / 64; ++w) t += h[w][threadIdx.x];
+  for (int c = 0; c < kHistCopies; ++c) t += h[c][threadIdx.x];
   if (t) atomicAdd(&hist[threadIdx.x], (unsigned long long)t);
 }
 
@@ -269,44 +282,137 @@ __global__ __launch_bounds__(kBlock) void k_cc_init(const uint8_t* __restrict__ 
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_cc_merge(const uint8_t* __restrict__ B, int32_t W, int32_t H,
-                                                     int32_t* parent) {
-  const int x = blockIdx.x * 64 + (threadIdx.x & 63);
-  const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
-  if (x >= W || y >= H) return;
-  const int32_t i = y * W + x;
-  if (!B[i]) return;
-  // the four neighbours before this pixel in raster order (8-connectivity)
-  if (x > 0 && B[i - 1]) uf_union(parent, i, i - 1);
-  if (y > 0) {
-    const int32_t u = i - W;
-    if (x > 0 && B[u - 1]) uf_union(parent, i, u - 1);
-    if (B[u]) uf_union(parent, i, u);
-    if (x + 1 < W && B[u + 1]) uf_union(parent, i, u + 1);
+// Two-level merge. k_cc_tile: one block per tile of kTileW x kTileH pixels
+// runs the same union-find on the tile's pixels in LDS (links from larger to
+// smaller local raster index, which is the global raster order within the
+// tile), then writes for every boundary pixel the global index of its tile
+// root. k_cc_edges then unions, through the global forest, only the
+// neighbour pairs that cross a tile edge. The forest's roots stay the
+// smallest raster index of their component.
+constexpr int kTileW = 64, kTileH = 16;
+
+__device__ __forceinline__ int32_t lds_find(int32_t* lp, int32_t a) {
+  for (;;) {
+    const int32_t p = lp[a];
+    if (p == a) return a;
+    const int32_t pp = lp[p];
+    if (pp == p) return p;
+    atomicMin(&lp[a], pp);
+    a = pp;
   }
 }
 
-// Roots for every pixel, and component sizes at the roots: a run of lanes
-// with the same root (neighbours in a row mostly share it) adds its length
-// with one atomic.
-__global__ __launch_bounds__(kBlock) void k_cc_flatten(int64_t N, int32_t* parent, int32_t* size) {
-  const int lane = (int)(threadIdx.x & 63);
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x; i0 < N; i0 += stride) {   // uniform per wavefront
-    const int64_t i = i0 + threadIdx.x;
-    int32_t r = -1;
-    if (i < N && parent[i] >= 0) {
-      r = uf_find(parent, (int32_t)i);
-      parent[i] = r;
+__device__ __forceinline__ void lds_union(int32_t* lp, int32_t a, int32_t b) {
+  for (;;) {
+    a = lds_find(lp, a);
+    b = lds_find(lp, b);
+    if (a == b) return;
+    if (a < b) { const int32_t t = a; a = b; b = t; }
+    const int32_t old = atomicMin(&lp[a], b);
+    if (old == a) return;
+    a = old;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_cc_tile(const uint8_t* __restrict__ B, int32_t W, int32_t H,
+                                                    int32_t* parent, int32_t* size) {
+  __shared__ int32_t lp[kTileW * kTileH];
+  __shared__ int32_t lsz[kTileW * kTileH];
+  const int x0 = blockIdx.x * kTileW, y0 = blockIdx.y * kTileH;
+  const int lx = threadIdx.x & (kTileW - 1);
+  constexpr int kRowsPerPass = kBlock / kTileW;
+  bool on[kTileH / kRowsPerPass];
+#pragma unroll
+  for (int j = 0; j < kTileH / kRowsPerPass; ++j) {
+    const int ly = (int)(threadIdx.x / kTileW) + kRowsPerPass * j;
+    const int x = x0 + lx, y = y0 + ly;
+    on[j] = x < W && y < H && B[(int64_t)y * W + x] != 0;
+    lp[ly * kTileW + lx] = on[j] ? ly * kTileW + lx : -1;
+    lsz[ly * kTileW + lx] = 0;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < kTileH / kRowsPerPass; ++j) {
+    if (!on[j]) continue;
+    const int ly = (int)(threadIdx.x / kTileW) + kRowsPerPass * j;
+    const int l = ly * kTileW + lx;
+    // the tile's neighbours before this pixel in raster order (8-connectivity)
+    if (lx > 0 && lp[l - 1] >= 0) lds_union(lp, l, l - 1);
+    if (ly > 0) {
+      const int u = l - kTileW;
+      if (lx > 0 && lp[u - 1] >= 0) lds_union(lp, l, u - 1);
+      if (lp[u] >= 0) lds_union(lp, l, u);
+      if (lx + 1 < kTileW && lp[u + 1] >= 0) lds_union(lp, l, u + 1);
     }
-    const int32_t prev = __shfl_up(r, 1, 64);
-    const bool start = r >= 0 && (lane == 0 || prev != r);
-    const uint64_t starts = __builtin_amdgcn_ballot_w64(start);
-    const uint64_t breaks = starts | __builtin_amdgcn_ballot_w64(r < 0);   // a run ends at a start or an empty lane
-    if (start) {
-      const uint64_t after = lane == 63 ? 0ull : (breaks >> (lane + 1));
-      const int len = after ? __builtin_ctzll(after) + 1 : 64 - lane;
-      atomicAdd(&size[r], len);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < kTileH / kRowsPerPass; ++j) {
+    if (!on[j]) continue;
+    const int ly = (int)(threadIdx.x / kTileW) + kRowsPerPass * j;
+    const int32_t r = lds_find(lp, ly * kTileW + lx);
+    parent[(int64_t)(y0 + ly) * W + x0 + lx] = (y0 + r / kTileW) * W + x0 + (r % kTileW);
+    atomicAdd(&lsz[r], 1);
+  }
+  __syncthreads();
+  // each tile root's local component size, at the root (the rest stay 0)
+#pragma unroll
+  for (int j = 0; j < kTileH / kRowsPerPass; ++j) {
+    const int ly = (int)(threadIdx.x / kTileW) + kRowsPerPass * j;
+    const int l = ly * kTileW + lx;
+    if (on[j] && lsz[l] > 0) size[(int64_t)(y0 + ly) * W + x0 + lx] = lsz[l];
+  }
+}
+
+// Neighbour pairs across tile edges: thread t of a tile's block takes edge
+// pixel t (its top row, then its left and right columns below the top row).
+__global__ __launch_bounds__(128) void k_cc_edges(const uint8_t* __restrict__ B, int32_t W, int32_t H,
+                                                  int32_t* parent) {
+  const int x0 = blockIdx.x * kTileW, y0 = blockIdx.y * kTileH;
+  const int t = threadIdx.x;
+  int lx, ly;
+  if (t < kTileW) { lx = t; ly = 0; }
+  else if (t < kTileW + kTileH - 1) { lx = 0; ly = t - kTileW + 1; }
+  else if (t < kTileW + 2 * (kTileH - 1)) { lx = kTileW - 1; ly = t - kTileW - kTileH + 2; }
+  else return;
+  const int x = x0 + lx, y = y0 + ly;
+  if (x >= W || y >= H) return;
+  const int32_t i = y * W + x;
+  if (!B[i]) return;
+  // raster-earlier neighbours that lie in another tile
+  if (x > 0 && lx == 0 && B[i - 1]) uf_union(parent, i, i - 1);
+  if (y > 0) {
+    const int32_t u = i - W;
+    if (x > 0 && (lx == 0 || ly == 0) && B[u - 1]) uf_union(parent, i, u - 1);
+    if (ly == 0 && B[u]) uf_union(parent, i, u);
+    if (x + 1 < W && (ly == 0 || lx == kTileW - 1) && B[u + 1]) uf_union(parent, i, u + 1);
+  }
+}
+
+// Roots for every pixel (plain loads: the forest is final), and component
+// sizes at the roots: k_cc_tile left each tile root's local size at the tile
+// root; a tile root that is not its component's root moves its count to the
+// root with one atomic. Roots of components are always tile roots (a
+// component's smallest index is the smallest of its tile part), so no count
+// moves into a tile root that moves its own count away.
+__global__ __launch_bounds__(kBlock) void k_cc_flatten(int64_t N, int32_t* parent, int32_t* size) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += stride) {
+    if (parent[i] < 0) continue;
+    // No link changes after the merge kernels except pixels being pointed at
+    // their root here, so any value read (cached, possibly stale) is an
+    // ancestor of i and the walk ends at i's root.
+    const int32_t t = parent[i];   // its tile root (or, for tile-edge pixels, an ancestor of it)
+    int32_t r = t;
+    for (int32_t q = parent[r]; q != r; q = parent[r]) r = q;
+    parent[i] = r;
+    if (t != r) parent[t] = r;     // shortcut: the tile's other pixels reach r in two steps
+    if (r != (int32_t)i) {
+      const int32_t sz = size[i];
+      if (sz > 0) {
+        size[i] = 0;
+        atomicAdd(&size[r], sz);
+      }
     }
   }
 }
@@ -882,7 +988,8 @@ int sbs_boundaries(const uint8_t* img, int32_t W, int32_t H, int32_t C, int64_t 
   hipLaunchKernelGGL(k_fill, dim3(1), dim3(kBlock), 0, s, (uint8_t*)hist, (int64_t)(256 * 8), (uint8_t)0);
   hipLaunchKernelGGL(k_fill, dim3(1), dim3(kBlock), 0, s, (uint8_t*)misc, (int64_t)1024, (uint8_t)0);
   hipLaunchKernelGGL(k_light, dim3(g), dim3(kBlock), 0, s, img, W, H, C, pitch, L8);
-  hipLaunchKernelGGL(k_hist, dim3(g), dim3(kBlock), 0, s, L8, N, hist);
+  // at most 512 blocks: each ends with up to 256 global adds
+  hipLaunchKernelGGL(k_hist, dim3(std::min(grid_for((N + 15) / 16), 512)), dim3(kBlock), 0, s, L8, N, hist);
   hipLaunchKernelGGL(k_kmeans, dim3(1), dim3(256), 0, s, hist, K, lut, passes);
   hipLaunchKernelGGL(k_label, dim3(g), dim3(kBlock), 0, s, L8, N, lut, lab);
   const uint8_t* labels = lab;
@@ -903,7 +1010,9 @@ int sbs_boundaries(const uint8_t* img, int32_t W, int32_t H, int32_t C, int64_t 
     if (ce != hipSuccess) return fail(SBS_ERR_HIP, "boundaries: %s", hipGetErrorString(ce));
   }
   hipLaunchKernelGGL(k_cc_init, dim3(g), dim3(kBlock), 0, s, B, N, parent, size);
-  hipLaunchKernelGGL(k_cc_merge, g2, dim3(kBlock), 0, s, B, W, H, parent);
+  const dim3 gt((W + kTileW - 1) / kTileW, (H + kTileH - 1) / kTileH);
+  hipLaunchKernelGGL(k_cc_tile, gt, dim3(kBlock), 0, s, B, W, H, parent, size);
+  hipLaunchKernelGGL(k_cc_edges, gt, dim3(128), 0, s, B, W, H, parent);
   hipLaunchKernelGGL(k_cc_flatten, dim3(g), dim3(kBlock), 0, s, N, parent, size);
 
   const int64_t nb = (N + kScanPer - 1) / kScanPer;

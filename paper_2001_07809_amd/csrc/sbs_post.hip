@@ -5,6 +5,8 @@
 //   * depth-based selective blurring with the normalised Gaussian of Eq. 1-2.
 // Declared in include/sbs.h.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 #include <stdint.h>
 
 #include <cmath>
@@ -88,22 +90,55 @@ __global__ __launch_bounds__(kRowThreads) void k_rc_fill(const int32_t* slot, co
   }
 }
 
-// Algorithm 2 on one column per thread: an undetermined pixel takes the
-// smaller of its nearest determined pixels above and below when their range
-// exceeds the threshold, else their mean rounded half up; one-sided when only
-// one exists; 0 when the column has none. Reads only Algorithm 1's output.
-__global__ __launch_bounds__(256) void k_rc_peek(const int16_t* f, int32_t W, int32_t H, int32_t threshold,
-                                                 int16_t* up, uint8_t* out) {
+// Algorithm 2: an undetermined pixel takes the smaller of its nearest
+// determined pixels above and below when their range exceeds the threshold,
+// else their mean rounded half up; one-sided when only one exists; 0 when the
+// column has none. Reads only Algorithm 1's output, so every column is
+// independent. A column is cut into segments of `seglen` rows (64, more for
+// images over 4M rows so the segments fit the grid), one thread per
+// (column, segment): k_rc_colseg records each segment's topmost and
+// bottommost determined value, then k_rc_peek takes the nearest determined
+// values above and below the segment from those records and resolves the
+// segment's rows in two passes (threads of a block cover adjacent columns,
+// so every row access is coalesced).
+constexpr int kColSeg = 64;
+
+__global__ __launch_bounds__(256) void k_rc_colseg(const int16_t* f, int32_t W, int32_t H, int32_t seglen,
+                                                   int16_t* seg_first, int16_t* seg_last) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int sg = blockIdx.y;
   if (x >= W) return;
+  const int y0 = sg * seglen, y1 = min(y0 + seglen, H);
+  int16_t first = -1, last = -1;
+  for (int y = y0; y < y1; ++y) {
+    const int16_t v = f[(int64_t)y * W + x];
+    if (v >= 0) {
+      if (first < 0) first = v;
+      last = v;
+    }
+  }
+  seg_first[(int64_t)sg * W + x] = first;
+  seg_last[(int64_t)sg * W + x] = last;
+}
+
+__global__ __launch_bounds__(256) void k_rc_peek(const int16_t* f, int32_t W, int32_t H, int32_t threshold,
+                                                 int32_t seglen, const int16_t* seg_first, const int16_t* seg_last,
+                                                 int32_t nseg, int16_t* up, uint8_t* out) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int sg = blockIdx.y;
+  if (x >= W) return;
+  const int y0 = sg * seglen, y1 = min(y0 + seglen, H);
+  // nearest determined value above the segment, and below it
   int16_t last = -1;
-  for (int y = 0; y < H; ++y) {
+  for (int t = sg - 1; t >= 0 && last < 0; --t) last = seg_last[(int64_t)t * W + x];
+  int16_t below = -1;
+  for (int t = sg + 1; t < nseg && below < 0; ++t) below = seg_first[(int64_t)t * W + x];
+  for (int y = y0; y < y1; ++y) {
     const int16_t v = f[(int64_t)y * W + x];
     up[(int64_t)y * W + x] = last;
     if (v >= 0) last = v;
   }
-  int16_t below = -1;
-  for (int y = H - 1; y >= 0; --y) {
+  for (int y = y1 - 1; y >= y0; --y) {
     const int64_t q = (int64_t)y * W + x;
     const int16_t v = f[q];
     if (v >= 0) {
@@ -212,7 +247,16 @@ int sbs_reconstruct(const uint32_t* idx, const uint8_t* disp, int64_t n, int32_t
   hipLaunchKernelGGL(k_rc_clear, dim3(1024), dim3(256), 0, s, slot, N);
   if (n > 0) hipLaunchKernelGGL(k_rc_scatter, dim3(256), dim3(256), 0, s, idx, n, N, slot);
   hipLaunchKernelGGL(k_rc_fill, dim3(H < 4096 ? H : 4096), dim3(kRowThreads), 0, s, slot, disp, W, H, f);
-  hipLaunchKernelGGL(k_rc_peek, dim3((W + 255) / 256), dim3(256), 0, s, f, W, H, threshold, up, out_map);
+  // The column pass's segment records reuse the slot array (no longer read
+  // after k_rc_fill): 2 x nseg x W int16 <= 4 x W x H bytes.
+  const int seglen = std::max(kColSeg, (H + 65534) / 65535);
+  const int nseg = (H + seglen - 1) / seglen;
+  int16_t* seg_first = (int16_t*)slot;
+  int16_t* seg_last = seg_first + (int64_t)nseg * W;
+  const dim3 cg((W + 255) / 256, nseg);
+  hipLaunchKernelGGL(k_rc_colseg, cg, dim3(256), 0, s, f, W, H, seglen, seg_first, seg_last);
+  hipLaunchKernelGGL(k_rc_peek, cg, dim3(256), 0, s, f, W, H, threshold, seglen, seg_first, seg_last, nseg, up,
+                     out_map);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(SBS_ERR_HIP, "reconstruct: %s", hipGetErrorString(e));
   return SBS_OK;

@@ -43,6 +43,23 @@ def test_reconstruct_unordered_duplicates_and_edges(mods):
         np.testing.assert_array_equal(got.cpu().numpy(), exp, err_msg=f"{W}x{H}")
 
 
+def test_reconstruct_sparse_columns_across_segments(mods):
+    """Few listed pixels on tall images: the column pass resolves rows from
+    determined pixels many 64-row segments away, in columns with one, several
+    or no determined pixels; heights on and off a multiple of 64."""
+    torch, sbs = mods
+    rng = np.random.default_rng(6)
+    for (W, H, n) in [(130, 700, 40), (3, 1000, 5), (64, 128, 10), (257, 64, 7), (90, 1, 3), (77, 641, 400)]:
+        idx = np.sort(rng.choice(W * H, n, replace=False)).astype(np.uint32)
+        disp = rng.integers(0, 40, n).astype(np.uint8)
+        for threshold in (0, 3):
+            exp = oracle.reconstruct(idx, disp, W, H, threshold)
+            got = sbs.reconstruct(torch.from_numpy(idx.view(np.int32)).cuda(), torch.from_numpy(disp).cuda(), W, H,
+                                  threshold)
+            torch.cuda.synchronize()
+            np.testing.assert_array_equal(got.cpu().numpy(), exp, err_msg=f"{W}x{H} n {n} t {threshold}")
+
+
 @pytest.mark.parametrize("C,sigma", [(1, 0.8), (3, 1.5), (3, 4.0)])
 def test_blur_matches_oracle(mods, C, sigma):
     torch, sbs = mods
