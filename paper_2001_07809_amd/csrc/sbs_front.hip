@@ -61,7 +61,7 @@ __global__ __launch_bounds__(kBlock) void k_light(const uint8_t* __restrict__ im
   const double e = 6.0 / 29.0;
   const double e3 = e * e * e, k3 = 3 * e * e;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
-    const int y = (int)(i / W), x = (int)(i % W);
+    const int y = (int)((uint32_t)i / (uint32_t)W), x = (int)((uint32_t)i % (uint32_t)W);   // N < 2^31
     const uint8_t* p = img + (int64_t)y * pitch + (int64_t)x * C;
     if (C == 1) { L8[i] = p[0]; continue; }
     const double Y = 0.2126 * lin[p[0]] + 0.7152 * lin[p[1]] + 0.0722 * lin[p[2]];
@@ -74,22 +74,6 @@ __global__ __launch_bounds__(kBlock) void k_light(const uint8_t* __restrict__ im
 
 __global__ __launch_bounds__(kBlock) void k_fill(uint8_t* p, int64_t n, uint8_t v) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
-}
-
-// Histogram: per-block counts in LDS, then one global add per bin.
-// Adds 1 at h[v] for every active lane, one atomic per distinct v in the
-// wavefront (lanes with equal values are found by ballot). Pays off where
-// neighbouring pixels share values, as in images and distance maps.
-__device__ __forceinline__ void wave_count(uint32_t* h, uint32_t v, bool active) {
-  uint64_t pending = __builtin_amdgcn_ballot_w64(active);
-  const int lane = (int)(threadIdx.x & 63);
-  while (pending) {
-    const int leader = __builtin_ctzll(pending);
-    const uint32_t lv = (uint32_t)__builtin_amdgcn_readlane((int)v, leader);
-    const uint64_t same = __builtin_amdgcn_ballot_w64(active && v == lv);
-    if (lane == leader) atomicAdd(&h[lv], (uint32_t)__builtin_popcountll(same));
-    pending &= ~same;
-  }
 }
 
 // Histogram: 16-byte loads (16 pixels per thread and step where the buffer
@@ -565,7 +549,7 @@ __device__ __forceinline__ unsigned long long mix64(unsigned long long z) {
 }
 
 __device__ __forceinline__ bool border(const ScanCtx& c, int64_t i) {
-  const int x = (int)(i % c.W);
+  const int x = (int)((uint32_t)i % (uint32_t)c.W);   // W * H < 2^31: 32-bit division suffices
   return x == 0 || x == c.W - 1;
 }
 
@@ -577,8 +561,8 @@ __device__ __forceinline__ bool selected(const ScanCtx& c, int64_t i) {
   const FracState& f = *c.fc;
   if (f.mode == 0) {
     if (!b) return false;
-    const int64_t y = i / c.W;
-    const int64_t rank0 = c.W == 1 ? y : 2 * y + ((i % c.W) == c.W - 1 ? 1 : 0);
+    const int64_t y = (uint32_t)i / (uint32_t)c.W;
+    const int64_t rank0 = c.W == 1 ? y : 2 * y + (((uint32_t)i % (uint32_t)c.W) == (uint32_t)(c.W - 1) ? 1 : 0);
     return rank0 < f.want;
   }
   if (b) return true;
@@ -743,28 +727,29 @@ __device__ __forceinline__ bool rs_key(const ScanCtx& c, int64_t i, unsigned lon
   return true;
 }
 
+// One radix-select pass: counts of the candidates' digit at `shift` among
+// keys whose higher digits match the prefix so far, in 16 bank-staggered LDS
+// copies (lane l adds to copy l % 16; see k_hist), then one global add per
+// digit and block.
 template <int SEL>
 __global__ __launch_bounds__(kBlock) void k_rs_hist(ScanCtx c, const RadixSel* rs, int shift, uint32_t* hist) {
-  __shared__ uint32_t h[256];
-  h[threadIdx.x] = 0;
+  __shared__ uint32_t h[kHistCopies][257];
+  for (int i = threadIdx.x; i < kHistCopies * 257; i += blockDim.x) (&h[0][0])[i] = 0u;
   __syncthreads();
+  uint32_t* mine = h[threadIdx.x & (kHistCopies - 1)];
   const unsigned long long pre = rs->prefix;
   const int hi = shift + 8;   // digits above this one must match the prefix
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x; i0 < c.N; i0 += stride) {   // uniform per wavefront
-    const int64_t i = i0 + threadIdx.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < c.N; i += stride) {
     unsigned long long key = 0;
-    bool cand = i < c.N && rs_key<SEL>(c, i, key);
+    bool cand = rs_key<SEL>(c, i, key);
     if (cand && hi < 64 && (key >> hi) != (pre >> hi)) cand = false;
-    const uint32_t digit = (uint32_t)((key >> shift) & 0xFF);
-    if constexpr (SEL == 3) {   // hash digits: spread out, plain atomics
-      if (cand) atomicAdd(&h[digit], 1u);
-    } else {                    // sizes and distances: runs of equal digits
-      wave_count(h, digit, cand);
-    }
+    if (cand) atomicAdd(&mine[(uint32_t)((key >> shift) & 0xFF)], 1u);
   }
   __syncthreads();
-  if (h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], h[threadIdx.x]);
+  uint32_t t = 0;
+  for (int k = 0; k < kHistCopies; ++k) t += h[k][threadIdx.x];
+  if (t) atomicAdd(&hist[threadIdx.x], t);
 }
 
 __global__ __launch_bounds__(256) void k_rs_pick(RadixSel* rs, int shift, uint32_t* hist) {
@@ -802,7 +787,7 @@ __device__ __forceinline__ bool in_set(const ScanCtx& c, int64_t i) { return c.c
 __global__ __launch_bounds__(kBlock) void k_dt_seg(ScanCtx c, int32_t H, int32_t nseg, int32_t* last, int32_t* first) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= (int64_t)nseg * c.W) return;
-  const int x = (int)(t % c.W), sg = (int)(t / c.W);
+  const int x = (int)((uint32_t)t % (uint32_t)c.W), sg = (int)((uint32_t)t / (uint32_t)c.W);   // t < N < 2^31
   int lo = -1, fi = kFar;
   for (int y = sg * kSegRows; y < min(H, (sg + 1) * kSegRows); ++y)
     if (in_set(c, (int64_t)y * c.W + x)) { lo = y; if (fi == kFar) fi = y; }
@@ -834,7 +819,7 @@ __global__ __launch_bounds__(kBlock) void k_dt_col(ScanCtx c, int32_t H, int32_t
                                                    const int32_t* down, int32_t* g) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= (int64_t)nseg * c.W) return;
-  const int x = (int)(t % c.W), sg = (int)(t / c.W);
+  const int x = (int)((uint32_t)t % (uint32_t)c.W), sg = (int)((uint32_t)t / (uint32_t)c.W);   // t < N < 2^31
   const int y0 = sg * kSegRows, y1 = min(H, (sg + 1) * kSegRows);
   int u = up[t];
   for (int y = y0; y < y1; ++y) {
@@ -1038,8 +1023,10 @@ int sbs_boundaries(const uint8_t* img, int32_t W, int32_t H, int32_t C, int64_t 
     hipLaunchKernelGGL(k_fc_class, dim3(g), dim3(kBlock), 0, s, c, cls, n1);
     hipLaunchKernelGGL(k_fc_plan, dim3(1), dim3(1), 0, s, fs, n1, want, n0);
     c.fc = fs; c.dist = dist; c.frank = frank; c.seed = (unsigned long long)seed; c.cls = cls;
+    // radix-select histograms: at most 512 blocks (each ends with up to 256 global adds)
+    const int gr = std::min(g, 512);
     for (int sh = 24; sh >= 0; sh -= 8) {      // kept pixels: size descending
-      hipLaunchKernelGGL(k_rs_hist<1>, dim3(g), dim3(kBlock), 0, s, c, &fs->s1, sh, rhist);
+      hipLaunchKernelGGL(k_rs_hist<1>, dim3(gr), dim3(kBlock), 0, s, c, &fs->s1, sh, rhist);
       hipLaunchKernelGGL(k_rs_pick, dim3(1), dim3(256), 0, s, &fs->s1, sh, rhist);
     }
     hipLaunchKernelGGL(k_scan_count<2>, dim3((unsigned)nb), dim3(kBlock), 0, s, c, bsum);
@@ -1060,12 +1047,16 @@ int sbs_boundaries(const uint8_t* img, int32_t W, int32_t H, int32_t C, int64_t 
     }
     hipLaunchKernelGGL(k_dt_row, dim3(H < 16384 ? H : 16384), dim3(kBlock), 0, s, c, H, gcol, dist);
     for (int sh = 24; sh >= 0; sh -= 8) {      // other pixels: distance
-      hipLaunchKernelGGL(k_rs_hist<2>, dim3(g), dim3(kBlock), 0, s, c, &fs->s2, sh, rhist);
+      // Distances are below W (the border columns are selected), so digits at
+      // and above a power of two >= W are 0 for every candidate: the pick
+      // would add 0 to the prefix and to the count below, so the pass is skipped.
+      if (sh >= 8 && (int64_t)W <= (1LL << sh)) continue;
+      hipLaunchKernelGGL(k_rs_hist<2>, dim3(gr), dim3(kBlock), 0, s, c, &fs->s2, sh, rhist);
       hipLaunchKernelGGL(k_rs_pick, dim3(1), dim3(256), 0, s, &fs->s2, sh, rhist);
     }
     hipLaunchKernelGGL(k_fc_after_dist, dim3(1), dim3(1), 0, s, fs);
     for (int sh = 56; sh >= 0; sh -= 8) {      // other pixels at that distance: hash
-      hipLaunchKernelGGL(k_rs_hist<3>, dim3(g), dim3(kBlock), 0, s, c, &fs->s3, sh, rhist);
+      hipLaunchKernelGGL(k_rs_hist<3>, dim3(gr), dim3(kBlock), 0, s, c, &fs->s3, sh, rhist);
       hipLaunchKernelGGL(k_rs_pick, dim3(1), dim3(256), 0, s, &fs->s3, sh, rhist);
     }
     hipLaunchKernelGGL(k_scan_count<3>, dim3((unsigned)nb), dim3(kBlock), 0, s, c, bsum);

@@ -168,43 +168,45 @@ struct BlurArgs {
   int32_t rad, nranges;
 };
 
+// One thread per pixel and all its channels (pixel indices are below 2^31,
+// so the row and column come from 32-bit division).
 __global__ __launch_bounds__(256) void k_blur_h(const uint8_t* img, int32_t W, int32_t H, int32_t C, int64_t pitch,
                                                 BlurArgs a, float* tmp) {
-  const int64_t total = (int64_t)W * H * C;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
-    const int c = (int)(i % C);
-    const int64_t px = i / C;
-    const int x = (int)(px % W), y = (int)(px / W);
+  const int64_t N = (int64_t)W * H;
+  for (int64_t px = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; px < N; px += (int64_t)gridDim.x * blockDim.x) {
+    const int x = (int)((uint32_t)px % (uint32_t)W), y = (int)((uint32_t)px / (uint32_t)W);
     const uint8_t* row = img + (int64_t)y * pitch;
-    float s = 0.f;
-    for (int k = -a.rad; k <= a.rad; ++k) {
-      const int xx = min(max(x + k, 0), W - 1);
-      s += a.g[k + a.rad] * (float)row[(int64_t)xx * C + c];
+    for (int c = 0; c < C; ++c) {
+      float s = 0.f;
+      for (int k = -a.rad; k <= a.rad; ++k) {
+        const int xx = min(max(x + k, 0), W - 1);
+        s += a.g[k + a.rad] * (float)row[(int64_t)xx * C + c];
+      }
+      tmp[px * C + c] = s;
     }
-    tmp[i] = s;
   }
 }
 
 __global__ __launch_bounds__(256) void k_blur_v(const uint8_t* img, const uint8_t* depth, int32_t W, int32_t H,
                                                 int32_t C, int64_t pitch, BlurArgs a, const float* tmp, float* out) {
-  const int64_t total = (int64_t)W * H * C;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
-    const int c = (int)(i % C);
-    const int64_t px = i / C;
-    const int x = (int)(px % W), y = (int)(px / W);
+  const int64_t N = (int64_t)W * H;
+  for (int64_t px = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; px < N; px += (int64_t)gridDim.x * blockDim.x) {
+    const int x = (int)((uint32_t)px % (uint32_t)W), y = (int)((uint32_t)px / (uint32_t)W);
     const int dv = depth[px];
     bool keep = false;
     for (int t = 0; t < a.nranges; ++t) keep |= (dv >= a.lo[t] && dv <= a.hi[t]);
     if (keep) {
-      out[i] = (float)img[(int64_t)y * pitch + (int64_t)x * C + c];
+      for (int c = 0; c < C; ++c) out[px * C + c] = (float)img[(int64_t)y * pitch + (int64_t)x * C + c];
       continue;
     }
-    float s = 0.f;
-    for (int k = -a.rad; k <= a.rad; ++k) {
-      const int yy = min(max(y + k, 0), H - 1);
-      s += a.g[k + a.rad] * tmp[((int64_t)yy * W + x) * C + c];
+    for (int c = 0; c < C; ++c) {
+      float s = 0.f;
+      for (int k = -a.rad; k <= a.rad; ++k) {
+        const int yy = min(max(y + k, 0), H - 1);
+        s += a.g[k + a.rad] * tmp[((int64_t)yy * W + x) * C + c];
+      }
+      out[px * C + c] = s;
     }
-    out[i] = s;
   }
 }
 
