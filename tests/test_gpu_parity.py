@@ -449,3 +449,39 @@ def test_unaligned_caller_arrays(torch, sbs):
                 d2, c2 = sbs.sad_disparity(Ld, Rd, ib, 9, 20, out=out, with_cost=False)
                 torch.cuda.synchronize()
                 assert c2 is None and np.array_equal(d2.cpu().numpy(), exp[0]), what + " without costs"
+
+
+def test_benchmark_configuration_sampled(torch, sbs):
+    """Full-size frames of the benchmark's video (4096x2304 RGB, block 31,
+    dmax 127, per-frame boundary fractions) through the batched persistent
+    launch with the plan the benchmark runs (16-disparity chunks, 128-row
+    tiles, 16 workgroups per CU; twelve frames already give the default plan
+    that choice): every frame checked against the oracle on sampled entries,
+    including each frame's first and last list entries."""
+    spec = scenes.PRESETS["uhd_video"]
+    F = 12
+    left, right, lists = _video(spec, F)
+    frames, keep = [], []
+    for t in range(F):
+        Ld, Rd, Id = dev(torch, left[t]), dev(torch, right[t]), dev(torch, lists[t].view(np.int32))
+        keep += [Ld, Rd, Id]
+        frames.append((Ld, Rd, Id, spec.block, spec.dmax))
+    rng = np.random.default_rng(17)
+    try:
+        for forced in (True, False):
+            if forced:
+                sbs.set_plan(cols_per_lane=4, chunk=16, tile_rows=128, waves_per_cu=16)
+            else:
+                sbs.set_plan()
+            runner = sbs.BatchRunner(frames)
+            runner.run()
+            torch.cuda.synchronize()
+            for t in range(F):
+                n = lists[t].size
+                pick = np.unique(np.concatenate([rng.choice(n, 250, replace=False), [0, n - 1]]))
+                exp = oracle.sad(left[t], right[t], lists[t][pick], spec.block, spec.dmax)
+                got = (runner.disp[t].cpu().numpy()[pick], runner.cost[t].cpu().numpy().view(np.uint32)[pick])
+                assert_parity(got, exp, f"frame {t} ({'benchmark plan' if forced else 'default plan'})")
+            assert runner.check_indices() == 0
+    finally:
+        sbs.set_plan()
