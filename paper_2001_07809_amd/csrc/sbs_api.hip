@@ -385,6 +385,7 @@ int run(const sbs_frame* frames, int nframes, void* workspace, size_t ws_bytes, 
     d.r = (f.block - 1) / 2;
     d.pack = packs(f) ? 1 : 0;
     d.cpl = cpl[(size_t)i];
+    d.linpl = (f.C == 3 && ((uintptr_t)f.left & 3) == 0 && (f.pitch_bytes & 3) == 0) ? 1 : 0;
     d.dmax = f.dmax;
     d.lpw = L.lpw; d.rpw = L.rpw; d.ph = L.ph; d.lpad = L.lpad; d.rpad = L.rpad; d.rbw = L.rbw;
     d.txo = L.txo;

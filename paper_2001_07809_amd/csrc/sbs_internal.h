@@ -23,7 +23,7 @@ struct FrameDev {
   uint32_t* out_cost;
   int32_t* map;        // W*H: a representative list slot per pixel, or -1
   uint32_t* keys;      // n: (cost << 8) | d, running minimum per representative slot
-  uint32_t* lp;        // left copy, RGBx u32 per pixel, replicate-padded
+  uint32_t* lp;        // left copy, RGBx u32 per pixel, replicate-padded (edge bands only when linpl)
   uint32_t* rp;        // right copy, RGBx u32 per pixel, replicate-padded
   uint64_t* rowbits;   // per row: one bit per 64-column group holding a listed pixel
   uint32_t* state;     // bit 0: the list is not in non-decreasing raster order
@@ -44,6 +44,8 @@ struct FrameDev {
   int32_t tpw;           // entries per row of tptr (ntx + 1)
   int32_t pack;          // 1: the sum of two window columns (<= 2 * block * 255 * C) fits in 16 bits
   int32_t cpl;           // window columns per lane: 4, or 8 (ordered lists, 8-disparity chunks, pack == 1)
+  int32_t linpl;         // 1: tiles whose window lies inside the image read the left image in place
+                         // (C == 3, 4-byte-aligned rows); the left copy then holds only the edge bands
 };
 
 struct DescBatch {

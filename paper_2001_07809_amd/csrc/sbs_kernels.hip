@@ -144,6 +144,14 @@ __global__ __launch_bounds__(256) void k_prep(const FrameDev* __restrict__ table
   const FrameDev& f = table[f0 + blockIdx.y];
   const int W = f.W, H = f.H, C = f.C, r = f.r;
   const bool unsorted = (*f.state & kUnsorted) != 0;
+  // Left copy groups written: all of them, or, where the tile kernel reads
+  // the left image in place inside it, only the groups that windows reaching
+  // past an image edge read (padded words below lpad + span, and from
+  // W + lpad - span - 2 on, span being the widest tile of the frame).
+  const int lg = f.lpw >> 2, span = kWave * f.cpl;
+  const int band0 = f.linpl ? min((f.lpad + span) >> 2, lg) : lg;
+  const int band1 = f.linpl ? min(max(band0, (W + f.lpad - span - 2) >> 2), lg) : lg;
+  const int nl = band0 + (lg - band1);
   for (int v = blockIdx.x; v < f.ph; v += gridDim.x) {
     const int y = clampi(v - r, 0, H - 1);
     const uint8_t* lrow = f.left + (int64_t)y * f.pitch;
@@ -151,7 +159,10 @@ __global__ __launch_bounds__(256) void k_prep(const FrameDev* __restrict__ table
     const bool la = ((uintptr_t)lrow & 3) == 0, ra = ((uintptr_t)rrow & 3) == 0;
     g_uint4_rw* lo = (g_uint4_rw*)(f.lp + (int64_t)v * f.lpw);
     g_uint4_rw* ro = (g_uint4_rw*)(f.rp + (int64_t)v * f.rpw);
-    for (int g = threadIdx.x; g < (f.lpw >> 2); g += blockDim.x) lo[g] = pack_group(lrow, 4 * g - f.lpad, W, C, la);
+    for (int g = threadIdx.x; g < nl; g += blockDim.x) {
+      const int gg = g < band0 ? g : g - band0 + band1;
+      lo[gg] = pack_group(lrow, 4 * gg - f.lpad, W, C, la);
+    }
     for (int g = threadIdx.x; g < (f.rpw >> 2); g += blockDim.x) ro[g] = pack_group(rrow, 4 * g - f.rpad, W, C, ra);
     if (unsorted && v >= r && v < r + H) {
       int32_t* mrow = f.map + (int64_t)(v - r) * W;
@@ -316,19 +327,71 @@ struct RowRegs {
   uint32_t R[DC + COLS];
 };
 
+// Where a wave's left pixels come from. Copy: the padded RGBx copy, one
+// 16-byte load per four columns. In place (tiles whose window lies inside the
+// image, C = 3, 4-byte-aligned caller rows): the caller's RGB row, one 16-byte
+// load at 12 bytes per four columns (its last 4 bytes belong to the next
+// group), spread to RGBx words by v_perm_b32 once the load has arrived. The
+// byte selectors are uniform; for the copy they leave the words as they are,
+// so both sources take the same instructions.
+struct LeftSrc {
+  const char* base;   // row q of the source: base + clamp(q - roff, 0, qmax) * pitch
+  int64_t pitch;
+  int roff, qmax;
+  uint32_t lb, gs;    // this lane's first byte in a row; bytes between its groups of four columns
+  uint32_t s0, s1, s2, s3;   // v_perm_b32 selectors of the four words of a group
+  __device__ __forceinline__ const char* row(int q) const {
+    const int v = q - roff;
+    return base + (int64_t)(v < 0 ? 0 : (v > qmax ? qmax : v)) * pitch;
+  }
+};
+
+// A pointer that is the same in every lane, as a scalar value (in the
+// out-of-line item functions the compiler cannot tell by itself).
+__device__ __forceinline__ const char* wave_uniform(const void* p) {
+  const uint64_t v = (uint64_t)p;
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return (const char*)(((uint64_t)hi << 32) | lo);
+}
+
+// lrow, rrow: the wave's row bases (uniform), taken as scalars, so each load
+// is the scalar base plus this lane's 32-bit byte offset (ls.lb on the left;
+// rb = 4 * COLS * lane on the right) with no per-lane address arithmetic.
 template <int DC, int COLS>
-__device__ __forceinline__ void load_row(const uint32_t* lrow, const uint32_t* rrow, uint32_t lo,
+__device__ __forceinline__ void load_row(const char* lrow_, const LeftSrc& ls, const uint32_t* rrow, uint32_t rb,
                                          RowRegs<DC, COLS>& o) {
-  // lrow, rrow: the wave's row bases (uniform); lo: this lane's word offset
+  const char* lrow = wave_uniform(lrow_);
+  const char* rr = wave_uniform(rrow);
+  // the offsets as opaque 32-bit values here, so each load is formed as
+  // (scalar base, 32-bit lane offset) rather than from a 64-bit lane address
+  uint32_t lb = ls.lb;
+  asm volatile("" : "+v"(lb));
+  asm volatile("" : "+v"(rb));
 #pragma unroll
   for (int b = 0; b < COLS / 4; ++b) {
-    const u32x4 lv = *(g_uint4*)(lrow + lo + 4 * b);
+    const u32x4 lv = *(g_uint4*)(lrow + (lb + (uint32_t)b * ls.gs));
     o.L[4 * b] = lv.x; o.L[4 * b + 1] = lv.y; o.L[4 * b + 2] = lv.z; o.L[4 * b + 3] = lv.w;
   }
 #pragma unroll
   for (int b = 0; b < (DC + COLS) / 4; ++b) {
-    const u32x4 t = *(g_uint4*)(rrow + lo + 4 * b);
+    const u32x4 t = *(g_uint4*)(rr + rb + 16 * b);
     o.R[4 * b] = t.x; o.R[4 * b + 1] = t.y; o.R[4 * b + 2] = t.z; o.R[4 * b + 3] = t.w;
+  }
+}
+
+// Left words of a loaded row to RGBx: word k of a group takes bytes of words
+// k and k - 1 (word 0 only its own), highest word first, so each reads words
+// not yet rewritten.
+template <int DC, int COLS>
+__device__ __forceinline__ void left_words(RowRegs<DC, COLS>& o, const LeftSrc& ls) {
+#pragma unroll
+  for (int b = 0; b < COLS / 4; ++b) {
+    uint32_t* w = o.L + 4 * b;
+    w[3] = __builtin_amdgcn_perm(w[3], w[2], ls.s3);
+    w[2] = __builtin_amdgcn_perm(w[2], w[1], ls.s2);
+    w[1] = __builtin_amdgcn_perm(w[1], w[0], ls.s1);
+    w[0] = __builtin_amdgcn_perm(w[0], w[0], ls.s0);
   }
 }
 
@@ -381,8 +444,9 @@ struct Acc {
 
 // Adds one padded row to the accumulators.
 template <int DC, bool kPack, int COLS>
-__device__ __forceinline__ void add_row(RowRegs<DC, COLS>& a, Acc<DC, kPack, COLS>& acc) {
+__device__ __forceinline__ void add_row(RowRegs<DC, COLS>& a, Acc<DC, kPack, COLS>& acc, const LeftSrc& ls) {
   keep_word0(a);
+  left_words(a, ls);
 #pragma unroll
   for (int c = 0; c < COLS; ++c)
 #pragma unroll
@@ -398,9 +462,12 @@ __device__ __forceinline__ void add_row(RowRegs<DC, COLS>& a, Acc<DC, kPack, COL
 // Moves the window down one row: padded row `ex` leaves, `en` enters. The
 // leaving row is taken off first, so no partial sum exceeds a full window.
 template <int DC, bool kPack, int COLS>
-__device__ __forceinline__ void slide_row(RowRegs<DC, COLS>& en, RowRegs<DC, COLS>& ex, Acc<DC, kPack, COLS>& acc) {
+__device__ __forceinline__ void slide_row(RowRegs<DC, COLS>& en, RowRegs<DC, COLS>& ex, Acc<DC, kPack, COLS>& acc,
+                                          const LeftSrc& ls) {
   keep_word0(en);
   keep_word0(ex);
+  left_words(ex, ls);
+  left_words(en, ls);
 #pragma unroll
   for (int c = 0; c < COLS; ++c)
 #pragma unroll
@@ -521,13 +588,30 @@ __device__ __forceinline__ void tile_item_impl(const FrameDev& f, int tile, int 
     return -1;
   };
 
-  // Row bases into the padded copies (the same for the whole wave): padded
-  // row q of the pass starts at lp0 + q * lpw and rp0 + q * rpw (window
-  // column j is image column x0 - lpad + j); lane l reads from word lo = COLS * l on.
-  const uint32_t* lp0 = f.lp + x0;
+  // Row bases (the same for the whole wave): padded row q of the pass (image
+  // row q - r, clamped) starts at rp0 + q * rpw in the right copy, and at
+  // ls.row(q) on the left (window column j is image column x0 - lpad + j);
+  // lane l's right words start at byte lo = 4 * COLS * l. The left source is the
+  // caller's image where the window lies inside it (with 2 columns to spare
+  // for the last lane's 16-byte load), else the padded copy, which the
+  // preparation writes for those windows.
   const uint32_t* rp0 = f.rp + x0 - lpad - d0 - DC + f.rpad;
-  const uint32_t lo = COLS * (uint32_t)lane;
-  const int64_t lpw = f.lpw, rpw = f.rpw;
+  const uint32_t lo = 4u * COLS * (uint32_t)lane;   // byte offset of this lane's right words
+  const int64_t rpw = f.rpw;
+  LeftSrc ls;
+  {
+    const bool inpl = f.linpl && x0 >= lpad && x0 - lpad + Geom<COLS>::kSpanC + 2 <= W;
+    ls.base = inpl ? (const char*)f.left + (int64_t)(x0 - lpad) * 3 : (const char*)(f.lp + x0);
+    ls.pitch = inpl ? f.pitch : (int64_t)f.lpw * 4;
+    ls.roff = inpl ? r : 0;
+    ls.qmax = inpl ? H - 1 : f.ph;
+    ls.gs = inpl ? 12u : 16u;
+    ls.lb = ls.gs * (COLS / 4) * (uint32_t)lane;
+    ls.s0 = inpl ? 0x0c020100u : 0x03020100u;
+    ls.s1 = inpl ? 0x0c050403u : 0x07060504u;
+    ls.s2 = inpl ? 0x0c040302u : 0x07060504u;
+    ls.s3 = inpl ? 0x0c030201u : 0x07060504u;
+  }
 
   // Disparities beyond dmax (last chunk only) never win: their keys are forced to ~0.
   uint32_t kill[DC];
@@ -581,14 +665,14 @@ __device__ __forceinline__ void tile_item_impl(const FrameDev& f, int tile, int 
   {
     const int last = ya + 2 * r;
     RowRegs<DC, COLS> A, B;
-    load_row<DC, COLS>(lp0 + ya * lpw, rp0 + ya * rpw, lo, A);
+    load_row<DC, COLS>(ls.row(ya), ls, rp0 + ya * rpw, lo, A);
     for (int q = ya; q < last; q += 2) {
-      load_row<DC, COLS>(lp0 + (q + 1) * lpw, rp0 + (q + 1) * rpw, lo, B);
-      add_row<DC, kPack, COLS>(A, acc);
-      load_row<DC, COLS>(lp0 + (q + 2) * lpw, rp0 + (q + 2) * rpw, lo, A);
-      add_row<DC, kPack, COLS>(B, acc);
+      load_row<DC, COLS>(ls.row(q + 1), ls, rp0 + (q + 1) * rpw, lo, B);
+      add_row<DC, kPack, COLS>(A, acc, ls);
+      load_row<DC, COLS>(ls.row(q + 2), ls, rp0 + (q + 2) * rpw, lo, A);
+      add_row<DC, kPack, COLS>(B, acc, ls);
     }
-    add_row<DC, kPack, COLS>(A, acc);
+    add_row<DC, kPack, COLS>(A, acc, ls);
   }
 
   // Row step y (y > ya first moves the window down from y - 1):
@@ -722,15 +806,14 @@ __device__ __forceinline__ void tile_item_impl(const FrameDev& f, int tile, int 
 
   // Walk down the rows. The loads for the step y -> y + 1 (padded row
   // y + 2r + 1 enters the window, padded row y leaves it) are issued one step
-  // ahead; the copies hold one spare padded row so the last, unused prefetch
-  // stays in bounds.
-  const uint32_t* lin = lp0 + (int64_t)(ya + 2 * r + 1) * lpw;
-  const uint32_t* rin = rp0 + (int64_t)(ya + 2 * r + 1) * rpw;
-  const uint32_t* lout = lp0 + (int64_t)ya * lpw;
-  const uint32_t* rout = rp0 + (int64_t)ya * rpw;
+  // ahead; the copies hold one spare padded row (and the image rows are
+  // clamped) so the last, unused prefetch stays in bounds.
+  int qin = ya + 2 * r + 1, qout = ya;
+  const uint32_t* rin = rp0 + (int64_t)qin * rpw;
+  const uint32_t* rout = rp0 + (int64_t)qout * rpw;
   RowRegs<DC, COLS> En, Ex;
-  load_row<DC, COLS>(lin, rin, lo, En);
-  load_row<DC, COLS>(lout, rout, lo, Ex);
+  load_row<DC, COLS>(ls.row(qin), ls, rin, lo, En);
+  load_row<DC, COLS>(ls.row(qout), ls, rout, lo, Ex);
   // Row ya (active by construction), then the steps y = ya + 1 .. yb. A
   // step takes its row's listed pixels (loaded a full step earlier) before it
   // issues the next step's loads, so the only waits are the slide's and a
@@ -743,13 +826,13 @@ __device__ __forceinline__ void tile_item_impl(const FrameDev& f, int tile, int 
   for (int y = ya + 1; y <= yb; ++y) {
     const bool act = y == ynext;
     pin_step(acc.v);
-    slide_row<DC, kPack, COLS>(En, Ex, acc);
+    slide_row<DC, kPack, COLS>(En, Ex, acc, ls);
     pin_step(acc.v);
     flush();
     if (act) take_row(y);
-    lin += lpw; rin += rpw; lout += lpw; rout += rpw;
-    load_row<DC, COLS>(lin, rin, lo, En);
-    load_row<DC, COLS>(lout, rout, lo, Ex);
+    ++qin; ++qout; rin += rpw; rout += rpw;
+    load_row<DC, COLS>(ls.row(qin), ls, rin, lo, En);
+    load_row<DC, COLS>(ls.row(qout), ls, rout, lo, Ex);
     if (act) {
       ynext = next_active(y);
       load_next(ynext);

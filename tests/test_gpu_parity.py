@@ -451,6 +451,52 @@ def test_unaligned_caller_arrays(torch, sbs):
                 assert c2 is None and np.array_equal(d2.cpu().numpy(), exp[0]), what + " without costs"
 
 
+def _image_at(torch, img, pitch, offset):
+    """img (H, W, 3) on the device with rows `pitch` bytes apart, starting
+    `offset` bytes into its allocation."""
+    H, W, C = img.shape
+    flat = np.zeros(offset + pitch * (H - 1) + W * C, np.uint8)
+    for y in range(H):
+        flat[offset + y * pitch: offset + y * pitch + W * C] = img[y].reshape(-1)
+    return torch.from_numpy(flat).cuda().as_strided((H, W, C), (pitch, C, 1), offset)
+
+
+def test_left_image_read_in_place(torch, sbs):
+    """Tiles whose window lies inside the image read the caller's left RGB
+    rows in place (4-byte-aligned base and pitch); the other tiles, and every
+    tile of an image at an unaligned address or with a pitch that is not a
+    multiple of 4, read the padded copy. The widths put a tile's window
+    exactly at the last column that allows the in-place 16-byte loads (494
+    for 4 columns per lane, 1006 for 8; block 9) and one column short of it;
+    rows are pitched beyond W * 3 or packed; the first and last rows and
+    columns are listed; ordered and unordered lists."""
+    rng = np.random.default_rng(47)
+    try:
+        for (W, H, dmax, plan) in [(494, 23, 40, (4, 16)), (493, 23, 40, (4, 16)), (700, 19, 70, (4, 16)),
+                                   (1006, 17, 20, (8, 8)), (1005, 17, 20, (8, 8))]:
+            sbs.set_plan(cols_per_lane=plan[0], chunk=plan[1], tile_rows=8)
+            L = rng.integers(0, 256, (H, W, 3), dtype=np.uint8)
+            R = np.roll(L, 6, axis=1)
+            R[::4] = rng.integers(0, 256, R[::4].shape, dtype=np.uint8)
+            edge = np.concatenate([np.arange(2 * W), np.arange((H - 2) * W, H * W),
+                                   np.arange(H) * W, np.arange(H) * W + W - 1])
+            idx = np.unique(np.concatenate([rng.choice(H * W, H * W // 5, replace=False), edge])).astype(np.uint32)
+            exp = oracle.sad(L, R, idx, 9, dmax)
+            for order in ("sorted", "shuffled"):
+                perm = np.arange(idx.size) if order == "sorted" else rng.permutation(idx.size)
+                Id = dev(torch, idx[perm].view(np.int32))
+                for (pitch, off) in ((3 * W, 0), (3 * W + 36, 0), (3 * W + 36, 1), (3 * W + 37, 0)):
+                    Ld = _image_at(torch, L, pitch, off)
+                    Rd = _image_at(torch, R, pitch, off)
+                    d, c = sbs.sad_disparity(Ld, Rd, Id, 9, dmax)
+                    torch.cuda.synchronize()
+                    got = (d.cpu().numpy(), c.cpu().numpy().view(np.uint32))
+                    assert_parity(got, (exp[0][perm], exp[1][perm]),
+                                  f"W {W} plan {plan} {order} pitch {pitch} offset {off}")
+    finally:
+        sbs.set_plan()
+
+
 def test_benchmark_configuration_sampled(torch, sbs):
     """Full-size frames of the benchmark's video (4096x2304 RGB, block 31,
     dmax 127, per-frame boundary fractions) through the batched persistent
