@@ -235,7 +235,7 @@ FrameLayout frame_layout(const sbs_frame& f, size_t base, int span) {
   L.txo = (span - L.lpad - r) & ~3;
   L.ntx = (f.W + L.txo - 1) / L.txo;
   L.tpw = L.ntx + 1;
-  L.state_off = o; o = align_up(o + 4, 256);
+  L.state_off = o; o = align_up(o + 16, 256);
   L.tptr_off = o; o = align_up(o + (size_t)f.H * L.tpw * 4, 256);
   L.end = o;
   return L;

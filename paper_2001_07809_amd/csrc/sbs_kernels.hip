@@ -9,9 +9,12 @@
 // Tiled path (per frame; every kernel also runs over a whole batch of frames):
 //   k_check     clears the result keys, answers indices >= W*H, and finds out
 //               whether the list is in non-decreasing raster order.
-//   k_prep      replicate-padded RGBx copies of both images (one u32 per pixel,
-//               so one v_sad_u8 covers all channels of a pixel). For an
-//               unordered list it also clears the pixel->slot map and row bits.
+//   k_prep      replicate-padded RGBx copy of the right image (one u32 per
+//               pixel, so one v_sad_u8 covers all channels of a pixel), and of
+//               the left image: whole, or only the edge bands that tiles
+//               reaching past an image edge read (RGB images in 4-byte-aligned
+//               rows, which the other tiles read in place). For an unordered
+//               list it also clears the pixel->slot map and row bits.
 //   k_scatter   unordered lists: map[p] = largest slot k with idx[k] == p, and
 //               per row one bit per 64-column group that holds a listed pixel.
 //   k_tptr      ordered lists: for each row and tile column, the first list
@@ -61,12 +64,13 @@ typedef __attribute__((address_space(1))) u32x4 g_uint4_rw;
 // ---------------------------------------------------------------------------
 // Descriptor upload: the descriptors travel inside the kernel argument, so a
 // captured graph replays them without touching host memory. Each frame's
-// state word is cleared here, before any kernel reads it.
+// state words are reset here, before any kernel reads them.
 __global__ void k_put_desc(FrameDev* table, DescBatch b) {
   int i = threadIdx.x;
   if (i < b.count) {
     table[b.first + i] = b.f[i];
     *b.f[i].state = 0u;
+    *(uint64_t*)(b.f[i].state + 2) = (uint64_t)b.f[i].n;
   }
 }
 
@@ -74,7 +78,8 @@ __global__ void k_reset_head(WsHeader* h) {
   if (threadIdx.x < kQueues) h->q[threadIdx.x].head = 0ull;
 }
 
-// Keys cleared, out-of-range entries answered, order checked.
+// Keys cleared, out-of-range entries answered (and the first such slot
+// recorded), order checked.
 // Four list entries per thread and step: 16-byte loads and stores where the
 // caller's arrays allow them (idx 16-byte aligned; keys live in the
 // workspace), entry by entry otherwise.
@@ -105,6 +110,7 @@ __global__ __launch_bounds__(256) void k_check(const FrameDev* __restrict__ tabl
         f.out_disp[k + j] = 255;
         if (f.out_cost) f.out_cost[k + j] = 0xFFFFFFFFu;
         atomicOr(&hdr->error, 1u);
+        atomicMin((unsigned long long*)(f.state + 2), (unsigned long long)(k + j));
       }
     }
   }
@@ -964,38 +970,46 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kWide ? 3 : 
   }
 }
 
-// Keys split into (disparity, cost), four entries per thread and step: one
-// 4-byte store of disparities and one 16-byte store of costs where the
-// caller's arrays allow them (out_disp 4-byte, out_cost and idx 16-byte
-// aligned). Entries out of range already hold 255 / ~0 from k_check; the
-// vector path writes those same values again.
+// Keys split into (disparity, cost), four entries per thread and step. An
+// ordered list holds its indices >= W*H in a tail from the first such slot on
+// (k_check recorded it and answered those entries): the entries before it
+// take key k, and the list itself is not read again. An unordered list
+// reads each index for its representative slot. One 4-byte store of
+// disparities and one 16-byte store of costs where the caller's arrays allow
+// them (out_disp 4-byte, out_cost 16-byte aligned; for unordered lists also
+// idx 16-byte aligned).
 __global__ __launch_bounds__(256) void k_finalize(const FrameDev* __restrict__ table, int f0) {
   const FrameDev& f = table[f0 + blockIdx.y];
-  const int64_t N = (int64_t)f.W * f.H, n = f.n;
+  const int64_t N = (int64_t)f.W * f.H;
   const bool unsorted = (*f.state & kUnsorted) != 0;
+  const int64_t n = unsorted ? f.n : min(f.n, (int64_t)*(const uint64_t*)(f.state + 2));
   const uint32_t* idx = f.idx;
   const uint32_t* keys = f.keys;
   uint8_t* od = f.out_disp;
   uint32_t* oc = f.out_cost;
-  const bool vec = ((uintptr_t)idx & 15u) == 0 && ((uintptr_t)od & 3u) == 0 && ((uintptr_t)oc & 15u) == 0;
+  const bool vec = ((uintptr_t)od & 3u) == 0 && ((uintptr_t)oc & 15u) == 0 &&
+                   (!unsorted || ((uintptr_t)idx & 15u) == 0);
   for (int64_t k = 4 * ((int64_t)blockIdx.x * blockDim.x + threadIdx.x); k < n; k += 4 * (int64_t)gridDim.x * blockDim.x) {
     if (vec && k + 3 < n) {
-      const u32x4 v = *(g_uint4*)(idx + k);
-      const uint32_t p[4] = {v.x, v.y, v.z, v.w};
       uint32_t key[4];
+      bool out[4] = {false, false, false, false};
       if (!unsorted) {
         const u32x4 kv = *(g_uint4*)(keys + k);
         key[0] = kv.x; key[1] = kv.y; key[2] = kv.z; key[3] = kv.w;
       } else {
+        const u32x4 v = *(g_uint4*)(idx + k);
+        const uint32_t p[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
-        for (int j = 0; j < 4; ++j) key[j] = (int64_t)p[j] < N ? keys[f.map[p[j]]] : 0u;
+        for (int j = 0; j < 4; ++j) {
+          out[j] = (int64_t)p[j] >= N;   // (255, ~0) as k_check wrote them
+          key[j] = out[j] ? 0u : keys[f.map[p[j]]];
+        }
       }
       uint32_t cost[4];
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const bool out = (int64_t)p[j] >= N;   // (255, ~0) as k_check wrote them
-        cost[j] = out ? 0xFFFFFFFFu : key[j] >> 8;
-        key[j] = out ? 0xFFu : key[j] & 0xFFu;
+        cost[j] = out[j] ? 0xFFFFFFFFu : key[j] >> 8;
+        key[j] = out[j] ? 0xFFu : key[j] & 0xFFu;
       }
       *(__attribute__((address_space(1))) uint32_t*)(od + k) = key[0] | (key[1] << 8) | (key[2] << 16) | (key[3] << 24);
       if (oc) *(g_uint4_rw*)(oc + k) = u32x4{cost[0], cost[1], cost[2], cost[3]};
@@ -1004,9 +1018,13 @@ __global__ __launch_bounds__(256) void k_finalize(const FrameDev* __restrict__ t
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       if (k + j >= n) break;
-      const uint32_t p = idx[k + j];
-      if ((int64_t)p >= N) continue;
-      const uint32_t key = keys[unsorted ? (int64_t)f.map[p] : k + j];
+      int64_t slot = k + j;
+      if (unsorted) {
+        const uint32_t p = idx[k + j];
+        if ((int64_t)p >= N) continue;
+        slot = f.map[p];
+      }
+      const uint32_t key = keys[slot];
       od[k + j] = (uint8_t)(key & 0xFFu);
       if (oc) oc[k + j] = key >> 8;
     }

@@ -422,21 +422,27 @@ def test_unaligned_caller_arrays(torch, sbs):
     """List and outputs at offsets that rule out the 16- and 4-byte vector
     paths of the list check and the finalize step (and at aligned offsets),
     lengths with a ragged tail of 1..3 entries, out-of-range indices inside
-    and at the ends, ordered and unordered lists, with and without costs."""
+    and at the ends, ordered lists whose out-of-range indices form their
+    tail (the finalize step stops at the first of them), unordered lists,
+    with and without costs."""
     rng = np.random.default_rng(43)
     H, W = 70, 150
     L = rng.integers(0, 256, (H, W, 3), dtype=np.uint8)
     R = np.roll(L, 4, axis=1)
     Ld, Rd = dev(torch, L), dev(torch, R)
-    for order in ("sorted", "shuffled"):
+    for order in ("sorted", "shuffled", "ordered tail"):
         for n in (1, 2, 3, 4, 5, 999, 1002, 1003):
             idx = np.sort(rng.choice(H * W, n, replace=False)).astype(np.uint32)
-            if order == "shuffled":
-                idx = rng.permutation(idx)
-            idx[rng.integers(0, n)] = H * W + 7          # out of range
-            if n > 2:
-                idx[0] = H * W
-                idx[-1] = 0xFFFFFFF0
+            if order == "ordered tail":   # still in raster order: indices >= W*H only at the end
+                tail = np.array([H * W, H * W, H * W + 7, 0xFFFFFFF0], np.uint32)[: min(n, 1 + n % 4)]
+                idx[n - tail.size:] = tail
+            else:
+                if order == "shuffled":
+                    idx = rng.permutation(idx)
+                idx[rng.integers(0, n)] = H * W + 7          # out of range
+                if n > 2:
+                    idx[0] = H * W
+                    idx[-1] = 0xFFFFFFF0
             exp = oracle.sad(L, R, idx, 9, 20)
             for off_i, off_d, off_c in ((0, 0, 0), (1, 1, 1), (2, 3, 3), (3, 4, 2)):
                 ib = dev(torch, np.concatenate([np.zeros(off_i, np.uint32), idx]).view(np.int32))[off_i:]
