@@ -13,6 +13,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <string>
+#include <utility>
 
 #include "../../include/sbs.h"
 #include "sbs_internal.h"
@@ -210,6 +211,77 @@ __global__ __launch_bounds__(256) void k_blur_v(const uint8_t* img, const uint8_
   }
 }
 
+// The same blur in one pass per tile of kBlurTX x ty pixels (ty = 32, or 16
+// when that gives too few tiles to fill the chip; radius up to kBlurTileRad,
+// a compile-time constant per instance so the tap loops unroll): the tile's
+// clamped input rows and columns go to LDS, the horizontal pass runs over the
+// tile's rows plus the vertical halo into LDS, and the vertical pass reads it
+// from there. Each sum runs over the taps in the same order as in the two
+// kernels above, so the results are the same floats; only the intermediate
+// image no longer travels through HBM.
+constexpr int kBlurTX = 64, kBlurTileRad = 14;   // LDS <= 64 KB per block at 32 rows
+
+template <int C, int RAD>
+__global__ __launch_bounds__(256) void k_blur_tile(const uint8_t* img, const uint8_t* depth, int32_t W, int32_t H,
+                                                   int64_t pitch, int32_t ty, BlurArgs a, float* out) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char blur_lds[];
+  constexpr int cols = kBlurTX + 2 * RAD, rowb = cols * C;   // input tile: image columns x0 - RAD ..
+  const int x0 = blockIdx.x * kBlurTX, y0 = blockIdx.y * ty;
+  const int rows = ty + 2 * RAD;                               // image rows y0 - RAD ..
+  float* hb = (float*)blur_lds;                                // rows x kBlurTX x C horizontal sums
+  uint8_t* ib = blur_lds + (size_t)rows * kBlurTX * C * 4;     // rows x cols x C input bytes
+#pragma unroll 8
+  for (int b = threadIdx.x; b < rows * rowb; b += 256) {
+    const int r = b / rowb, jc = b - r * rowb, j = jc / C;
+    const int yy = min(max(y0 - RAD + r, 0), H - 1), xx = min(max(x0 - RAD + j, 0), W - 1);
+    ib[b] = img[(int64_t)yy * pitch + (int64_t)xx * C + (jc - j * C)];
+  }
+  __syncthreads();
+#pragma unroll 2
+  for (int i = threadIdx.x; i < rows * kBlurTX * C; i += 256) {
+    const int r = i / (kBlurTX * C), xc = i - r * (kBlurTX * C);
+    const uint8_t* src = ib + r * rowb + xc;   // tap k at src[(k + RAD) * C]
+    float s = 0.f;
+#pragma unroll
+    for (int k = -RAD; k <= RAD; ++k) s += a.g[k + RAD] * (float)src[(k + RAD) * C];
+    hb[i] = s;
+  }
+  __syncthreads();
+#pragma unroll 2
+  for (int i = threadIdx.x; i < ty * kBlurTX * C; i += 256) {
+    const int y = i / (kBlurTX * C), xc = i - y * (kBlurTX * C);
+    const int x = xc / C;
+    if (y0 + y >= H || x0 + x >= W) continue;
+    const int64_t px = (int64_t)(y0 + y) * W + x0 + x;
+    const int dv = depth[px];
+    bool keep = false;
+    for (int t = 0; t < a.nranges; ++t) keep |= (dv >= a.lo[t] && dv <= a.hi[t]);
+    float v;
+    if (keep) {
+      v = (float)ib[(y + RAD) * rowb + (x + RAD) * C + (xc - x * C)];
+    } else {
+      const float* col = hb + xc;   // row y + RAD + k at col[(y + RAD + k) * kBlurTX * C]
+      v = 0.f;
+#pragma unroll
+      for (int k = -RAD; k <= RAD; ++k) v += a.g[k + RAD] * col[(y + RAD + k) * kBlurTX * C];
+    }
+    out[px * C + (xc - x * C)] = v;
+  }
+}
+
+template <int C, int RAD>
+void launch_blur_tile(dim3 grid, size_t lds, hipStream_t s, const uint8_t* img, const uint8_t* depth, int32_t W,
+                      int32_t H, int64_t pitch, int32_t ty, const BlurArgs& a, float* out) {
+  hipLaunchKernelGGL((k_blur_tile<C, RAD>), grid, dim3(256), lds, s, img, depth, W, H, pitch, ty, a, out);
+}
+
+template <int C, int... R>
+void blur_tile_dispatch(int rad, std::integer_sequence<int, R...>, dim3 grid, size_t lds, hipStream_t s,
+                        const uint8_t* img, const uint8_t* depth, int32_t W, int32_t H, int64_t pitch, int32_t ty,
+                        const BlurArgs& a, float* out) {
+  ((rad == R + 1 ? launch_blur_tile<C, R + 1>(grid, lds, s, img, depth, W, H, pitch, ty, a, out) : void()), ...);
+}
+
 int fail(int st, const char* fmt, ...) {
   char buf[256];
   va_list ap;
@@ -289,9 +361,20 @@ int sbs_selective_blur(const uint8_t* img, int32_t W, int32_t H, int32_t C, int6
   a.nranges = nranges;
   for (int t = 0; t < nranges; ++t) { a.lo[t] = ranges[2 * t]; a.hi[t] = ranges[2 * t + 1]; }
   hipStream_t s = (hipStream_t)stream;
-  float* tmp = (float*)workspace;
-  hipLaunchKernelGGL(k_blur_h, dim3(2048), dim3(256), 0, s, img, W, H, C, pitch, a, tmp);
-  hipLaunchKernelGGL(k_blur_v, dim3(2048), dim3(256), 0, s, img, depth, W, H, C, pitch, a, tmp, out);
+  if (rad <= kBlurTileRad) {
+    const int64_t tx = (W + kBlurTX - 1) / kBlurTX;
+    const int ty = tx * ((H + 31) / 32) >= 1024 ? 32 : 16;
+    const int rows = ty + 2 * rad, cols = kBlurTX + 2 * rad;
+    const size_t lds = (size_t)rows * kBlurTX * C * 4 + (size_t)rows * cols * C;
+    const dim3 grid((unsigned)tx, (unsigned)((H + ty - 1) / ty));
+    const auto radii = std::make_integer_sequence<int, kBlurTileRad>{};
+    if (C == 3) blur_tile_dispatch<3>(rad, radii, grid, lds, s, img, depth, W, H, pitch, ty, a, out);
+    else blur_tile_dispatch<1>(rad, radii, grid, lds, s, img, depth, W, H, pitch, ty, a, out);
+  } else {
+    float* tmp = (float*)workspace;
+    hipLaunchKernelGGL(k_blur_h, dim3(2048), dim3(256), 0, s, img, W, H, C, pitch, a, tmp);
+    hipLaunchKernelGGL(k_blur_v, dim3(2048), dim3(256), 0, s, img, depth, W, H, C, pitch, a, tmp, out);
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(SBS_ERR_HIP, "blur: %s", hipGetErrorString(e));
   return SBS_OK;

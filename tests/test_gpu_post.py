@@ -60,7 +60,7 @@ def test_reconstruct_sparse_columns_across_segments(mods):
             np.testing.assert_array_equal(got.cpu().numpy(), exp, err_msg=f"{W}x{H} n {n} t {threshold}")
 
 
-@pytest.mark.parametrize("C,sigma", [(1, 0.8), (3, 1.5), (3, 4.0)])
+@pytest.mark.parametrize("C,sigma", [(1, 0.8), (3, 1.5), (3, 4.0), (3, 4.6), (1, 5.0), (3, 5.0)])
 def test_blur_matches_oracle(mods, C, sigma):
     torch, sbs = mods
     rng = np.random.default_rng(7)
@@ -72,3 +72,23 @@ def test_blur_matches_oracle(mods, C, sigma):
     got = sbs.selective_blur(torch.from_numpy(img).cuda(), torch.from_numpy(depth).cuda(), ranges, sigma)
     torch.cuda.synchronize()
     np.testing.assert_allclose(got.cpu().numpy(), exp, atol=1e-3, rtol=0)
+
+@pytest.mark.parametrize("sigma", [2.0, 4.6])
+def test_blur_pitched_rows_over_many_tiles(mods, sigma):
+    """An RGB image inside wider rows (pitch > W * 3), several 64 x 32 tiles
+    with partial ones at the right and bottom, the largest radius the tiled
+    kernel takes (14 at sigma 4.6) and a common one (6 at sigma 2)."""
+    torch, sbs = mods
+    rng = np.random.default_rng(11)
+    H, W = 150, 300
+    wide = rng.integers(0, 256, (H, 320, 3), dtype=np.uint8)
+    img = np.ascontiguousarray(wide[:, :W])
+    depth = rng.integers(0, 60, (H, W), dtype=np.uint8)
+    ranges = [(0, 20)]
+    exp = oracle.blur(img, depth, ranges, sigma)
+    dev = torch.from_numpy(wide).cuda()[:, :W]
+    assert dev.stride(0) == 960
+    got = sbs.selective_blur(dev, torch.from_numpy(depth).cuda(), ranges, sigma)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(got.cpu().numpy(), exp, atol=1e-3, rtol=0)
+
