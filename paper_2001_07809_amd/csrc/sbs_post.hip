@@ -35,59 +35,68 @@ __global__ __launch_bounds__(256) void k_rc_scatter(const uint32_t* idx, int64_t
   }
 }
 
-// Algorithm 1 on one row per block: a pixel strictly between two consecutive
-// listed pixels of the row that carry the same disparity takes it. Each
-// thread owns a contiguous segment; the nearest listed pixel to the left and
-// to the right of every pixel come from block-wide max/min scans over the
-// segments. Output: f[p] = disparity or -1 (undetermined).
+// Algorithm 1, one block of four wavefronts per row: a pixel strictly
+// between two consecutive listed pixels of the row that carry the same
+// disparity takes it. Each wavefront owns a quarter of the row's 64-pixel
+// chunks and walks them one pixel per lane (coalesced): a ballot marks a
+// chunk's listed pixels, the nearest one at or left of each lane comes from
+// the mask's bits up to the lane (its value by a lane shuffle), and the last
+// listed value of the chunks before is carried as a wave-uniform value. A
+// left-to-right pass writes, per pixel, the value of the nearest listed pixel
+// on its left within the quarter (-2: none there yet) and records the
+// quarter's first and last listed values; after an exchange through LDS a
+// right-to-left pass finds the nearest listed pixel on the right the same
+// way, takes the one on the left from the quarters before where it was
+// missing, and decides. Output: f[p] = disparity or -1 (undetermined).
 __global__ __launch_bounds__(kRowThreads) void k_rc_fill(const int32_t* slot, const uint8_t* disp, int32_t W,
                                                            int32_t H, int16_t* f) {
-  __shared__ int32_t lastpos[kRowThreads];
-  __shared__ int32_t firstpos[kRowThreads];
-  const int t = threadIdx.x;
-  const int seg = (W + kRowThreads - 1) / kRowThreads;
+  constexpr int kWaves = kRowThreads / 64;
+  __shared__ int q_first[kWaves], q_last[kWaves];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int nch = (W + 63) >> 6, per = (nch + kWaves - 1) / kWaves;
+  const int c0 = min(wv * per, nch), c1 = min(c0 + per, nch);
+  const uint64_t upto = (2ull << lane) - 1ull;    // bits 0 .. lane
+  const uint64_t from = ~((1ull << lane) - 1ull); // bits lane .. 63
   for (int y = blockIdx.x; y < H; y += gridDim.x) {
     const int32_t* srow = slot + (int64_t)y * W;
     int16_t* frow = f + (int64_t)y * W;
-    const int xa = min(t * seg, W), xb = min(xa + seg, W);
-    int last = -1, first = W;
-    for (int x = xa; x < xb; ++x)
-      if (srow[x] >= 0) { last = x; if (first == W) first = x; }
-    lastpos[t] = last;
-    firstpos[t] = first;
-    __syncthreads();
-    // inclusive max-scan of lastpos (left to right), inclusive min-scan of firstpos (right to left)
-    for (int off = 1; off < kRowThreads; off <<= 1) {
-      const int a = t >= off ? lastpos[t - off] : -1;
-      const int b = t + off < kRowThreads ? firstpos[t + off] : W;
-      __syncthreads();
-      lastpos[t] = max(lastpos[t], a);
-      firstpos[t] = min(firstpos[t], b);
-      __syncthreads();
-    }
-    int prev = t > 0 ? lastpos[t - 1] : -1;          // nearest listed pixel left of this segment
-    int next = t + 1 < kRowThreads ? firstpos[t + 1] : W;  // nearest right of this segment
-    // Left to right through the segment carrying the nearest listed pixel on
-    // the left; the nearest on the right is found by a short forward search
-    // inside the segment (segments are W / 256 pixels), else it is `next`.
-    for (int x = xa; x < xb; ++x) {
-      const int32_t k = srow[x];
-      if (k >= 0) {
-        frow[x] = disp[k];
-        prev = x;
-        continue;
+    int carry = -2, first = -1;
+#pragma unroll 4
+    for (int c = c0; c < c1; ++c) {
+      const int x = (c << 6) + lane;
+      const int32_t k = x < W ? srow[x] : -1;
+      const int v = k >= 0 ? (int)disp[k] : -1;
+      const uint64_t m = __builtin_amdgcn_ballot_w64(k >= 0);
+      const uint64_t b = m & upto;
+      const int left = __shfl(v, b ? 63 - __builtin_clzll(b) : 0);
+      if (x < W) frow[x] = (int16_t)(b ? left : carry);
+      if (m) {
+        if (first < 0) first = __shfl(v, __builtin_ctzll(m));
+        carry = __shfl(v, 63 - __builtin_clzll(m));
       }
-      int nx = next;
-      for (int u = x + 1; u < xb; ++u)
-        if (srow[u] >= 0) { nx = u; break; }
-      int16_t v = -1;
-      if (prev >= 0 && nx < W) {
-        const uint8_t dl = disp[srow[prev]], dr = disp[srow[nx]];
-        if (dl == dr) v = dl;
-      }
-      frow[x] = v;
     }
+    if (lane == 0) { q_first[wv] = first; q_last[wv] = carry < 0 ? -1 : carry; }
     __syncthreads();
+    int cl = -1, cr = -1;   // nearest listed value in the quarters to the left / right
+    for (int j = wv - 1; j >= 0 && cl < 0; --j) cl = q_last[j];
+    for (int j = wv + 1; j < kWaves && cr < 0; ++j) cr = q_first[j];
+    __syncthreads();   // the next row rewrites q_first / q_last
+    carry = cr;
+#pragma unroll 4
+    for (int c = c1 - 1; c >= c0; --c) {
+      const int x = (c << 6) + lane;
+      const int32_t k = x < W ? srow[x] : -1;
+      const int v = k >= 0 ? (int)disp[k] : -1;
+      const uint64_t m = __builtin_amdgcn_ballot_w64(k >= 0);
+      const uint64_t b = m & from;
+      const int right = b ? __shfl(v, __builtin_ctzll(b)) : carry;
+      if (x < W) {
+        int left = frow[x];
+        if (left == -2) left = cl;
+        frow[x] = (int16_t)(k >= 0 ? v : ((left >= 0 && left == right) ? left : -1));
+      }
+      if (m) carry = __shfl(v, __builtin_ctzll(m));
+    }
   }
 }
 
@@ -320,7 +329,7 @@ int sbs_reconstruct(const uint32_t* idx, const uint8_t* disp, int64_t n, int32_t
   int16_t* up = (int16_t*)(base + align256(N * 4) + align256(N * 2));
   hipLaunchKernelGGL(k_rc_clear, dim3(1024), dim3(256), 0, s, slot, N);
   if (n > 0) hipLaunchKernelGGL(k_rc_scatter, dim3(256), dim3(256), 0, s, idx, n, N, slot);
-  hipLaunchKernelGGL(k_rc_fill, dim3(H < 4096 ? H : 4096), dim3(kRowThreads), 0, s, slot, disp, W, H, f);
+  hipLaunchKernelGGL(k_rc_fill, dim3(H < 65536 ? H : 65536), dim3(kRowThreads), 0, s, slot, disp, W, H, f);
   // The column pass's segment records reuse the slot array (no longer read
   // after k_rc_fill): 2 x nseg x W int16 <= 4 x W x H bytes.
   const int seglen = std::max(kColSeg, (H + 65534) / 65535);

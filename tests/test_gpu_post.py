@@ -33,8 +33,10 @@ def test_reconstruct_matches_oracle(mods, threshold):
 def test_reconstruct_unordered_duplicates_and_edges(mods):
     torch, sbs = mods
     rng = np.random.default_rng(5)
-    for (W, H) in [(1, 1), (1, 30), (45, 1), (300, 77), (4100, 3)]:
-        n = max(1, W * H // 5)
+    # the last two: a handful of listed pixels, so whole quarters of a row
+    # (and whole rows) hold none and the nearest ones lie quarters apart
+    for (W, H, n) in [(1, 1, 1), (1, 30, 6), (45, 1, 9), (300, 77, 4620), (4100, 3, 2460), (700, 9, 7),
+                      (4100, 2, 3)]:
         idx = rng.integers(0, W * H + 3, n).astype(np.uint32)      # includes out-of-range entries
         disp = rng.integers(0, 6, n).astype(np.uint8)              # few values: many equal neighbours
         exp = oracle.reconstruct(idx, disp, W, H, 1)
