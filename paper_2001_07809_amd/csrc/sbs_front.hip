@@ -1007,7 +1007,9 @@ int sbs_boundaries(const uint8_t* img, int32_t W, int32_t H, int32_t C, int64_t 
   c.out = out_idx; c.refined = out_refined; c.count = (long long*)out_count;
   if (mode == 1) {
     hipLaunchKernelGGL(k_fill, dim3(g), dim3(kBlock), 0, s, (uint8_t*)cnt, (int64_t)(N + 1) * 4, (uint8_t)0);
-    hipLaunchKernelGGL(k_drop_count, dim3(g), dim3(kBlock), 0, s, parent, size, N, total, cnt);
+    // at most 512 blocks: each block's closing adds (its total and its small
+    // sizes' counts) go to the same few global words, so fewer blocks wait less
+    hipLaunchKernelGGL(k_drop_count, dim3(std::min(g, 512)), dim3(kBlock), 0, s, parent, size, N, total, cnt);
     hipLaunchKernelGGL(k_drop_find, dim3(1), dim3(1024), 0, s, cnt, total, 0.04, rule);
     c.rule = rule;
     // rank of each root of size s* among those roots, in raster order
