@@ -184,17 +184,14 @@ __global__ __launch_bounds__(kBlock) void k_label(const uint8_t* __restrict__ L8
 }
 
 // ---------------------------------------------------------------------------
-// 3x3 stencils. One thread per pixel of a 2-D grid.
+// 3x3 stencils.
 //   op 0: erosion (min), op 1: dilation (max), replicate border;
 //   op 2: Moore boundary (1 iff an in-image 8-neighbour differs);
 //   op 3: 'fill' (a 0 whose eight neighbours are all 1 becomes 1; outside = 0);
 //   op 4: 'remove' (a 1 whose four 4-neighbours are all 1 becomes 0; outside = 0).
+// One pixel, with every border rule spelled out.
 template <int OP>
-__global__ __launch_bounds__(kBlock) void k_stencil(const uint8_t* __restrict__ in, int32_t W, int32_t H,
-                                                    uint8_t* __restrict__ out) {
-  const int x = blockIdx.x * 64 + (threadIdx.x & 63);
-  const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
-  if (x >= W || y >= H) return;
+__device__ __forceinline__ uint8_t stencil_px(const uint8_t* __restrict__ in, int32_t W, int32_t H, int x, int y) {
   const uint8_t v = in[(int64_t)y * W + x];
   auto at = [&](int yy, int xx) -> int { return in[(int64_t)yy * W + xx]; };
   uint8_t r = v;
@@ -225,7 +222,91 @@ __global__ __launch_bounds__(kBlock) void k_stencil(const uint8_t* __restrict__ 
     auto in_at = [&](int yy, int xx) -> int { return (yy < 0 || yy >= H || xx < 0 || xx >= W) ? 0 : at(yy, xx); };
     if (v && in_at(y - 1, x) && in_at(y + 1, x) && in_at(y, x - 1) && in_at(y, x + 1)) r = 0;
   }
-  out[(int64_t)y * W + x] = r;
+  return r;
+}
+
+// One thread per pixel of a 2-D grid (any width).
+template <int OP>
+__global__ __launch_bounds__(kBlock) void k_stencil(const uint8_t* __restrict__ in, int32_t W, int32_t H,
+                                                    uint8_t* __restrict__ out) {
+  const int x = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
+  if (x >= W || y >= H) return;
+  out[(int64_t)y * W + x] = stencil_px<OP>(in, W, H, x, y);
+}
+
+// Widths that are a multiple of 4: four pixels per thread (256 columns x 4
+// rows per block). Away from the image's edges a thread reads three aligned
+// words per row (the four pixels and one word on each side for the
+// neighbours) and writes one word; threads touching an edge take the
+// per-pixel rules.
+template <int OP>
+__global__ __launch_bounds__(kBlock) void k_stencil4(const uint8_t* __restrict__ in, int32_t W, int32_t H,
+                                                     uint8_t* __restrict__ out) {
+  const int x = (blockIdx.x * 64 + (threadIdx.x & 63)) * 4;
+  const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
+  if (x >= W || y >= H) return;
+  if (x < 4 || x + 8 > W || y < 1 || y + 1 >= H) {
+    uint32_t w = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) w |= (uint32_t)stencil_px<OP>(in, W, H, x + i, y) << (8 * i);
+    *(uint32_t*)(out + (int64_t)y * W + x) = w;
+    return;
+  }
+  // q[j][0 .. 5]: row y - 1 + j, columns x - 1 .. x + 4
+  int q[3][6];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    const uint32_t* row = (const uint32_t*)(in + (int64_t)(y - 1 + j) * W + x);
+    const uint32_t a = row[-1], b = row[0], c = row[1];
+    q[j][0] = (int)(a >> 24);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) q[j][1 + i] = (int)((b >> (8 * i)) & 0xFFu);
+    q[j][5] = (int)(c & 0xFFu);
+  }
+  uint32_t w = 0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int v = q[1][1 + i];
+    int r = v;
+    if constexpr (OP == 0 || OP == 1) {
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) r = OP == 0 ? min(r, q[j][i + k]) : max(r, q[j][i + k]);
+    } else if constexpr (OP == 2) {
+      bool d = false;
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) d |= q[j][i + k] != v;
+      r = d ? 1 : 0;
+    } else if constexpr (OP == 3) {
+      if (!v) {
+        bool all = true;
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+#pragma unroll
+          for (int k = 0; k < 3; ++k)
+            if (j != 1 || k != 1) all = all && q[j][i + k] != 0;
+        r = all ? 1 : 0;
+      }
+    } else {
+      if (v && q[0][1 + i] && q[2][1 + i] && q[1][i] && q[1][i + 2]) r = 0;
+    }
+    w |= (uint32_t)r << (8 * i);
+  }
+  *(uint32_t*)(out + (int64_t)y * W + x) = w;
+}
+
+// Launches op OP over the image: four pixels per thread where rows are
+// 4-byte aligned, one otherwise.
+template <int OP>
+void launch_stencil(const uint8_t* in, int32_t W, int32_t H, uint8_t* out, hipStream_t s) {
+  if ((W & 3) == 0 && ((uintptr_t)in & 3) == 0 && ((uintptr_t)out & 3) == 0)
+    hipLaunchKernelGGL(k_stencil4<OP>, dim3((W / 4 + 63) / 64, (H + 3) / 4), dim3(kBlock), 0, s, in, W, H, out);
+  else
+    hipLaunchKernelGGL(k_stencil<OP>, dim3((W + 63) / 64, (H + 3) / 4), dim3(kBlock), 0, s, in, W, H, out);
 }
 
 // ---------------------------------------------------------------------------
@@ -967,7 +1048,6 @@ int sbs_boundaries(const uint8_t* img, int32_t W, int32_t H, int32_t C, int64_t 
   uint32_t* rhist = (uint32_t*)(base + Lo.rhist);
   static_assert(sizeof(FracState) <= 256, "misc layout");
   const int g = grid_for(N);
-  const dim3 g2((W + 63) / 64, (H + 3) / 4);
 
   // Clear the small counters with kernels (no memset nodes if the caller captures the stream).
   hipLaunchKernelGGL(k_fill, dim3(1), dim3(kBlock), 0, s, (uint8_t*)hist, (int64_t)(256 * 8), (uint8_t)0);
@@ -979,15 +1059,15 @@ int sbs_boundaries(const uint8_t* img, int32_t W, int32_t H, int32_t C, int64_t 
   hipLaunchKernelGGL(k_label, dim3(g), dim3(kBlock), 0, s, L8, N, lut, lab);
   const uint8_t* labels = lab;
   if (mode == 0) {
-    hipLaunchKernelGGL(k_stencil<0>, g2, dim3(kBlock), 0, s, lab, W, H, lab2);   // erode
-    hipLaunchKernelGGL(k_stencil<1>, g2, dim3(kBlock), 0, s, lab2, W, H, lab);   // dilate: open
-    hipLaunchKernelGGL(k_stencil<1>, g2, dim3(kBlock), 0, s, lab, W, H, lab2);   // dilate
-    hipLaunchKernelGGL(k_stencil<0>, g2, dim3(kBlock), 0, s, lab2, W, H, lab);   // erode: close
-    hipLaunchKernelGGL(k_stencil<2>, g2, dim3(kBlock), 0, s, lab, W, H, B);      // boundary
+    launch_stencil<0>(lab, W, H, lab2, s);    // erode
+    launch_stencil<1>(lab2, W, H, lab, s);    // dilate: open
+    launch_stencil<1>(lab, W, H, lab2, s);    // dilate
+    launch_stencil<0>(lab2, W, H, lab, s);    // erode: close
+    launch_stencil<2>(lab, W, H, B, s);       // boundary
   } else {
-    hipLaunchKernelGGL(k_stencil<2>, g2, dim3(kBlock), 0, s, lab, W, H, B2);     // boundary
-    hipLaunchKernelGGL(k_stencil<3>, g2, dim3(kBlock), 0, s, B2, W, H, B);       // fill
-    hipLaunchKernelGGL(k_stencil<4>, g2, dim3(kBlock), 0, s, B, W, H, B2);       // remove
+    launch_stencil<2>(lab, W, H, B2, s);      // boundary
+    launch_stencil<3>(B2, W, H, B, s);        // fill
+    launch_stencil<4>(B, W, H, B2, s);        // remove
     B = B2;
   }
   if (out_labels) {
