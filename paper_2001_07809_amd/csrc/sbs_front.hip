@@ -675,6 +675,37 @@ __device__ __forceinline__ bool flag(const ScanCtx& c, int64_t i) {
   }
 }
 
+// Inclusive scan of one value per lane across the wavefront (shuffles).
+__device__ __forceinline__ uint32_t wave_scan_incl(uint32_t v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t a = (uint32_t)__shfl_up((int)v, off);
+    if (lane >= off) v += a;
+  }
+  return v;
+}
+
+// Exclusive scan of the per-lane values of a block of kWaves wavefronts:
+// wavefront scans, then the wavefront totals through LDS (two barriers).
+template <int kWaves>
+__device__ __forceinline__ uint32_t block_scan_excl(uint32_t v, uint32_t* wtot, uint32_t& total) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const uint32_t incl = wave_scan_incl(v);
+  if (lane == 63) wtot[wv] = incl;
+  __syncthreads();
+  uint32_t before = 0, all = 0;
+#pragma unroll
+  for (int j = 0; j < kWaves; ++j) {
+    const uint32_t t = wtot[j];
+    before += j < wv ? t : 0u;
+    all += t;
+  }
+  __syncthreads();   // wtot may be rewritten after this
+  total = all;
+  return before + incl - v;
+}
+
 template <int KIND>
 __global__ __launch_bounds__(kBlock) void k_scan_count(ScanCtx c, uint32_t* bsum) {
   __shared__ uint32_t s;
@@ -686,40 +717,35 @@ __global__ __launch_bounds__(kBlock) void k_scan_count(ScanCtx c, uint32_t* bsum
     const int64_t i = i0 + j;
     if (i < c.N && flag<KIND>(c, i)) ++m;
   }
-  atomicAdd(&s, m);
+  m = wave_scan_incl(m);   // lane 63: the wavefront's count
+  if ((threadIdx.x & 63) == 63) atomicAdd(&s, m);
   __syncthreads();
   if (threadIdx.x == 0) bsum[blockIdx.x] = s;
 }
 
-// exclusive scan of nb block counts in place (one block of 1024 threads)
+// exclusive scan of nb block counts in place (one block of 1024 threads; each
+// thread sums a contiguous run of counts, the runs are scanned across the
+// block, then each thread writes its run's prefixes)
 __global__ __launch_bounds__(1024) void k_scan_top(uint32_t* bsum, int64_t nb, long long* total) {
-  __shared__ uint32_t sc[1024];
-  __shared__ uint32_t base;
-  if (threadIdx.x == 0) base = 0;
-  __syncthreads();
-  for (int64_t b0 = 0; b0 < nb; b0 += 1024) {
-    const int64_t b = b0 + threadIdx.x;
-    const uint32_t v = b < nb ? bsum[b] : 0u;
-    sc[threadIdx.x] = v;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-      const uint32_t a = threadIdx.x >= off ? sc[threadIdx.x - off] : 0u;
-      __syncthreads();
-      sc[threadIdx.x] += a;
-      __syncthreads();
-    }
-    if (b < nb) bsum[b] = base + sc[threadIdx.x] - v;
-    __syncthreads();
-    if (threadIdx.x == 1023) base += sc[1023];
-    __syncthreads();
+  __shared__ uint32_t wtot[16];
+  const int64_t per = (nb + 1023) / 1024;
+  const int64_t b0 = (int64_t)threadIdx.x * per, b1 = min(b0 + per, nb);
+  uint32_t run = 0;
+  for (int64_t b = b0; b < b1; ++b) run += bsum[b];
+  uint32_t all;
+  uint32_t pos = block_scan_excl<16>(run, wtot, all);
+  for (int64_t b = b0; b < b1; ++b) {
+    const uint32_t v = bsum[b];
+    bsum[b] = pos;
+    pos += v;
   }
-  if (threadIdx.x == 0 && total) *total = (long long)base;
+  if (threadIdx.x == 0 && total) *total = (long long)all;
 }
 
 template <int KIND>
 __global__ __launch_bounds__(kBlock) void k_scan_apply(ScanCtx c, const uint32_t* bsum) {
   // thread t owns elements i0 + 4t .. i0 + 4t + 3 (in order)
-  __shared__ uint32_t sc[kBlock];
+  __shared__ uint32_t sc[kBlock / 64];
   const int64_t i0 = (int64_t)blockIdx.x * kScanPer;
   constexpr int per = kScanPer / kBlock;
   bool f[per];
@@ -730,15 +756,8 @@ __global__ __launch_bounds__(kBlock) void k_scan_apply(ScanCtx c, const uint32_t
     f[j] = i < c.N && flag<KIND>(c, i);
     m += f[j];
   }
-  sc[threadIdx.x] = m;
-  __syncthreads();
-  for (int off = 1; off < kBlock; off <<= 1) {
-    const uint32_t a = threadIdx.x >= off ? sc[threadIdx.x - off] : 0u;
-    __syncthreads();
-    sc[threadIdx.x] += a;
-    __syncthreads();
-  }
-  uint32_t pos = bsum[blockIdx.x] + sc[threadIdx.x] - m;
+  uint32_t all;
+  uint32_t pos = bsum[blockIdx.x] + block_scan_excl<kBlock / 64>(m, sc, all);
 #pragma unroll
   for (int j = 0; j < per; ++j) {
     const int64_t i = i0 + (int64_t)threadIdx.x * per + j;
