@@ -21,6 +21,7 @@
 //                  the left/right borders of the map count as boundary)
 // Declared in include/sbs.h.
 #include <hip/hip_runtime.h>
+#include <cstring>
 #include <stdint.h>
 
 #include <algorithm>
@@ -49,28 +50,85 @@ __device__ __forceinline__ double srgb_linear(int v) {
   return c <= 0.04045 ? c / 12.92 : pow((c + 0.055) / 1.055, 2.4);
 }
 
+// L8 as a function of Y is a non-decreasing step function, so a pixel's
+// value is the number of steps at or below its Y: t[v] (v = 1 .. 255) is the
+// smallest Y whose L8 is at least v (+inf if none). The table comes from the
+// host (light_steps below); the kernel then needs no cube root per pixel.
+struct LightSteps {
+  double t[256];
+};
+
 __global__ __launch_bounds__(kBlock) void k_light(const uint8_t* __restrict__ img, int32_t W, int32_t H, int32_t C,
-                                                  int64_t pitch, uint8_t* __restrict__ L8) {
+                                                  int64_t pitch, uint8_t* __restrict__ L8, LightSteps steps) {
 #pragma clang fp contract(off)
   __shared__ double lin[256];
+  __shared__ double t[256];
   if (C == 3) {
     lin[threadIdx.x] = srgb_linear((int)threadIdx.x);
+    t[threadIdx.x] = steps.t[threadIdx.x];
     __syncthreads();
   }
   const int64_t N = (int64_t)W * H;
-  const double e = 6.0 / 29.0;
-  const double e3 = e * e * e, k3 = 3 * e * e;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
     const int y = (int)((uint32_t)i / (uint32_t)W), x = (int)((uint32_t)i % (uint32_t)W);   // N < 2^31
     const uint8_t* p = img + (int64_t)y * pitch + (int64_t)x * C;
     if (C == 1) { L8[i] = p[0]; continue; }
     const double Y = 0.2126 * lin[p[0]] + 0.7152 * lin[p[1]] + 0.0722 * lin[p[2]];
-    const double f = Y > e3 ? cbrt(Y) : Y / k3 + 4.0 / 29.0;
-    const double s = (116.0 * f - 16.0) * 255.0 / 100.0;
-    const double q = s >= 0 ? floor(s + 0.5) : -floor(-s + 0.5);
-    L8[i] = (uint8_t)(q < 0 ? 0 : (q > 255 ? 255 : (int)q));
+    int v = 0;
+#pragma unroll
+    for (int st = 128; st; st >>= 1)
+      if (Y >= t[v + st]) v += st;
+    L8[i] = (uint8_t)v;
   }
 }
+
+// Gray images: L8 is the image itself (rows gathered from the pitch).
+__global__ __launch_bounds__(kBlock) void k_gray(const uint8_t* __restrict__ img, int32_t W, int32_t H, int64_t pitch,
+                                                 uint8_t* __restrict__ L8) {
+  const int64_t N = (int64_t)W * H;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
+    const int y = (int)((uint32_t)i / (uint32_t)W), x = (int)((uint32_t)i % (uint32_t)W);   // N < 2^31
+    L8[i] = img[(int64_t)y * pitch + x];
+  }
+}
+
+// RGB rows whose width is a multiple of 4 at word-aligned addresses: four
+// pixels per thread from three aligned words, one word written.
+__global__ __launch_bounds__(kBlock) void k_light4(const uint8_t* __restrict__ img, int32_t W, int32_t H,
+                                                   int64_t pitch, uint8_t* __restrict__ L8, LightSteps steps) {
+#pragma clang fp contract(off)
+  __shared__ double lin[256];
+  __shared__ double t[256];
+  lin[threadIdx.x] = srgb_linear((int)threadIdx.x);
+  t[threadIdx.x] = steps.t[threadIdx.x];
+  __syncthreads();
+  const int64_t Q = (int64_t)W * H / 4;   // groups of four pixels (W % 4 == 0)
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < Q; g += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = 4 * g;
+    const int y = (int)((uint32_t)i / (uint32_t)W), x = (int)((uint32_t)i % (uint32_t)W);   // N < 2^31
+    const uint32_t* p = (const uint32_t*)(img + (int64_t)y * pitch + (int64_t)x * 3);
+    const uint32_t w0 = p[0], w1 = p[1], w2 = p[2];
+    const uint32_t px[4][3] = {{w0 & 0xFFu, (w0 >> 8) & 0xFFu, (w0 >> 16) & 0xFFu},
+                               {w0 >> 24, w1 & 0xFFu, (w1 >> 8) & 0xFFu},
+                               {(w1 >> 16) & 0xFFu, w1 >> 24, w2 & 0xFFu},
+                               {(w2 >> 8) & 0xFFu, (w2 >> 16) & 0xFFu, w2 >> 24}};
+    uint32_t out = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const double Y = 0.2126 * lin[px[k][0]] + 0.7152 * lin[px[k][1]] + 0.0722 * lin[px[k][2]];
+      int v = 0;
+#pragma unroll
+      for (int st = 128; st; st >>= 1)
+        if (Y >= t[v + st]) v += st;
+      out |= (uint32_t)v << (8 * k);
+    }
+    *(uint32_t*)(L8 + i) = out;
+  }
+}
+
+// Lightness of an image on `s`: the four-pixel kernel where its layout allows.
+void launch_light(const uint8_t* img, int32_t W, int32_t H, int32_t C, int64_t pitch, uint8_t* L8, int grid,
+                  hipStream_t s);
 
 __global__ __launch_bounds__(kBlock) void k_fill(uint8_t* p, int64_t n, uint8_t v) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
@@ -1001,6 +1059,52 @@ Layout layout(int32_t W, int32_t H) {
   return o;
 }
 
+// The steps of L8(Y) for k_light: L8 = round half away from zero of
+// (116 f(Y) - 16) * 255 / 100, clamped to [0, 255], with f the CIE function
+// (cube root above (6/29)^3, linear below), all in fp64. For each v, a binary
+// search over the ordered bit patterns of the non-negative doubles up to 2
+// finds the smallest Y with L8(Y) >= v. Computed once per process.
+const LightSteps& light_steps() {
+  static const LightSteps steps = [] {
+#pragma clang fp contract(off)
+    LightSteps r{};
+    const double e = 6.0 / 29.0;
+    const double e3 = e * e * e, k3 = 3 * e * e;
+    auto l8 = [&](double Y) -> int {
+      const double f = Y > e3 ? std::cbrt(Y) : Y / k3 + 4.0 / 29.0;
+      const double s = (116.0 * f - 16.0) * 255.0 / 100.0;
+      const double q = s >= 0 ? std::floor(s + 0.5) : -std::floor(-s + 0.5);
+      return q < 0 ? 0 : (q > 255 ? 255 : (int)q);
+    };
+    auto at = [](uint64_t b) { double d; std::memcpy(&d, &b, 8); return d; };
+    uint64_t hi_bits;
+    const double two = 2.0;
+    std::memcpy(&hi_bits, &two, 8);
+    r.t[0] = 0.0;
+    for (int v = 1; v < 256; ++v) {
+      if (l8(two) < v) { r.t[v] = HUGE_VAL; continue; }
+      uint64_t lo = 0, hi = hi_bits;   // l8(at(hi)) >= v
+      while (lo < hi) {
+        const uint64_t mid = lo + (hi - lo) / 2;
+        if (l8(at(mid)) >= v) hi = mid; else lo = mid + 1;
+      }
+      r.t[v] = at(lo);
+    }
+    return r;
+  }();
+  return steps;
+}
+
+void launch_light(const uint8_t* img, int32_t W, int32_t H, int32_t C, int64_t pitch, uint8_t* L8, int grid,
+                  hipStream_t s) {
+  if (C == 1)
+    hipLaunchKernelGGL(k_gray, dim3(grid), dim3(kBlock), 0, s, img, W, H, pitch, L8);
+  else if ((W & 3) == 0 && (pitch & 3) == 0 && ((uintptr_t)img & 3) == 0 && ((uintptr_t)L8 & 3) == 0)
+    hipLaunchKernelGGL(k_light4, dim3(grid), dim3(kBlock), 0, s, img, W, H, pitch, L8, light_steps());
+  else
+    hipLaunchKernelGGL(k_light, dim3(grid), dim3(kBlock), 0, s, img, W, H, C, pitch, L8, light_steps());
+}
+
 int grid_for(int64_t n) {
   const int64_t g = (n + kBlock - 1) / kBlock;
   return (int)(g < 1 ? 1 : (g > 8192 ? 8192 : g));
@@ -1017,7 +1121,7 @@ int sbs_lightness(const uint8_t* img, int32_t W, int32_t H, int32_t C, int64_t p
     return fail(SBS_ERR_INVALID_ARG, "bad image geometry");
   if (!img || !out_l8) return fail(SBS_ERR_INVALID_ARG, "NULL pointer");
   hipStream_t s = (hipStream_t)stream;
-  hipLaunchKernelGGL(k_light, dim3(grid_for((int64_t)W * H)), dim3(kBlock), 0, s, img, W, H, C, pitch, out_l8);
+  launch_light(img, W, H, C, pitch, out_l8, grid_for((int64_t)W * H), s);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(SBS_ERR_HIP, "lightness: %s", hipGetErrorString(e));
   return SBS_OK;
@@ -1071,7 +1175,7 @@ int sbs_boundaries(const uint8_t* img, int32_t W, int32_t H, int32_t C, int64_t 
   // Clear the small counters with kernels (no memset nodes if the caller captures the stream).
   hipLaunchKernelGGL(k_fill, dim3(1), dim3(kBlock), 0, s, (uint8_t*)hist, (int64_t)(256 * 8), (uint8_t)0);
   hipLaunchKernelGGL(k_fill, dim3(1), dim3(kBlock), 0, s, (uint8_t*)misc, (int64_t)1024, (uint8_t)0);
-  hipLaunchKernelGGL(k_light, dim3(g), dim3(kBlock), 0, s, img, W, H, C, pitch, L8);
+  launch_light(img, W, H, C, pitch, L8, g, s);
   // at most 512 blocks: each ends with up to 256 global adds
   hipLaunchKernelGGL(k_hist, dim3(std::min(grid_for((N + 15) / 16), 512)), dim3(kBlock), 0, s, L8, N, hist);
   hipLaunchKernelGGL(k_kmeans, dim3(1), dim3(256), 0, s, hist, K, lut, passes);
