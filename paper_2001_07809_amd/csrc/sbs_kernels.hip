@@ -789,14 +789,23 @@ __device__ __forceinline__ void tile_item_impl(const FrameDev& f, int tile, int 
     uint32_t best[NB];
 #pragma unroll
     for (int b = 0; b < NB; ++b) best[b] = 0xFFFFFFFFu;
+    // Ordered lists: the next 64 entries of a dense row (entry 64 * NB + lane)
+    // have their offset loaded here and their best kept over the groups, with
+    // one key update at the end; entries past those take one per group.
+    constexpr int kHeld = kSorted ? NB + 1 : NB;
+    const bool has2 = kSorted && (int)lane + kWave * NB < cnt;
+    int o2 = 0;
+    uint32_t best2 = 0xFFFFFFFFu;
+    if (has2) o2 = (int)(idx_at(e0 + (int)lane + kWave * NB) - rowbase);
 #pragma unroll
     for (int g = 0; g < DC; g += G) {
       prefix_group(g);
 #pragma unroll
       for (int b = 0; b < NB; ++b)
         if (has[b]) best[b] = group_best(g, ob[b], best[b]);
-      // rows with more than 64 * NB listed pixels in the tile: one key update per group
-      for (int e = (int)lane + kWave * NB; e < cnt; e += kWave) {
+      if (has2) best2 = group_best(g, o2, best2);
+      // rows with more than 64 * kHeld listed pixels in the tile: one key update per group
+      for (int e = (int)lane + kWave * kHeld; e < cnt; e += kWave) {
         int o, slot;
         if constexpr (kSorted) { o = (int)(idx_at(e0 + e) - rowbase); slot = e0 + e; }
         else { o = sm.eo[e]; slot = sm.es[e]; }
@@ -804,6 +813,7 @@ __device__ __forceinline__ void tile_item_impl(const FrameDev& f, int tile, int 
       }
       wave_lds_order();   // LDS free for the next group / row
     }
+    if (has2) key_min(e0 + (int)lane + kWave * NB, best2);
 #pragma unroll
     for (int b = 0; b < NB; ++b) pend_best[b] = best[b];
     if constexpr (kSorted) { pend_e0 = e0; pend_cnt = cnt; }
