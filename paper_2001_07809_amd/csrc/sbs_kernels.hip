@@ -635,6 +635,7 @@ __device__ __forceinline__ void tile_item_impl(const FrameDev& f, int tile, int 
   int e0 = 0, cnt = 0;
   uint32_t pf_next[NB];                    // ordered lists: first 64 * NB list entries of the next active row
   int ob[NB];                              //                their output offsets, once the row is taken
+  uint32_t idx2 = 0u;                      // ordered lists: list entry 64 * NB + lane of the row being taken
 #pragma unroll
   for (int b = 0; b < NB; ++b) { pf_next[b] = 0u; ob[b] = 0; }
   int32_t mv[COLS];                        // unordered lists: pixel map of the next active row
@@ -735,6 +736,9 @@ __device__ __forceinline__ void tile_item_impl(const FrameDev& f, int tile, int 
         ob[b] = (int)(pf_next[b] - rowbase);
         asm volatile("" : "+v"(ob[b])::"memory");
       }
+      // The next 64 entries of a dense row, loaded before the step's row
+      // loads: waiting for this load then leaves those in flight.
+      if ((int)lane + kWave * NB < cnt) idx2 = idx_at(e0 + (int)lane + kWave * NB);
     } else {
 #pragma unroll
       for (int c = 0; c < COLS; ++c) {
@@ -789,14 +793,14 @@ __device__ __forceinline__ void tile_item_impl(const FrameDev& f, int tile, int 
     uint32_t best[NB];
 #pragma unroll
     for (int b = 0; b < NB; ++b) best[b] = 0xFFFFFFFFu;
-    // Ordered lists: the next 64 entries of a dense row (entry 64 * NB + lane)
-    // have their offset loaded here and their best kept over the groups, with
+    // Ordered lists: the next 64 entries of a dense row (entry 64 * NB + lane,
+    // loaded when the row was taken) keep their best over the groups, with
     // one key update at the end; entries past those take one per group.
     constexpr int kHeld = kSorted ? NB + 1 : NB;
     const bool has2 = kSorted && (int)lane + kWave * NB < cnt;
     int o2 = 0;
     uint32_t best2 = 0xFFFFFFFFu;
-    if (has2) o2 = (int)(idx_at(e0 + (int)lane + kWave * NB) - rowbase);
+    if (has2) o2 = (int)(idx2 - rowbase);
 #pragma unroll
     for (int g = 0; g < DC; g += G) {
       prefix_group(g);
