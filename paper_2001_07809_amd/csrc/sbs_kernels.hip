@@ -646,6 +646,7 @@ __device__ __forceinline__ void tile_item_impl(const FrameDev& f, int tile, int 
   uint32_t pend_best[NB];
 #pragma unroll
   for (int b = 0; b < NB; ++b) pend_best[b] = 0xFFFFFFFFu;
+  uint32_t pend_best2 = 0xFFFFFFFFu;       // ordered lists: entry 64 * NB + lane of the previous active row
   int pend_e0 = 0, pend_cnt = 0;
   int32_t pend_slot = -1;
   auto load_next = [&](int y) {            // list data of active row y (y < 0: none)
@@ -774,6 +775,7 @@ __device__ __forceinline__ void tile_item_impl(const FrameDev& f, int tile, int 
 #pragma unroll
       for (int b = 0; b < NB; ++b)
         if ((int)lane + 64 * b < pend_cnt) key_min(pend_e0 + (int)lane + 64 * b, pend_best[b]);
+      if ((int)lane + 64 * NB < pend_cnt) key_min(pend_e0 + (int)lane + 64 * NB, pend_best2);
       pend_cnt = 0;
     } else {
       if (pend_slot >= 0) key_min(pend_slot, pend_best[0]);
@@ -817,7 +819,7 @@ __device__ __forceinline__ void tile_item_impl(const FrameDev& f, int tile, int 
       }
       wave_lds_order();   // LDS free for the next group / row
     }
-    if (has2) key_min(e0 + (int)lane + kWave * NB, best2);
+    pend_best2 = best2;
 #pragma unroll
     for (int b = 0; b < NB; ++b) pend_best[b] = best[b];
     if constexpr (kSorted) { pend_e0 = e0; pend_cnt = cnt; }
