@@ -220,15 +220,15 @@ __global__ __launch_bounds__(256) void k_blur_v(const uint8_t* img, const uint8_
   }
 }
 
-// The same blur in one pass per tile of kBlurTX x ty pixels (ty = 32, or 16
-// when that gives too few tiles to fill the chip; radius up to kBlurTileRad,
-// a compile-time constant per instance so the tap loops unroll): the tile's
+// The same blur in one pass per tile of kBlurTX x ty pixels (ty = 16: more
+// blocks fit a CU than with taller tiles, which measured slower; radius up to
+// kBlurTileRad, a compile-time constant per instance so the tap loops unroll): the tile's
 // clamped input rows and columns go to LDS, the horizontal pass runs over the
 // tile's rows plus the vertical halo into LDS, and the vertical pass reads it
 // from there. Each sum runs over the taps in the same order as in the two
 // kernels above, so the results are the same floats; only the intermediate
 // image no longer travels through HBM.
-constexpr int kBlurTX = 64, kBlurTileRad = 14;   // LDS <= 64 KB per block at 32 rows
+constexpr int kBlurTX = 64, kBlurTileRad = 14;   // LDS < 48 KB per block at 16 rows
 
 template <int C, int RAD>
 __global__ __launch_bounds__(256) void k_blur_tile(const uint8_t* img, const uint8_t* depth, int32_t W, int32_t H,
@@ -372,7 +372,7 @@ int sbs_selective_blur(const uint8_t* img, int32_t W, int32_t H, int32_t C, int6
   hipStream_t s = (hipStream_t)stream;
   if (rad <= kBlurTileRad) {
     const int64_t tx = (W + kBlurTX - 1) / kBlurTX;
-    const int ty = tx * ((H + 31) / 32) >= 1024 ? 32 : 16;
+    const int ty = 16;
     const int rows = ty + 2 * rad, cols = kBlurTX + 2 * rad;
     const size_t lds = (size_t)rows * kBlurTX * C * 4 + (size_t)rows * cols * C;
     const dim3 grid((unsigned)tx, (unsigned)((H + ty - 1) / ty));
