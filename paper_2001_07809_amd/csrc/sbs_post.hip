@@ -104,14 +104,15 @@ __global__ __launch_bounds__(kRowThreads) void k_rc_fill(const int32_t* slot, co
 // determined pixels above and below when their range exceeds the threshold,
 // else their mean rounded half up; one-sided when only one exists; 0 when the
 // column has none. Reads only Algorithm 1's output, so every column is
-// independent. A column is cut into segments of `seglen` rows (64, more for
-// images over 4M rows so the segments fit the grid), one thread per
+// independent. A column is cut into segments of `seglen` rows (16: many
+// short walks fill the chip better than fewer long ones; more for images
+// over 1M rows so the segments fit the grid), one thread per
 // (column, segment): k_rc_colseg records each segment's topmost and
 // bottommost determined value, then k_rc_peek takes the nearest determined
 // values above and below the segment from those records and resolves the
 // segment's rows in two passes (threads of a block cover adjacent columns,
 // so every row access is coalesced).
-constexpr int kColSeg = 64;
+constexpr int kColSeg = 16;
 
 __global__ __launch_bounds__(256) void k_rc_colseg(const int16_t* f, int32_t W, int32_t H, int32_t seglen,
                                                    int16_t* seg_first, int16_t* seg_last) {
