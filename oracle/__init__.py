@@ -9,7 +9,8 @@ the paper (arXiv 2001.07809) that it follows. ``build()`` compiles it to
 ``liboracle.so`` in this folder.
 
 Parity status: every function is pinned by the CPU tests
-(``tests/test_oracle_*.py``). The lightness rounding in ``lightness()`` is
+(``tests/test_oracle_*.py``), the K-means start by hand-worked histograms and
+the fraction-control ranking (``fraction_select``) by library routines. The lightness rounding in ``lightness()`` is
 pinned only at known values and by monotonicity, because the paper's colour
 transform reference is lost. It affects which pixels a list holds, never a
 SAD value.
@@ -59,6 +60,7 @@ def _load():
         "oracle_components": ([V, I32, I32, V, V], I64),
         "oracle_cc_filter": ([V, I32, I32, I32, I64, D, V], None),
         "oracle_boundaries": ([V, I32, I32, I32, I64, I32, I32, I64, D, U64, V, I64, V], I64),
+        "oracle_fraction_select": ([V, I32, I32, D, U64, V, I64], I64),
         "oracle_sad": ([V, V, I32, I32, I32, I64, V, I64, I32, I32, V, V, I32], ctypes.c_int),
         "oracle_sad_sat": ([V, V, I32, I32, I32, I64, V, I64, I32, I32, V, V], ctypes.c_int),
         "oracle_reconstruct": ([V, V, I64, I32, I32, I32, V], None),
@@ -176,6 +178,18 @@ def boundaries(img: np.ndarray, K: int = 4, mode: int = 0, min_cc: int = 50, fra
         raise ValueError("oracle_boundaries failed")
     lst = out[:n].copy()
     return (lst, rmap) if return_map else lst
+
+
+def fraction_select(refined: np.ndarray, frac: float, seed: int = 0) -> np.ndarray:
+    """Border columns plus refined pixels (frac < 0), or exactly round(frac*W*H)
+    pixels by the fixed ranking; ascending uint32 raster indices."""
+    refined = np.ascontiguousarray(refined, dtype=np.uint8)
+    H, W = refined.shape
+    out = np.empty(W * H, np.uint32)
+    n = _load().oracle_fraction_select(_p(refined), W, H, float(frac), seed & (2**64 - 1), _p(out), W * H)
+    if n < 0:
+        raise ValueError("oracle_fraction_select failed")
+    return out[:n].copy()
 
 
 def sad(left: np.ndarray, right: np.ndarray, idx: np.ndarray, block: int, dmax: int,

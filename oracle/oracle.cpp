@@ -289,43 +289,21 @@ void oracle_cc_filter(const uint8_t* B, int32_t W, int32_t H, int32_t mode, int6
   for (int64_t i = 0; i < N; ++i) out[i] = (uint8_t)(comp[(size_t)i] >= 0 && keep[(size_t)comp[(size_t)i]]);
 }
 
-// Full front end: lightness -> histogram K-means -> labels -> refinement ->
-// boundary -> component filter -> border columns (Sec. III: pixels that map
-// to the left/right borders of the disparity map are boundary pixels too)
-// -> optional fraction control.
-//   mode 0 (configured): label open/close, 8-neighbour boundary, keep CC >= min_cc.
-//   mode 1 (paper): 8-neighbour boundary, fill, remove, drop smallest CCs
-//                   totalling <= 4% of boundary pixels.
-// frac < 0: no fraction control; the list is border + refined pixels.
+// Border columns plus refined pixels, then optional fraction control (the
+// last step of the front end; Sec. III: pixels that map to the left/right
+// borders of the disparity map are boundary pixels too).
+// refined: W*H map (1 = kept boundary pixel).
+// frac < 0: the list is the border columns and the refined pixels.
 // frac >= 0 (a benchmark knob, not the paper's): exactly round(frac*W*H)
 // pixels ranked as (1) border columns, (2) refined pixels by component size
 // descending then raster index, (3) other pixels by chessboard distance to
-// the set of (1)+(2) ascending, then mix64(index ^ seed).
+// the set of (1)+(2) ascending, then mix64(index ^ seed), then index.
 // Output: ascending raster indices. Returns the count, -1 on error.
-int64_t oracle_boundaries(const uint8_t* img, int32_t W, int32_t H, int32_t C, int64_t pitch,
-                          int32_t K, int32_t mode, int64_t min_cc, double frac, uint64_t seed,
-                          uint32_t* out, int64_t cap, uint8_t* refined_map) {
-  if (W < 1 || H < 1 || (C != 1 && C != 3) || K < 1) return -1;
+int64_t oracle_fraction_select(const uint8_t* refined, int32_t W, int32_t H, double frac, uint64_t seed,
+                               uint32_t* out, int64_t cap) {
+  if (W < 1 || H < 1) return -1;
   const int64_t N = (int64_t)W * H;
-  std::vector<uint8_t> L((size_t)N), lab((size_t)N), lab2((size_t)N), B((size_t)N), B2((size_t)N), R((size_t)N);
-  oracle_lightness(img, W, H, C, pitch, L.data());
-  int64_t hist[256];
-  oracle_histogram(L.data(), N, hist);
-  int32_t bl[256];
-  std::vector<int64_t> cS(K), cN(K);
-  oracle_kmeans_bins(hist, K, bl, cS.data(), cN.data());
-  oracle_label_pixels(L.data(), N, bl, lab.data());
-  if (mode == 0) {
-    oracle_label_open_close(lab.data(), W, H, lab2.data());
-    oracle_boundary(lab2.data(), W, H, B.data());
-    oracle_cc_filter(B.data(), W, H, 0, min_cc, 0.0, R.data());
-  } else {
-    oracle_boundary(lab.data(), W, H, B.data());
-    oracle_fill(B.data(), W, H, B2.data());
-    oracle_remove(B2.data(), W, H, B.data());
-    oracle_cc_filter(B.data(), W, H, 1, 0, 0.04, R.data());
-  }
-  if (refined_map) std::memcpy(refined_map, R.data(), (size_t)N);
+  const uint8_t* R = refined;
   std::vector<uint8_t> sel((size_t)N, 0);
   for (int y = 0; y < H; ++y) { sel[(size_t)y * W] = 1; sel[(size_t)y * W + W - 1] = 1; }
   if (frac < 0) {
@@ -339,7 +317,9 @@ int64_t oracle_boundaries(const uint8_t* img, int32_t W, int32_t H, int32_t C, i
   // Rank keys: (class, primary, secondary) compared lexicographically.
   std::vector<int32_t> comp((size_t)N);
   std::vector<int64_t> sizes((size_t)N + 1);
-  oracle_components(R.data(), W, H, comp.data(), sizes.data());
+  oracle_components(R, W, H, comp.data(), sizes.data());
+  // Chessboard distance to the selected set: two raster passes, each taking
+  // the 8-neighbours already visited (exact for this metric).
   const int32_t INF = 1 << 28;
   std::vector<int32_t> dist((size_t)N, INF);
   for (int64_t i = 0; i < N; ++i) if (sel[(size_t)i] || R[(size_t)i]) dist[(size_t)i] = 0;
@@ -381,6 +361,40 @@ int64_t oracle_boundaries(const uint8_t* img, int32_t W, int32_t H, int32_t C, i
   int64_t n = 0;
   for (int64_t i = 0; i < N; ++i) if (take[(size_t)i]) out[n++] = (uint32_t)i;
   return n;
+}
+
+// Full front end (Sec. III): lightness -> histogram K-means -> labels ->
+// refinement -> boundary -> component filter -> oracle_fraction_select.
+//   mode 0 (configured): label open/close, 8-neighbour boundary, keep CC >= min_cc.
+//   mode 1 (paper): 8-neighbour boundary, fill, remove, drop smallest CCs
+//                   totalling <= 4% of boundary pixels.
+// frac and seed as for oracle_fraction_select. refined_map (W*H or NULL)
+// receives the kept boundary map. Returns the count, -1 on error.
+int64_t oracle_boundaries(const uint8_t* img, int32_t W, int32_t H, int32_t C, int64_t pitch,
+                          int32_t K, int32_t mode, int64_t min_cc, double frac, uint64_t seed,
+                          uint32_t* out, int64_t cap, uint8_t* refined_map) {
+  if (W < 1 || H < 1 || (C != 1 && C != 3) || K < 1) return -1;
+  const int64_t N = (int64_t)W * H;
+  std::vector<uint8_t> L((size_t)N), lab((size_t)N), lab2((size_t)N), B((size_t)N), B2((size_t)N), R((size_t)N);
+  oracle_lightness(img, W, H, C, pitch, L.data());
+  int64_t hist[256];
+  oracle_histogram(L.data(), N, hist);
+  int32_t bl[256];
+  std::vector<int64_t> cS(K), cN(K);
+  oracle_kmeans_bins(hist, K, bl, cS.data(), cN.data());
+  oracle_label_pixels(L.data(), N, bl, lab.data());
+  if (mode == 0) {
+    oracle_label_open_close(lab.data(), W, H, lab2.data());
+    oracle_boundary(lab2.data(), W, H, B.data());
+    oracle_cc_filter(B.data(), W, H, 0, min_cc, 0.0, R.data());
+  } else {
+    oracle_boundary(lab.data(), W, H, B.data());
+    oracle_fill(B.data(), W, H, B2.data());
+    oracle_remove(B2.data(), W, H, B.data());
+    oracle_cc_filter(B.data(), W, H, 1, 0, 0.04, R.data());
+  }
+  if (refined_map) std::memcpy(refined_map, R.data(), (size_t)N);
+  return oracle_fraction_select(R.data(), W, H, frac, seed, out, cap);
 }
 
 // ---------------------------------------------------------------------------

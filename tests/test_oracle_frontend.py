@@ -208,3 +208,165 @@ def test_paper_mode_frontend_runs():
     f = scenes.make_frame(spec)
     lst = oracle.boundaries(f.left, K=10, mode=1)
     assert lst.size >= 2 * spec.H and np.all(np.diff(lst.astype(np.int64)) > 0)
+
+
+# --- pins for the K-means start and the fraction-control ranking -----------------
+
+def test_kmeans_initial_centres_hand_worked():
+    """Hand-worked histograms whose final partition depends on the initial
+    centres, the tie rule and the empty-cluster rule (traces in the fixture)."""
+    g = json.load(open(os.path.join(GOLD, "kmeans_init_hand.json")))
+    for case in g["cases"]:
+        h = np.zeros(256, np.int64)
+        for b, c in case["bins"].items():
+            h[int(b)] = c
+        bl, cS, cN, _ = oracle.kmeans_bins(h, case["K"])
+        for b, lab in case["labels"].items():
+            assert bl[int(b)] == lab, (case["bins"], b)
+        assert np.all(bl[h == 0] == -1)
+        for i, (s, n) in enumerate(case["centres"]):
+            assert Fraction(int(cS[i]), int(cN[i])) == Fraction(s, n), (i, cS, cN)
+
+
+_M64 = (1 << 64) - 1
+
+
+def _splitmix64_mix(z):
+    """SplitMix64's output function (Steele, Lea & Flood, OOPSLA 2014) on uint64 arrays."""
+    z = np.asarray(z, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+    return z ^ (z >> np.uint64(31))
+
+
+def test_splitmix64_published_vector():
+    # The reference generator seeded with 1234567 (state += 0x9E3779B97F4A7C15,
+    # then the output function) starts with these published values.
+    s = 1234567
+    expect = [6457827717110365317, 3203168211198807973, 9817491932198370423,
+              4593380528125082431, 16408922859458223821]
+    for e in expect:
+        s = (s + 0x9E3779B97F4A7C15) & _M64
+        assert int(_splitmix64_mix(np.uint64(s))) == e
+
+
+def _ranked_selection(rmap, frac, seed):
+    """The fraction-control ranking computed with library routines: border
+    columns (class 0, by index); refined pixels (class 1) by 8-connected
+    component size descending (scipy.ndimage.label), then index; the rest
+    (class 2) by chessboard distance to classes 0 and 1
+    (scipy.ndimage.distance_transform_cdt), then the hash of (index ^ seed),
+    then index. The first round(frac * W * H), ascending."""
+    H, W = rmap.shape
+    N = W * H
+    idx = np.arange(N, dtype=np.int64)
+    border = np.zeros((H, W), bool)
+    border[:, 0] = border[:, W - 1] = True
+    refined = rmap.astype(bool)
+    lab, _ = ndi.label(refined, structure=np.ones((3, 3)))
+    sizes = np.bincount(lab.reshape(-1))
+    dist = ndi.distance_transform_cdt(~(border | refined), metric="chessboard").reshape(-1)
+    b = border.reshape(-1)
+    r = refined.reshape(-1) & ~b
+    cls = np.where(b, 0, np.where(r, 1, 2))
+    prim = np.where(b, 0, np.where(r, -sizes[lab.reshape(-1)], dist)).astype(np.int64)
+    hsh = _splitmix64_mix(idx.astype(np.uint64) ^ np.uint64(seed & _M64))
+    sec = np.where(cls == 2, hsh, idx.astype(np.uint64))
+    order = np.lexsort((idx, sec, prim, cls))
+    want = min(N, int(round(frac * N)))
+    return np.sort(order[:want]).astype(np.uint32), int(b.sum()), int(r.sum())
+
+
+def _rect_scene(W, H, seed):
+    """A piecewise-constant gray image: rectangles of distinct sizes and four
+    well-separated levels, so the refined set has components of many sizes."""
+    rng = np.random.default_rng(seed)
+    img = np.full((H, W), 30, np.uint8)
+    for k in range(14):
+        w, h = int(rng.integers(6, W // 3)), int(rng.integers(6, H // 3))
+        x, y = int(rng.integers(1, W - w - 1)), int(rng.integers(1, H - h - 1))
+        img[y:y + h, x:x + w] = (90, 150, 220)[k % 3]
+    return img
+
+
+@pytest.mark.parametrize("case", ["rects", "tsukuba_gray"])
+def test_fraction_control_ranking_matches_library_routines(case):
+    if case == "rects":
+        img = _rect_scene(160, 120, 11)
+        seed = 0x1234
+    else:
+        spec = scenes.PRESETS[case]
+        img = scenes.make_frame(spec).left
+        seed = spec.seed
+    H, W = img.shape[:2]
+    N = W * H
+    _, rmap = oracle.boundaries(img, K=4, mode=0, min_cc=50, return_map=True)
+    _, nb, nr = _ranked_selection(rmap, 0.0, seed)
+    assert nr > 200, "the map must hold refined pixels beyond the border columns"
+    # cuts inside class 0, inside class 1 (component size order decides),
+    # just past it and deep into class 2 (distance, then hash, decides)
+    wants = [nb // 2, nb + nr // 3, nb + (2 * nr) // 3, nb + nr + 5, nb + nr + (N - nb - nr) // 4,
+             nb + nr + (N - nb - nr) // 2, N]
+    for want in wants:
+        frac = want / N
+        got = oracle.boundaries(img, K=4, mode=0, min_cc=50, frac=frac, seed=seed)
+        exp, _, _ = _ranked_selection(rmap, frac, seed)
+        np.testing.assert_array_equal(got, exp, err_msg=f"{case} want={want}")
+
+
+def test_fraction_control_size_order_and_distance_decide():
+    """On the rectangle scene the cut inside class 1 keeps whole large
+    components before small ones, and the cut inside class 2 keeps every
+    pixel at distance 1 before any pixel at distance 3."""
+    img = _rect_scene(160, 120, 11)
+    H, W = img.shape
+    _, rmap = oracle.boundaries(img, K=4, mode=0, min_cc=50, return_map=True)
+    lab, n = ndi.label(rmap.astype(bool), structure=np.ones((3, 3)))
+    sizes = np.bincount(lab.reshape(-1))[1:]
+    assert np.unique(sizes).size >= 3
+    border = np.zeros((H, W), bool)
+    border[:, 0] = border[:, W - 1] = True
+    nb = int(border.sum())
+    inner = rmap.astype(bool) & ~border
+    biggest = np.argmax(sizes) + 1
+    nbig = int((inner & (lab == biggest)).sum())
+    got = oracle.boundaries(img, K=4, mode=0, min_cc=50, frac=(nb + nbig) / (W * H), seed=1)
+    taken = np.zeros(W * H, bool)
+    taken[got] = True
+    np.testing.assert_array_equal(taken.reshape(H, W) & inner, inner & (lab == biggest))
+    dist = ndi.distance_transform_cdt(~(border | rmap.astype(bool)), metric="chessboard")
+    n1 = int((dist == 1).sum())
+    got = oracle.boundaries(img, K=4, mode=0, min_cc=50, frac=(nb + int(inner.sum()) + n1) / (W * H), seed=1)
+    taken = np.zeros(W * H, bool)
+    taken[got] = True
+    taken = taken.reshape(H, W)
+    assert np.all(taken[dist == 1]) and not np.any(taken[dist >= 2])
+
+
+@pytest.mark.parametrize("density,seed", [(0.002, 21), (0.01, 22), (0.05, 23)])
+def test_fraction_select_on_sparse_maps_matches_library_routines(density, seed):
+    """Fraction control on arbitrary refined maps: isolated pixels and short
+    runs, where every term of the chessboard distance and every component
+    size matter, against the ranking built from scipy routines."""
+    rng = np.random.default_rng(seed)
+    H, W = 57, 83
+    rmap = (rng.random((H, W)) < density).astype(np.uint8)
+    for _ in range(6):   # a few short horizontal and vertical runs of various lengths
+        y, x, L = int(rng.integers(0, H)), int(rng.integers(0, W - 9)), int(rng.integers(2, 9))
+        if rng.random() < 0.5:
+            rmap[y, x:x + L] = 1
+        else:
+            rmap[max(0, y - L):y, x] = 1
+    _, nb, nr = _ranked_selection(rmap, 0.0, seed)
+    N = W * H
+    natural = oracle.fraction_select(rmap, -1.0)
+    border = np.zeros((H, W), bool)
+    border[:, 0] = border[:, W - 1] = True
+    np.testing.assert_array_equal(natural, np.flatnonzero(border | rmap.astype(bool)).astype(np.uint32))
+    for want in sorted({nb // 3, nb + nr // 2, nb + nr + 1, nb + nr + (N - nb - nr) // 8,
+                        nb + nr + (N - nb - nr) // 3, nb + nr + (2 * (N - nb - nr)) // 3, N}):
+        got = oracle.fraction_select(rmap, want / N, seed)
+        exp, _, _ = _ranked_selection(rmap, want / N, seed)
+        assert got.size == want
+        np.testing.assert_array_equal(got, exp, err_msg=f"want={want}")
