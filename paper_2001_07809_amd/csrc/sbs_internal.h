@@ -26,7 +26,7 @@ struct FrameDev {
   uint32_t* lp;        // left copy, RGBx u32 per pixel, replicate-padded (edge bands only when linpl)
   uint32_t* rp;        // right copy, RGBx u32 per pixel, replicate-padded
   uint64_t* rowbits;   // per row: one bit per 64-column group holding a listed pixel
-  uint32_t* state;     // state[0] bit 0: the list is not in non-decreasing raster order;
+  uint32_t* state;     // state[0] bit 0: the list is not in strictly increasing raster order;
                        // state[2..3]: u64, the first list slot holding an index >= W*H (n if none)
   int32_t* tptr;       // sorted lists: tptr[y * tpw + t] = first list slot >= y*W + t*txo
   int64_t pitch;       // bytes between image rows

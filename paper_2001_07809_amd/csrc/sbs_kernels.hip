@@ -8,7 +8,8 @@
 //
 // Tiled path (per frame; every kernel also runs over a whole batch of frames):
 //   k_check     clears the result keys, answers indices >= W*H, and finds out
-//               whether the list is in non-decreasing raster order.
+//               whether the list is in strictly increasing raster order
+//               (a repeated index sends it down the pixel-map path).
 //   k_prep      replicate-padded RGBx copy of the right image (one u32 per
 //               pixel, so one v_sad_u8 covers all channels of a pixel), and of
 //               the left image: whole, or only the edge bands that tiles
@@ -101,11 +102,11 @@ __global__ __launch_bounds__(256) void k_check(const FrameDev* __restrict__ tabl
       for (int j = 0; j < 4; ++j)
         if (k + j < n) { p[j] = idx[k + j]; keys[k + j] = 0xFFFFFFFFu; }
     }
-    if (k > 0 && idx[k - 1] > p[0]) unsorted = true;
+    if (k > 0 && idx[k - 1] >= p[0]) unsorted = true;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       if (k + j >= n) break;
-      if (j < 3 && k + j + 1 < n && p[j] > p[j + 1]) unsorted = true;
+      if (j < 3 && k + j + 1 < n && p[j] >= p[j + 1]) unsorted = true;
       if ((int64_t)p[j] >= N) {
         f.out_disp[k + j] = 255;
         if (f.out_cost) f.out_cost[k + j] = 0xFFFFFFFFu;

@@ -103,6 +103,28 @@ def test_oracle_frontend_list(torch, sbs):
     assert_parity(run_gpu(torch, sbs, vga.left, vga.right, idx, 11, 31), exp, "frontend list rgb")
 
 
+def test_sorted_list_with_repeats(torch, sbs):
+    # A list in non-decreasing order with every index twice, on a frame whose
+    # tile rows hold every pixel (a tile row then has twice its width in list
+    # entries): repeats must not take the ordered path, whose per-row ranges
+    # count distinct entries.
+    rng = np.random.default_rng(21)
+    for C, W, H in ((3, 600, 40), (1, 1100, 24)):
+        shape = (H, W) if C == 1 else (H, W, C)
+        L = rng.integers(0, 256, shape, dtype=np.uint8)
+        R = np.roll(L, -5, axis=1)
+        base = np.arange(W * H, dtype=np.uint32)[rng.random(W * H) < 0.9]
+        idx = np.sort(np.concatenate([base, base]))
+        exp = oracle.sad(L, R, idx, 7, 40)
+        try:
+            for cpl, chunk in ((4, 8), (4, 16), (8, 8)):
+                sbs.set_plan(cols_per_lane=cpl, chunk=chunk, tile_rows=32)
+                assert_parity(run_gpu(torch, sbs, L, R, idx, 7, 40), exp,
+                              f"sorted repeats C{C} {W}x{H} cpl{cpl} chunk{chunk}")
+        finally:
+            sbs.set_plan()
+
+
 def test_middlebury_shape(torch, sbs):
     spec = scenes.PRESETS["middlebury_rgb"]
     f = scenes.make_frame(spec)
