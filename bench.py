@@ -3,14 +3,20 @@
 
 Workload (default ``uhd_video``): 250 synthetic 4096x2304 RGB stereo frames.
 Each has 40 textured regions with disparity 0..127 that move up to 4 px and
-drift by up to 1 disparity per frame. Each frame's boundary list holds a
-fraction of its pixels drawn per frame from [0.12, 0.24], taken near the
-region outlines. Block 31, dmax 127.
+drift by up to 1 disparity per frame. Block 31, dmax 127. Each frame's list
+is the method's own refined boundary set (Sec. III: lightness K-means with
+K = 4, 3x3 open/close of the labels, 8-neighbour boundaries, components of
+at least 50 pixels, the border columns), built on the device by the front end
+before timing and cut to a fraction of the frame drawn from [0.12, 0.24] by a
+fixed ranking.
 
 One step is one pass of the whole hot path over the batch: every frame goes
-through one persistent, queue-fed launch (sbs_sad_disparity_batched). Inputs
-are resident in HBM before timing starts. value = sum over frames of
-n_f * (dmax + 1) evaluations / step time.
+through one persistent, queue-fed launch (sbs_sad_disparity_batched) with the
+plan the autotuner picks for this batch (sbs_tune, run before timing; the
+default plan's time is reported beside it). Inputs are resident in HBM before
+timing starts. value = sum over frames of n_f * (dmax + 1) evaluations / step
+time. A secondary line times the same pass over the generator's contour-band
+lists.
 
 Printed beside it (one JSON line on stdout):
   * roofline: the tile kernel (the dominant kernel), timed live with HIP events
@@ -37,6 +43,8 @@ sys.path.insert(0, ROOT)
 METRIC = "boundary-px×disparity SAD evals/s + roofline %; batched vs per-frame"
 PEAK_LANE_OPS = 256 * 64 * 2.4e9          # 32-bit integer VALU lane-ops/s (39.3 T)
 PEAK_SAD_AD = PEAK_LANE_OPS * 4           # absolute differences/s with v_sad_u8 (4 per lane-op)
+FRONT_K = 4                               # lightness clusters of the front end
+FRONT_MIN_CC = 50                         # smallest kept boundary component (pixels)
 
 
 def log(msg):
@@ -87,6 +95,9 @@ def main():
     ap.add_argument("--workload", default="uhd_video", choices=["uhd_video"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the per-frame / graph comparisons")
+    ap.add_argument("--no-tune", action="store_true", help="run the default plan (no autotuning before timing)")
+    ap.add_argument("--no-contour", action="store_true",
+                    help="skip the secondary measurement on the generator's contour-band lists")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target oracle time for the CPU sample")
     ap.add_argument("--tuning", default=os.path.join(ROOT, "paper_2001_07809_amd", "tuning.json"))
     ap.add_argument("--serve", action="store_true",
@@ -149,94 +160,47 @@ def main():
     F = args.frames
     t0 = time.time()
     fracs = scenes.video_fracs(spec, 0, F)
-    left, right, lists = scenes.make_video(spec, 0, F, fracs)
+    # The generator's contour-band lists come with the frames; they feed only
+    # the secondary measurement.
+    left, right, contour = scenes.make_video(spec, 0, F, fracs, with_lists=not args.no_contour)
     log(f"generated {F} frames of {spec.W}x{spec.H}x{spec.C} in {time.time() - t0:.1f}s")
 
     dev = torch.device("cuda:0")
     t0 = time.time()
     Ld = torch.from_numpy(left).to(dev)
     Rd = torch.from_numpy(right).to(dev)
-    Id = [torch.from_numpy(l.view(np.int32)).to(dev) for l in lists]
     torch.cuda.synchronize()
     h2d_s = time.time() - t0
-    h2d_bytes = left.nbytes + right.nbytes + sum(l.nbytes for l in lists)
+    h2d_bytes = left.nbytes + right.nbytes
     log(f"uploaded {h2d_bytes / 1e9:.1f} GB in {h2d_s:.1f}s")
 
-    frames = [(Ld[t], Rd[t], Id[t], spec.block, spec.dmax) for t in range(F)]
-    runner = sbs.BatchRunner(frames, with_cost=True)
-    n_total = sum(int(l.size) for l in lists)
-    evals = sum(int(l.size) * (spec.dmax + 1) for l in lists)
-    log(f"workspace {runner.workspace.numel() / 1e9:.1f} GB, {n_total} listed pixels, {evals:.3e} evals/step")
+    # The method's own boundary set, built on the device before timing: per
+    # frame the refined segment boundaries of the left image (lightness
+    # K-means with K = 4, 3x3 open/close of the labels, 8-neighbour boundary,
+    # components of >= 50 px, border columns), cut to the frame's fraction by
+    # the fixed ranking (sbs_boundaries).
+    t0 = time.time()
+    Id = []
+    for t in range(F):
+        lst = sbs.boundaries(Ld[t], K=FRONT_K, mode=0, min_cc=FRONT_MIN_CC, frac=float(fracs[t]),
+                             seed=spec.seed + t)
+        Id.append(lst.clone())
+    torch.cuda.synchronize()
+    log(f"front-end lists for {F} frames in {time.time() - t0:.1f}s")
 
-    for _ in range(args.warmup):
-        runner.run()
-    torch.cuda.synchronize()
-    log("warm-up done")
-
-    # Timed region: K batched steps.
-    stream = torch.cuda.current_stream()
-    sbs.kernel_timing(True)
-    sbs.kernel_times()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    w0 = time.perf_counter()
-    e0.record(stream)
-    for _ in range(args.steps):
-        runner.run()
-    e1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - w0
-    sbs.kernel_timing(False)
-    ktimes = sbs.kernel_times()
-    step_ms = e0.elapsed_time(e1) / args.steps
-    step_ms = max(step_ms, wall * 1000.0 / args.steps)   # never report faster than the host clock saw
-    kern_ms = float(np.mean(ktimes)) if ktimes else float("nan")
+    main_run = measure(args, sbs, torch, np, spec, Ld, Rd, Id, tune=not args.no_tune, compare=not args.no_compare)
+    runner = main_run["runner"]
+    n_total = main_run["n_total"]
+    evals = main_run["evals"]
+    step_ms = main_run["step_ms"]
+    kern_ms = main_run["kernel_ms"]
     value = evals / (step_ms / 1e3)
-    log(f"batched step {step_ms:.2f} ms, tile kernel {kern_ms:.2f} ms over {len(ktimes)} launches")
-
-    # Batching comparison.
-    compare = None
-    if not args.no_compare:
-        reps = max(1, min(args.steps, 3))
-
-        def timed(fn):
-            torch.cuda.synchronize()
-            a = torch.cuda.Event(enable_timing=True)
-            b = torch.cuda.Event(enable_timing=True)
-            a.record(stream)
-            for _ in range(reps):
-                fn()
-            b.record(stream)
-            torch.cuda.synchronize()
-            return a.elapsed_time(b) / reps
-
-        per_frame_ms = timed(runner.run_per_frame)
-        g_batched = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(g_batched):
-            runner.run()
-        graph_batched_ms = timed(g_batched.replay)
-        del g_batched
-        g_pf = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(g_pf):
-            runner.run_per_frame()
-        graph_per_frame_ms = timed(g_pf.replay)
-        del g_pf
-        compare = {
-            "batched_persistent_ms": round(step_ms, 3),
-            "batched_persistent_graph_ms": round(graph_batched_ms, 3),
-            "per_frame_launches_ms": round(per_frame_ms, 3),
-            "per_frame_launches_graph_ms": round(graph_per_frame_ms, 3),
-            "speedup_vs_per_frame": round(per_frame_ms / step_ms, 3),
-            "speedup_vs_per_frame_graph": round(graph_per_frame_ms / min(step_ms, graph_batched_ms), 3),
-        }
-        log(f"compare: {compare}")
 
     # Roofline of the dominant kernel.
-    ops = algorithmic_lane_ops([(spec.W, spec.H, int(l.size), spec.dmax) for l in lists])
+    ops = algorithmic_lane_ops([(spec.W, spec.H, int(l.numel()), spec.dmax) for l in Id])
     achieved = ops / (kern_ms / 1e3) / 1e12
     brute_ad = evals * spec.block * spec.block * spec.C
-    workload_key = f"{args.workload}:{F}"
+    workload_key = f"{args.workload}:{F}:frontend"
     roofline = {
         "bound": "alu",
         "achieved": round(achieved, 3),
@@ -261,7 +225,7 @@ def main():
     if not args.no_cpu_baseline:
         import oracle
         threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or (os.cpu_count() or 1)
-        idx0 = lists[0]
+        idx0 = Id[0].cpu().numpy().view(np.uint32)
         rng = np.random.default_rng(0)
         perm = np.sort(rng.permutation(idx0.size))
         # Size the sample from a probe run (the first, small call also pays the
@@ -285,10 +249,26 @@ def main():
             "unit": "evals/s",
             "cores": threads,
             "kind": "oracle",
-            "sample": f"{m} random entries of frame 0's list ({m * (spec.dmax + 1)} evals, {cpu_s:.1f} s)",
+            "sample": f"{m} random entries of frame 0's front-end list ({m * (spec.dmax + 1)} evals, {cpu_s:.1f} s)",
             "gpu_matches_sample": match,
         }
         log(f"cpu baseline {cpu}")
+    del runner, main_run["runner"]
+
+    # Secondary: the same pass over the generator's contour-band lists.
+    secondary = None
+    if contour is not None:
+        Cd = [torch.from_numpy(c.view(np.int32)).to(dev) for c in contour]
+        sec = measure(args, sbs, torch, np, spec, Ld, Rd, Cd, tune=not args.no_tune, compare=False)
+        del sec["runner"]
+        secondary = {
+            "lists": "generator contour bands: border columns, then pixels nearest the region outlines "
+                     "(seeded hash on ties), the same per-frame fractions",
+            "value": sec["evals"] / (sec["step_ms"] / 1e3), "unit": "evals/s",
+            "ms_per_step": round(sec["step_ms"], 3), "kernel_ms": round(sec["kernel_ms"], 4),
+            "listed_pixels_per_step": sec["n_total"], "plan": sec["plan"], "tuned": sec["tuned"],
+        }
+        log(f"contour-band lists: {secondary}")
 
     rec = {
         "metric": METRIC,
@@ -304,19 +284,111 @@ def main():
         "dtype": "u8",
         "data": "synthetic",
         "config": {
-            "workload": f"{F}-frame {spec.W}x{spec.H} RGB stereo video, batched persistent launch",
+            "workload": f"{F}-frame {spec.W}x{spec.H} RGB stereo video, batched persistent launch, "
+                        f"lists from the device front end",
             "frames": F, "W": spec.W, "H": spec.H, "C": spec.C, "block": spec.block, "dmax": spec.dmax,
-            "boundary_fraction": "per frame U[0.12, 0.24] (contour bands)",
+            "lists": f"refined segment boundaries per frame (K={FRONT_K} lightness K-means, 3x3 open/close, "
+                     f"components >= {FRONT_MIN_CC} px, border columns), cut to the frame's fraction "
+                     f"U[0.12, 0.24] by the fixed ranking; built on the device before timing",
             "listed_pixels_per_step": n_total, "evals_per_step": evals,
+            "plan": main_run["plan"], "tuned": main_run["tuned"],
+            "default_plan": main_run["default_plan"], "default_plan_ms_per_step": main_run["default_ms"],
             "parallelism": "single GPU",
         },
         "roofline": roofline,
         "brute_force_equivalent": brute_equiv,
-        "batching": compare,
-        "h2d": {"bytes": h2d_bytes, "seconds": round(h2d_s, 3), "note": "excluded from value"},
+        "batching": main_run["compare"],
+        "secondary_contour_lists": secondary,
+        "h2d": {"bytes": h2d_bytes, "seconds": round(h2d_s, 3), "note": "images only; excluded from value"},
         "cpu_baseline": cpu,
     }
     print(json.dumps(rec), flush=True)
+
+
+def measure(args, sbs, torch, np, spec, Ld, Rd, Id, tune, compare):
+    """One batched pass over all frames: default-plan time, then (with
+    ``tune``) the autotuned plan, then the timed region of ``args.steps``
+    passes with the tile kernel timed by HIP events on its stream."""
+    F = len(Id)
+    frames = [(Ld[t], Rd[t], Id[t], spec.block, spec.dmax) for t in range(F)]
+    runner = sbs.BatchRunner(frames, with_cost=True)
+    n_total = sum(int(l.numel()) for l in Id)
+    evals = n_total * (spec.dmax + 1)
+    log(f"workspace {runner.workspace.numel() / 1e9:.1f} GB, {n_total} listed pixels, {evals:.3e} evals/step")
+    stream = torch.cuda.current_stream()
+
+    def timed(fn, reps):
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(reps):
+            fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    default_plan = runner.plan()
+    for _ in range(max(args.warmup, 1)):
+        runner.run()
+    default_ms = timed(runner.run, max(1, min(args.steps, 3)))
+    log(f"default plan {default_plan}: {default_ms:.2f} ms per step")
+    if tune:
+        t0 = time.time()
+        runner.tune()
+        log(f"tuned in {time.time() - t0:.1f}s")
+    plan = runner.plan()
+    for _ in range(args.warmup):
+        runner.run()
+    torch.cuda.synchronize()
+    log(f"plan {plan}; warm-up done")
+
+    # Timed region: K batched steps.
+    sbs.kernel_timing(True)
+    sbs.kernel_times()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(args.steps):
+        runner.run()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    sbs.kernel_timing(False)
+    ktimes = sbs.kernel_times()
+    step_ms = e0.elapsed_time(e1) / args.steps
+    step_ms = max(step_ms, wall * 1000.0 / args.steps)   # never report faster than the host clock saw
+    kern_ms = float(np.mean(ktimes)) if ktimes else float("nan")
+    log(f"batched step {step_ms:.2f} ms, tile kernel {kern_ms:.2f} ms over {len(ktimes)} launches")
+
+    cmp = None
+    if compare:
+        reps = max(1, min(args.steps, 3))
+        per_frame_ms = timed(runner.run_per_frame, reps)
+        g_batched = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g_batched):
+            runner.run()
+        graph_batched_ms = timed(g_batched.replay, reps)
+        del g_batched
+        g_pf = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g_pf):
+            runner.run_per_frame()
+        graph_per_frame_ms = timed(g_pf.replay, reps)
+        del g_pf
+        cmp = {
+            "batched_persistent_ms": round(step_ms, 3),
+            "batched_persistent_graph_ms": round(graph_batched_ms, 3),
+            "per_frame_launches_ms": round(per_frame_ms, 3),
+            "per_frame_launches_graph_ms": round(graph_per_frame_ms, 3),
+            "speedup_vs_per_frame": round(per_frame_ms / step_ms, 3),
+            "speedup_vs_per_frame_graph": round(graph_per_frame_ms / min(step_ms, graph_batched_ms), 3),
+        }
+        log(f"compare: {cmp}")
+    return {"runner": runner, "n_total": n_total, "evals": evals, "step_ms": step_ms, "kernel_ms": kern_ms,
+            "plan": plan, "tuned": bool(tune), "default_plan": default_plan, "default_ms": round(default_ms, 3),
+            "compare": cmp}
 
 
 SERVE_CLASSES = [("serve_vga", 1000), ("serve_fhd", 600), ("serve_uhd", 400)]

@@ -124,10 +124,13 @@ int sbs_check_indices(const sbs_frame* frames, int32_t nframes, void* workspace,
 /*
  * Autotuner: times each tile plan (columns per lane, disparities per chunk,
  * rows per tile, persistent grid size) on these frames, keeps the fastest, and
- * stores it under the key (arch, W, H, C, block, dmax, density bucket) in a
- * JSON cache at cache_path (created or updated; NULL: in memory only). Later
- * calls with a matching key use the stored plan. Synchronous. Outputs of the
- * frames are written as a side effect.
+ * stores it under the key (arch, W, H, C, block, dmax, density bucket,
+ * frames per call rounded up to a power of two; taken from the first frame
+ * with a non-empty list) in a JSON cache at cache_path (created or updated;
+ * NULL: in memory only). Later calls with a matching key use the stored plan.
+ * Synchronous; runs in a library-managed workspace (allocated on first use,
+ * kept until the process ends). Outputs of the frames are written as a side
+ * effect.
  */
 int sbs_tune(const sbs_frame* frames, int32_t nframes, const char* cache_path);
 
@@ -163,7 +166,8 @@ int sbs_sad_disparity_per_frame(const sbs_frame* frames, int32_t nframes, void* 
  * (cols_per_lane, chunk, tile_rows, waves_per_cu); 0 in a field means
  * "automatic". sbs_set_plan forces a plan for subsequent calls (all fields 0
  * restores automatic choice); sbs_get_plan reports the plan the library would
- * use for a frame. Valid cols_per_lane: 4, 8 (8 only with chunk 8); chunk:
+ * use for a single-frame call on `frame`, sbs_get_plan_batched the plan of a
+ * batched call on `frames`. Valid cols_per_lane: 4, 8 (8 only with chunk 8); chunk:
  * 8, 16; tile_rows: 8..256; waves_per_cu: 1..16. A frame runs with 8 columns
  * per lane only where its window sums allow packed 16-bit accumulators
  * (2 * block * 255 * C <= 65535) and min(n, (tile_rows - 1) * W) < 2^23;
@@ -180,6 +184,7 @@ typedef struct {
 
 int sbs_set_plan(const sbs_plan* plan);
 int sbs_get_plan(const sbs_frame* frame, sbs_plan* plan);
+int sbs_get_plan_batched(const sbs_frame* frames, int32_t nframes, sbs_plan* plan);
 
 /*
  * Kernel timing (for the benchmark). While enabled, every call records a pair

@@ -94,6 +94,7 @@ def lib():
         "sbs_abi_version": ([], ctypes.c_int),
         "sbs_set_plan": ([ctypes.POINTER(Plan)], ctypes.c_int),
         "sbs_get_plan": ([FP, ctypes.POINTER(Plan)], ctypes.c_int),
+        "sbs_get_plan_batched": ([FP, I32, ctypes.POINTER(Plan)], ctypes.c_int),
         "sbs_kernel_timing": ([I32], ctypes.c_int),
         "sbs_reconstruct_workspace_bytes": ([I32, I32], SZ),
         "sbs_reconstruct": ([V, V, I64, I32, I32, I32, V, V, SZ, V], ctypes.c_int),
@@ -351,3 +352,14 @@ class BatchRunner:
 
     def check_indices(self, stream=None) -> int:
         return check_indices(self.workspace, stream)
+
+    def plan(self) -> dict:
+        """The plan a batched call on these frames runs with."""
+        p = Plan()
+        _check(lib().sbs_get_plan_batched(self.desc, self.nframes, ctypes.byref(p)))
+        return {"cols_per_lane": p.cols_per_lane, "chunk": p.chunk, "tile_rows": p.tile_rows,
+                "waves_per_cu": p.waves_per_cu}
+
+    def tune(self, cache_path: str | None = None):
+        """Autotune the plan of a batched call on these frames (sbs_tune)."""
+        _check(lib().sbs_tune(self.desc, self.nframes, None if cache_path is None else cache_path.encode()))

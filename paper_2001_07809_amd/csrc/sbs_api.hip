@@ -105,10 +105,19 @@ int density_bucket(const sbs_frame& f) {
   return b > 20 ? 20 : b;
 }
 
-std::string plan_key(const sbs_frame& f) {
+// Frames per launch, rounded up to a power of two: a plan tuned for a
+// 250-frame batch (few, large items per wavefront slot) is not the plan of a
+// single frame of the same shape.
+int batch_bucket(int nframes) {
+  int b = 1;
+  while (b < nframes && b < (1 << 20)) b <<= 1;
+  return b;
+}
+
+std::string plan_key(const sbs_frame& f, int nframes) {
   std::ostringstream o;
   o << "gfx950/" << f.W << "x" << f.H << "x" << f.C << "/b" << f.block << "/d" << f.dmax << "/rho"
-    << density_bucket(f);
+    << density_bucket(f) << "/nf" << batch_bucket(nframes);
   return o.str();
 }
 
@@ -182,7 +191,7 @@ Plan choose_plan(const sbs_frame* frames, int nframes, const sbs_frame& key) {
     if (g_forced_plan.wpc) p.wpc = g_forced_plan.wpc;
     return p;
   }
-  auto it = g_tuned.find(plan_key(key));
+  auto it = g_tuned.find(plan_key(key, nframes));
   if (it != g_tuned.end()) return it->second;
   return default_plan(frames, nframes);
 }
@@ -632,6 +641,22 @@ int sbs_get_plan(const sbs_frame* frame, sbs_plan* plan) {
   return SBS_OK;
 }
 
+int sbs_get_plan_batched(const sbs_frame* frames, int32_t nframes, sbs_plan* plan) {
+  if (!frames || nframes < 1 || !plan) return fail(SBS_ERR_INVALID_ARG, "NULL argument or no frames");
+  for (int i = 0; i < nframes; ++i) {
+    int st = validate(frames[i], i);
+    if (st != SBS_OK) return st;
+  }
+  int lead = 0;
+  while (lead < nframes - 1 && frames[lead].n == 0) ++lead;
+  Plan p = choose_plan(frames, nframes, frames[lead]);   // as a batched call would plan it
+  plan->cols_per_lane = p.cpl;
+  plan->chunk = p.chunk;
+  plan->tile_rows = p.ty;
+  plan->waves_per_cu = p.wpc;
+  return SBS_OK;
+}
+
 int sbs_load_tuning(const char* cache_path) {
   if (!cache_path) return fail(SBS_ERR_INVALID_ARG, "NULL path");
   return load_cache(cache_path);
@@ -645,6 +670,8 @@ int sbs_tune(const sbs_frame* frames, int32_t nframes, const char* cache_path) {
   }
   int st = device_check(nullptr);
   if (st != SBS_OK) return st;
+  int lead = 0;   // the key frame, as a batched call picks it
+  while (lead < nframes - 1 && frames[lead].n == 0) ++lead;
   bool was_forced;
   Plan was_plan;
   {
@@ -690,7 +717,7 @@ done:
     std::lock_guard<std::mutex> lk(g_mu);
     g_forced = was_forced;
     g_forced_plan = was_plan;
-    if (st == SBS_OK) g_tuned[plan_key(frames[0])] = best;
+    if (st == SBS_OK) g_tuned[plan_key(frames[lead], nframes)] = best;
   }
   if (st != SBS_OK) return st;
   if (cache_path) return save_cache(cache_path);

@@ -527,27 +527,38 @@ def test_left_image_read_in_place(torch, sbs):
 
 def test_benchmark_configuration_sampled(torch, sbs):
     """Full-size frames of the benchmark's video (4096x2304 RGB, block 31,
-    dmax 127, per-frame boundary fractions) through the batched persistent
-    launch with the plan the benchmark runs (16-disparity chunks, 128-row
-    tiles, 16 workgroups per CU; twelve frames already give the default plan
-    that choice): every frame checked against the oracle on sampled entries,
-    including each frame's first and last list entries."""
+    dmax 127) with the benchmark's lists: each frame's refined boundary set
+    from the device front end (K = 4, open/close, components >= 50 px, border
+    columns) cut to its per-frame fraction. Frame 0's list equals the
+    oracle's front end. The batched persistent launch runs with the plan the
+    benchmark's default comes to (16-disparity chunks, 128-row tiles, 16
+    workgroups per CU), with the library's default for twelve frames, and
+    with an autotuned plan: every frame is checked against the oracle on
+    sampled entries (each frame's first and last entries included), and
+    frame 0's whole list (about 1.7 M pixels, 2.2e8 evaluations) against the
+    oracle in full."""
     spec = scenes.PRESETS["uhd_video"]
     F = 12
-    left, right, lists = _video(spec, F)
-    frames, keep = [], []
+    fr = scenes.video_fracs(spec, 0, F)
+    left, right, _ = scenes.make_video(spec, 0, F, with_lists=False)
+    frames, keep, lists = [], [], []
     for t in range(F):
-        Ld, Rd, Id = dev(torch, left[t]), dev(torch, right[t]), dev(torch, lists[t].view(np.int32))
+        Ld, Rd = dev(torch, left[t]), dev(torch, right[t])
+        Id = sbs.boundaries(Ld, K=4, mode=0, min_cc=50, frac=float(fr[t]), seed=spec.seed + t).clone()
         keep += [Ld, Rd, Id]
+        lists.append(Id.cpu().numpy().view(np.uint32))
         frames.append((Ld, Rd, Id, spec.block, spec.dmax))
+    exp0_list = oracle.boundaries(left[0], K=4, mode=0, min_cc=50, frac=float(fr[0]), seed=spec.seed)
+    assert np.array_equal(lists[0], exp0_list), "frame 0: device front-end list differs from the oracle's"
     rng = np.random.default_rng(17)
     try:
-        for forced in (True, False):
-            if forced:
+        for plan in ("benchmark", "default", "tuned"):
+            sbs.set_plan()
+            if plan == "benchmark":
                 sbs.set_plan(cols_per_lane=4, chunk=16, tile_rows=128, waves_per_cu=16)
-            else:
-                sbs.set_plan()
             runner = sbs.BatchRunner(frames)
+            if plan == "tuned":
+                runner.tune()
             runner.run()
             torch.cuda.synchronize()
             for t in range(F):
@@ -555,7 +566,12 @@ def test_benchmark_configuration_sampled(torch, sbs):
                 pick = np.unique(np.concatenate([rng.choice(n, 250, replace=False), [0, n - 1]]))
                 exp = oracle.sad(left[t], right[t], lists[t][pick], spec.block, spec.dmax)
                 got = (runner.disp[t].cpu().numpy()[pick], runner.cost[t].cpu().numpy().view(np.uint32)[pick])
-                assert_parity(got, exp, f"frame {t} ({'benchmark plan' if forced else 'default plan'})")
+                assert_parity(got, exp, f"frame {t} ({plan} plan {runner.plan()})")
+            if plan == "benchmark":
+                exp = oracle.sad(left[0], right[0], lists[0], spec.block, spec.dmax)
+                got = (runner.disp[0].cpu().numpy(), runner.cost[0].cpu().numpy().view(np.uint32))
+                assert_parity(got, exp, f"frame 0, whole list of {lists[0].size} entries (benchmark plan)")
             assert runner.check_indices() == 0
+            del runner
     finally:
         sbs.set_plan()

@@ -25,11 +25,14 @@ def test_tune_cache_roundtrip(tmp_path):
     cache = tmp_path / "tuning.json"
     sbs.tune(list(runner.desc), str(cache))
     data = json.loads(cache.read_text())
-    assert len(data) == 1
-    (key, plan), = data.items()
-    assert key.startswith("gfx950/700x400x3/b31/d127/") and plan["chunk"] in (8, 16)
+    # the cache holds every plan tuned in this process; this batch's key ends
+    # with its frame count rounded up to a power of two
+    mine = {k: v for k, v in data.items() if k.startswith("gfx950/700x400x3/b31/d127/")}
+    assert len(mine) == 1
+    (key, plan), = mine.items()
+    assert key.endswith("/nf4") and plan["chunk"] in (8, 16)
     sbs.load_tuning(str(cache))
-    assert sbs.get_plan(runner.desc[0]) == plan
+    assert runner.plan() == plan
     for d in runner.disp:
         d.fill_(0)
     runner.run()
