@@ -80,6 +80,29 @@ int sbs_sad_disparity(const uint8_t* left, const uint8_t* right, int32_t W, int3
                       int32_t dmax, uint8_t* out_disp, uint32_t* out_cost, void* workspace,
                       size_t workspace_bytes, void* stream);
 
+/*
+ * For callers that cannot allocate (code under stream capture, serving loops
+ * and harnesses that forbid allocation): sbs_sad_disparity for one frame,
+ * computed in a fixed scratch array of SBS_SCRATCH_BYTES that the library
+ * holds in device memory (one copy per GPU, from the library's first use on
+ * that GPU until the process ends). The call allocates nothing and takes no
+ * workspace; arguments, results and errors are those of sbs_sad_disparity,
+ * plus SBS_ERR_WORKSPACE when the frame needs more than the scratch holds
+ * (sbs_workspace_bytes for the frame > SBS_SCRATCH_BYTES; a 4096x2304 RGB
+ * frame at block 31, dmax 127 and up to 100% listed pixels fits).
+ * The first call on a device looks up that device's scratch address and
+ * clears its header on `stream`; make that first call outside stream capture.
+ * Every call on one GPU uses the same scratch: calls whose work overlaps on
+ * one GPU (different streams, or host threads without ordering) race and
+ * give wrong results; order them on one stream. Out-of-range indices are
+ * answered with 255 / 0xFFFFFFFF as in sbs_sad_disparity; sbs_check_indices
+ * does not read the scratch's error word.
+ */
+#define SBS_SCRATCH_BYTES (160u << 20)
+int sbs_sad_disparity_noalloc(const uint8_t* left, const uint8_t* right, int32_t W, int32_t H, int32_t C,
+                              int64_t pitch_bytes, const uint32_t* boundary_idx, int64_t n, int32_t block,
+                              int32_t dmax, uint8_t* out_disp, uint32_t* out_cost, void* stream);
+
 /* One frame of a batch. Field meanings as for sbs_sad_disparity. Host memory. */
 typedef struct {
   const uint8_t* left;

@@ -45,7 +45,8 @@ class SbsError(RuntimeError):
 def build() -> str:
     """Compile libsbs.so for gfx950 (always recompiles)."""
     srcs = [os.path.join(_CSRC, "sbs_kernels.hip"), os.path.join(_CSRC, "sbs_api.hip"),
-            os.path.join(_CSRC, "sbs_post.hip"), os.path.join(_CSRC, "sbs_front.hip")]
+            os.path.join(_CSRC, "sbs_post.hip"), os.path.join(_CSRC, "sbs_front.hip"),
+            os.path.join(_CSRC, "sbs_noalloc.hip")]
     cmd = [HIPCC, *HIP_FLAGS, *srcs, "-o", _SO + ".tmp"]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
@@ -83,6 +84,7 @@ def lib():
     FP = ctypes.POINTER(Frame)
     sig = {
         "sbs_sad_disparity": ([V, V, I32, I32, I32, I64, V, I64, I32, I32, V, V, V, SZ, V], ctypes.c_int),
+        "sbs_sad_disparity_noalloc": ([V, V, I32, I32, I32, I64, V, I64, I32, I32, V, V, V], ctypes.c_int),
         "sbs_sad_disparity_ref": ([V, V, I32, I32, I32, I64, V, I64, I32, I32, V, V, V], ctypes.c_int),
         "sbs_workspace_bytes": ([FP, I32], SZ),
         "sbs_sad_disparity_batched": ([FP, I32, V, SZ, V], ctypes.c_int),
@@ -188,6 +190,24 @@ def sad_disparity(left, right, idx, block: int, dmax: int, out=None, cost=None, 
                                    f.block, f.dmax, f.out_disp, f.out_cost, ws_ptr, ws_bytes,
                                    _stream_handle(stream)))
     return out, cost
+
+
+def sad_disparity_noalloc(left, right, idx, block: int, dmax: int, out=None, cost=None, stream=None):
+    """sad_disparity in the library's fixed device scratch (no allocation by
+    the library; ``out``/``cost`` are allocated here when not given)."""
+    torch = _torch()
+    n = idx.numel()
+    if out is None:
+        out = torch.empty(n, dtype=torch.uint8, device=left.device)
+    if cost is None:
+        cost = torch.empty(n, dtype=torch.int32, device=left.device)
+    f = make_frame(left, right, idx, block, dmax, out, cost)
+    _check(lib().sbs_sad_disparity_noalloc(f.left, f.right, f.W, f.H, f.C, f.pitch_bytes, f.boundary_idx, f.n,
+                                           f.block, f.dmax, f.out_disp, f.out_cost, _stream_handle(stream)))
+    return out, cost
+
+
+SCRATCH_BYTES = 160 << 20
 
 
 def sad_disparity_ref(left, right, idx, block: int, dmax: int, out=None, cost=None, stream=None):

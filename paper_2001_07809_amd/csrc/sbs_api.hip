@@ -323,7 +323,8 @@ void timing_end(hipStream_t s, hipEvent_t a) {
 // ---------------------------------------------------------------- run
 enum Mode { kSingle = 0, kBatched = 1, kPerFrame = 2 };
 
-int run(const sbs_frame* frames, int nframes, void* workspace, size_t ws_bytes, hipStream_t s, Mode mode) {
+int run(const sbs_frame* frames, int nframes, void* workspace, size_t ws_bytes, hipStream_t s, Mode mode,
+        bool timed = true) {
   if (nframes < 0 || (nframes > 0 && !frames)) return fail(SBS_ERR_INVALID_ARG, "bad frame array");
   for (int i = 0; i < nframes; ++i) {
     int st = validate(frames[i], i);
@@ -422,8 +423,8 @@ int run(const sbs_frame* frames, int nframes, void* workspace, size_t ws_bytes, 
       if (frames[i].n == 0) continue;
       e = launch_prologue(table, i, 1, host[(size_t)i].ph, frames[i].H * host[(size_t)i].tpw, hdr, s);
       if (e != hipSuccess) return hip_fail(e, "prologue");
-      hipEvent_t ev;
-      timing_begin(s, &ev);
+      hipEvent_t ev = nullptr;
+      if (timed) timing_begin(s, &ev);
       e = launch_tile_grid(table, i, host[(size_t)i].nitems, plan.chunk, cpl[(size_t)i] == 8, s);
       timing_end(s, ev);
       if (e != hipSuccess) return hip_fail(e, "tile kernel");
@@ -437,8 +438,8 @@ int run(const sbs_frame* frames, int nframes, void* workspace, size_t ws_bytes, 
     // wide launches hold at most 12 wavefronts per CU (3 per SIMD)
     int64_t grid = (int64_t)cus * (wide ? std::min(plan.wpc, 12) : plan.wpc);
     if (grid > items) grid = items;
-    hipEvent_t ev;
-    timing_begin(s, &ev);
+    hipEvent_t ev = nullptr;
+    if (timed) timing_begin(s, &ev);
     e = launch_tile_persistent(table, nframes, qt, plan.chunk, wide, (int)std::max<int64_t>(grid, 1), hdr, s);
     timing_end(s, ev);
     if (e != hipSuccess) return hip_fail(e, "persistent tile kernel");
@@ -517,6 +518,18 @@ bool plan_valid(const Plan& p) {
 }
 
 }  // namespace
+
+namespace sbs {
+// For the fixed-scratch entry point (sbs_noalloc.hip): checks, workspace
+// bound and the single-frame run into a caller-given buffer, without kernel
+// timing (which creates events).
+int validate_frame(const sbs_frame& f) { return validate(f, 0); }
+size_t workspace_bound(const sbs_frame& f) { return total_bytes(&f, 1); }
+int run_single_into(const sbs_frame& f, void* workspace, size_t ws_bytes, hipStream_t s) {
+  return run(&f, 1, workspace, ws_bytes, s, kSingle, false);
+}
+int fail_message(int status, const char* msg) { return fail(status, "%s", msg); }
+}  // namespace sbs
 
 extern "C" {
 

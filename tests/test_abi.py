@@ -96,3 +96,16 @@ def test_front_end_workspace_bytes():
     assert lib.sbs_boundaries_workspace_bytes(0, 5) == 0
     assert lib.sbs_boundaries_workspace_bytes(100, 50) >= 100 * 50 * 13
     assert lib.sbs_lightness(None, 4, 4, 3, 12, None, None) == 1
+
+
+def test_noalloc_rejects_frames_beyond_the_scratch_on_host():
+    # 8192x8192 RGB at block 31, dmax 127 needs more workspace than the fixed
+    # scratch holds: refused before any device work.
+    lib = sbs.lib()
+    p = ctypes.c_void_p(1)
+    st = lib.sbs_sad_disparity_noalloc(p, p, 8192, 8192, 3, 8192 * 3, p, 1 << 20, 31, 127, p, None, None)
+    assert st == 3
+    assert "scratch" in lib.sbs_last_error().decode()
+    # invalid arguments still come first
+    assert lib.sbs_sad_disparity_noalloc(p, p, 0, 8, 1, 8, p, 1, 3, 2, p, None, None) == 1
+    assert lib.sbs_sad_disparity_noalloc(None, None, 8, 8, 1, 8, None, 0, 3, 2, None, None, None) == 0
