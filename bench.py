@@ -96,6 +96,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the per-frame / graph comparisons")
     ap.add_argument("--no-tune", action="store_true", help="run the default plan (no autotuning before timing)")
+    ap.add_argument("--plan", default="", metavar="CHUNK,ROWS,WPC",
+                    help="force a plan (disparities per wavefront, tile rows, wavefronts per CU; implies --no-tune)")
     ap.add_argument("--no-contour", action="store_true",
                     help="skip the secondary measurement on the generator's contour-band lists")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target oracle time for the CPU sample")
@@ -143,6 +145,10 @@ def main():
     sbs.lib()
     if args.tuning and os.path.exists(args.tuning):
         sbs.load_tuning(args.tuning)
+    if args.plan:
+        chunk, rows, wpc = (int(v) for v in args.plan.split(","))
+        sbs.set_plan(chunk=chunk, tile_rows=rows, waves_per_cu=wpc)
+        args.no_tune = True
     if args.serve:
         serve_main(args)
         return
@@ -392,7 +398,6 @@ def measure(args, sbs, torch, np, spec, Ld, Rd, Id, tune, compare):
 
 
 SERVE_CLASSES = [("serve_vga", 1000), ("serve_fhd", 600), ("serve_uhd", 400)]
-SERVE_FRACS = (0.12, 0.16, 0.20, 0.24)
 
 
 def single_main(args):
@@ -540,13 +545,18 @@ def serve_main(args):
     import numpy as np
     import torch
 
+    import paper_2001_07809_amd as sbs
     import scenes
     from paper_2001_07809_amd.serve import Request, Server
 
     dev = torch.device("cuda:0")
     scale = args.serve_requests / 2000.0
     counts = [(name, max(1, int(round(c * scale)))) for name, c in SERVE_CLASSES]
-    # Pools: 8 scenes per class, each with lists at 4 fractions, resident on the GPU.
+    # Pools: 8 scenes per class, resident on the GPU (reused round-robin; this
+    # bounds host-side scene generation). Every request draws its own boundary
+    # fraction from U[0.12, 0.24]; with ready lists, each request's list is
+    # made on the device by the front end before the trace (K = 4, open/close,
+    # components >= 50 px, fraction control) and stays resident.
     t0 = time.time()
     pools = {}
     for ci, (name, _) in enumerate(counts):
@@ -555,10 +565,7 @@ def serve_main(args):
         for s_i in range(8):
             sp = scenes.scaled(spec, seed=spec.seed + 1000 * ci + s_i)
             f = scenes.make_frame(sp)
-            Ld, Rd = torch.from_numpy(f.left).to(dev), torch.from_numpy(f.right).to(dev)
-            lists = [torch.from_numpy(scenes.contour_list(f.rid, fr, sp.seed).view(np.int32)).to(dev)
-                     for fr in SERVE_FRACS]
-            entries.append((Ld, Rd, lists))
+            entries.append((torch.from_numpy(f.left).to(dev), torch.from_numpy(f.right).to(dev)))
         pools[name] = (spec, entries)
     torch.cuda.synchronize()
     log(f"serving pools ready in {time.time() - t0:.1f}s")
@@ -566,20 +573,31 @@ def serve_main(args):
     rng = np.random.default_rng(105)
     kinds = np.concatenate([np.full(c, i) for i, (_, c) in enumerate(counts)])
     rng.shuffle(kinds)
-    picks = rng.integers(0, len(SERVE_FRACS), kinds.size)
+    req_fracs = rng.uniform(0.12, 0.24, kinds.size)
+    used = [0, 0, 0]
+    req_frames = []
+    for i, k in enumerate(kinds):
+        name = counts[k][0]
+        spec, entries = pools[name]
+        Ld, Rd = entries[used[k] % 8]
+        used[k] += 1
+        lst = None
+        if not args.serve_raw:
+            lst = sbs.boundaries(Ld, K=FRONT_K, mode=0, min_cc=FRONT_MIN_CC, frac=float(req_fracs[i]),
+                                 seed=spec.seed + i).clone()
+        req_frames.append((name, spec, Ld, Rd, lst))
+    torch.cuda.synchronize()
+    log(f"{kinds.size} request lists ready in {time.time() - t0:.1f}s")
 
     def make_requests(arrivals):
-        reqs, used = [], [0, 0, 0]
-        for i, (k, fpick) in enumerate(zip(kinds[:len(arrivals)], picks[:len(arrivals)])):
-            name = counts[k][0]
-            spec, entries = pools[name]
-            Ld, Rd, lists = entries[used[k] % 8]
-            used[k] += 1
+        reqs = []
+        for i in range(len(arrivals)):
+            name, spec, Ld, Rd, lst = req_frames[i]
             if args.serve_raw:
                 reqs.append(Request(i, Ld, Rd, None, spec.block, spec.dmax, float(arrivals[i]), name,
-                                    frac=SERVE_FRACS[fpick], K=4, seed=spec.seed + i))
+                                    frac=float(req_fracs[i]), K=FRONT_K, seed=spec.seed + i))
             else:
-                reqs.append(Request(i, Ld, Rd, lists[fpick], spec.block, spec.dmax, float(arrivals[i]), name))
+                reqs.append(Request(i, Ld, Rd, lst, spec.block, spec.dmax, float(arrivals[i]), name))
         return reqs
 
     free, total = torch.cuda.mem_get_info()
@@ -599,9 +617,10 @@ def serve_main(args):
         runs.append(st)
         log(f"lambda {lam:.1f}/s: p50 {st['p50_ms']:.2f} ms p99 {st['p99_ms']:.2f} ms {st['frames_per_s']:.1f} frames/s")
     evals = 0
-    for k, fpick in zip(kinds, picks):
-        spec, entries = pools[counts[k][0]]
-        evals += entries[0][2][fpick].numel() * (spec.dmax + 1)
+    for i, (name, spec, Ld, Rd, lst) in enumerate(req_frames):
+        N = spec.W * spec.H
+        n = lst.numel() if lst is not None else min(N, int(np.floor(req_fracs[i] * N + 0.5)))
+        evals += n * (spec.dmax + 1)
     rec = {
         "metric": "serving: frames/s and p50/p99 latency (continuous batching)",
         "value": lam_sat,
@@ -611,8 +630,9 @@ def serve_main(args):
         "data": "synthetic",
         "dtype": "u8",
         "config": {"workload": f"{kinds.size} requests, mix " + "/".join(f"{c} {n}" for n, c in counts)
-                   + ("; raw frames: lists from the device front end (K=4, open/close, CC>=50, fraction control)"
-                      if args.serve_raw else "; pools of 8 resident scenes x 4 list fractions per class"),
+                   + "; 8 resident scenes per class reused round-robin; per-request boundary fraction "
+                     "U[0.12, 0.24]; lists from the device front end (K=4, open/close, CC>=50, fraction control)"
+                   + (", made by the server per request" if args.serve_raw else ", made before the trace"),
                    "classes": {n: {"W": pools[n][0].W, "H": pools[n][0].H, "block": pools[n][0].block,
                                    "dmax": pools[n][0].dmax} for n, _ in counts},
                    "budget_bytes": budget, "max_inflight_batches": 2, "max_batch": 64},

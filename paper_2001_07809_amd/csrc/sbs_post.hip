@@ -108,10 +108,12 @@ __global__ __launch_bounds__(kRowThreads) void k_rc_fill(const int32_t* slot, co
 // short walks fill the chip better than fewer long ones; more for images
 // over 1M rows so the segments fit the grid), one thread per
 // (column, segment): k_rc_colseg records each segment's topmost and
-// bottommost determined value, then k_rc_peek takes the nearest determined
-// values above and below the segment from those records and resolves the
-// segment's rows in two passes (threads of a block cover adjacent columns,
-// so every row access is coalesced).
+// bottommost determined value, k_rc_segscan turns those records into the
+// nearest determined value above and below each segment (one pass down and
+// one up each column, so a column with few determined pixels costs O(nseg),
+// not O(nseg^2)), and k_rc_peek resolves the segment's rows in two passes
+// (threads of a block cover adjacent columns, so every row access is
+// coalesced).
 constexpr int kColSeg = 16;
 
 __global__ __launch_bounds__(256) void k_rc_colseg(const int16_t* f, int32_t W, int32_t H, int32_t seglen,
@@ -132,18 +134,38 @@ __global__ __launch_bounds__(256) void k_rc_colseg(const int16_t* f, int32_t W, 
   seg_last[(int64_t)sg * W + x] = last;
 }
 
+// In place: seg_last[sg] becomes the nearest determined value above segment
+// sg (the last one of the segments before it), seg_first[sg] the nearest
+// below it (the first one of the segments after it); -1 where none.
+__global__ __launch_bounds__(256) void k_rc_segscan(int32_t W, int32_t nseg, int16_t* seg_first, int16_t* seg_last) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= W) return;
+  int16_t carry = -1;
+  for (int sg = 0; sg < nseg; ++sg) {
+    const int64_t q = (int64_t)sg * W + x;
+    const int16_t v = seg_last[q];
+    seg_last[q] = carry;
+    if (v >= 0) carry = v;
+  }
+  carry = -1;
+  for (int sg = nseg - 1; sg >= 0; --sg) {
+    const int64_t q = (int64_t)sg * W + x;
+    const int16_t v = seg_first[q];
+    seg_first[q] = carry;
+    if (v >= 0) carry = v;
+  }
+}
+
 __global__ __launch_bounds__(256) void k_rc_peek(const int16_t* f, int32_t W, int32_t H, int32_t threshold,
-                                                 int32_t seglen, const int16_t* seg_first, const int16_t* seg_last,
-                                                 int32_t nseg, int16_t* up, uint8_t* out) {
+                                                 int32_t seglen, const int16_t* above_seg, const int16_t* below_seg,
+                                                 int16_t* up, uint8_t* out) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int sg = blockIdx.y;
   if (x >= W) return;
   const int y0 = sg * seglen, y1 = min(y0 + seglen, H);
-  // nearest determined value above the segment, and below it
-  int16_t last = -1;
-  for (int t = sg - 1; t >= 0 && last < 0; --t) last = seg_last[(int64_t)t * W + x];
-  int16_t below = -1;
-  for (int t = sg + 1; t < nseg && below < 0; ++t) below = seg_first[(int64_t)t * W + x];
+  // nearest determined value above the segment, and below it (k_rc_segscan)
+  int16_t last = above_seg[(int64_t)sg * W + x];
+  int16_t below = below_seg[(int64_t)sg * W + x];
   for (int y = y0; y < y1; ++y) {
     const int16_t v = f[(int64_t)y * W + x];
     up[(int64_t)y * W + x] = last;
@@ -221,75 +243,162 @@ __global__ __launch_bounds__(256) void k_blur_v(const uint8_t* img, const uint8_
   }
 }
 
-// The same blur in one pass per tile of kBlurTX x ty pixels (ty = 16: more
-// blocks fit a CU than with taller tiles, which measured slower; radius up to
-// kBlurTileRad, a compile-time constant per instance so the tap loops unroll): the tile's
-// clamped input rows and columns go to LDS, the horizontal pass runs over the
-// tile's rows plus the vertical halo into LDS, and the vertical pass reads it
-// from there. Each sum runs over the taps in the same order as in the two
-// kernels above, so the results are the same floats; only the intermediate
-// image no longer travels through HBM.
-constexpr int kBlurTX = 64, kBlurTileRad = 14;   // LDS < 48 KB per block at 16 rows
+// The same blur in one pass per tile of kBlurTX x kBlurTY pixels (radius up
+// to kBlurTileRad, a compile-time constant per instance so the tap loops
+// unroll):
+//  - the tile's in-focus flags first: a tile whose every pixel is in focus
+//    only converts its pixels (no input tile, no sums);
+//  - the clamped input rows and columns go to LDS, as aligned dword loads
+//    where the image rows start on 4-byte boundaries and the tile does not
+//    reach past a side edge, byte by byte with clamped columns otherwise;
+//  - the horizontal pass runs over the tile's rows plus the vertical halo,
+//    each thread 8 adjacent outputs of one row and channel from 8 + 2 RAD
+//    input bytes (lanes over rows and channels: no LDS bank conflicts), into
+//    an LDS float tile with padded rows;
+//  - the vertical pass, each thread 8 rows of one column and channel from
+//    8 + 2 RAD horizontal sums (lanes over columns: coalesced stores).
+// Each sum runs over the taps in the same order as in the two kernels
+// above, so the results are the same floats; the intermediate image never
+// travels through HBM.
+constexpr int kBlurTX = 64, kBlurTY = 32, kBlurTileRad = 14;
+constexpr int kBlurRun = 8;   // outputs per thread and pass
+
+template <int C, int RAD>
+struct BlurTileGeom {
+  static constexpr int rows = kBlurTY + 2 * RAD;              // image rows y0 - RAD ..
+  static constexpr int cols = kBlurTX + 2 * RAD;              // image columns x0 - RAD ..
+  static constexpr int rowb = cols * C;                       // input bytes per row
+  static constexpr int rowbp = (rowb + 3) & ~3;
+  static constexpr int hrow = kBlurTX * C + 1;                // floats per horizontal-sum row (padded)
+  static constexpr size_t lds = (size_t)rows * hrow * 4 + (size_t)rows * rowbp + kBlurTX * kBlurTY;
+};
 
 template <int C, int RAD>
 __global__ __launch_bounds__(256) void k_blur_tile(const uint8_t* img, const uint8_t* depth, int32_t W, int32_t H,
-                                                   int64_t pitch, int32_t ty, BlurArgs a, float* out) {
+                                                   int64_t pitch, int32_t aligned, BlurArgs a, float* out) {
+  using G = BlurTileGeom<C, RAD>;
   extern __shared__ __attribute__((aligned(16))) unsigned char blur_lds[];
-  constexpr int cols = kBlurTX + 2 * RAD, rowb = cols * C;   // input tile: image columns x0 - RAD ..
-  const int x0 = blockIdx.x * kBlurTX, y0 = blockIdx.y * ty;
-  const int rows = ty + 2 * RAD;                               // image rows y0 - RAD ..
-  float* hb = (float*)blur_lds;                                // rows x kBlurTX x C horizontal sums
-  uint8_t* ib = blur_lds + (size_t)rows * kBlurTX * C * 4;     // rows x cols x C input bytes
-#pragma unroll 8
-  for (int b = threadIdx.x; b < rows * rowb; b += 256) {
-    const int r = b / rowb, jc = b - r * rowb, j = jc / C;
-    const int yy = min(max(y0 - RAD + r, 0), H - 1), xx = min(max(x0 - RAD + j, 0), W - 1);
-    ib[b] = img[(int64_t)yy * pitch + (int64_t)xx * C + (jc - j * C)];
-  }
-  __syncthreads();
-#pragma unroll 2
-  for (int i = threadIdx.x; i < rows * kBlurTX * C; i += 256) {
-    const int r = i / (kBlurTX * C), xc = i - r * (kBlurTX * C);
-    const uint8_t* src = ib + r * rowb + xc;   // tap k at src[(k + RAD) * C]
-    float s = 0.f;
-#pragma unroll
-    for (int k = -RAD; k <= RAD; ++k) s += a.g[k + RAD] * (float)src[(k + RAD) * C];
-    hb[i] = s;
-  }
-  __syncthreads();
-#pragma unroll 2
-  for (int i = threadIdx.x; i < ty * kBlurTX * C; i += 256) {
-    const int y = i / (kBlurTX * C), xc = i - y * (kBlurTX * C);
-    const int x = xc / C;
-    if (y0 + y >= H || x0 + x >= W) continue;
-    const int64_t px = (int64_t)(y0 + y) * W + x0 + x;
-    const int dv = depth[px];
-    bool keep = false;
-    for (int t = 0; t < a.nranges; ++t) keep |= (dv >= a.lo[t] && dv <= a.hi[t]);
-    float v;
-    if (keep) {
-      v = (float)ib[(y + RAD) * rowb + (x + RAD) * C + (xc - x * C)];
-    } else {
-      const float* col = hb + xc;   // row y + RAD + k at col[(y + RAD + k) * kBlurTX * C]
-      v = 0.f;
-#pragma unroll
-      for (int k = -RAD; k <= RAD; ++k) v += a.g[k + RAD] * col[(y + RAD + k) * kBlurTX * C];
+  float* hb = (float*)blur_lds;                                          // rows x hrow
+  uint8_t* ib = blur_lds + (size_t)G::rows * G::hrow * 4;               // rows x rowbp input bytes
+  uint8_t* keep = ib + (size_t)G::rows * G::rowbp;                       // kBlurTY x kBlurTX in-focus flags
+  const int x0 = blockIdx.x * kBlurTX, y0 = blockIdx.y * kBlurTY;
+  const int tid = threadIdx.x;
+
+  // in-focus flags of the tile's pixels (1 outside the image: nothing to do there)
+  bool need = false;
+  for (int i = tid; i < kBlurTX * kBlurTY; i += 256) {
+    const int y = i / kBlurTX, x = i - y * kBlurTX;
+    bool k = true;
+    if (y0 + y < H && x0 + x < W) {
+      const int dv = depth[(int64_t)(y0 + y) * W + x0 + x];
+      k = false;
+      for (int t = 0; t < a.nranges; ++t) k |= (dv >= a.lo[t] && dv <= a.hi[t]);
     }
-    out[px * C + (xc - x * C)] = v;
+    keep[i] = k ? 1 : 0;
+    need |= !k;
+  }
+  if (!__syncthreads_or(need)) {
+    // every pixel in focus: the image itself, as floats
+    for (int i = tid; i < kBlurTY * kBlurTX * C; i += 256) {
+      const int y = i / (kBlurTX * C), xc = i - y * (kBlurTX * C);
+      if (y0 + y < H && x0 * C + xc < W * C)
+        out[((int64_t)(y0 + y) * W + x0) * C + xc] = (float)img[(int64_t)(y0 + y) * pitch + (int64_t)x0 * C + xc];
+    }
+    return;
+  }
+
+  // input tile: image rows y0 - RAD .. (clamped), columns x0 - RAD .. (clamped)
+  if (aligned && x0 - RAD >= 0 && x0 + kBlurTX + RAD <= W) {
+    const int s0 = (x0 - RAD) * C;                  // first byte of a tile row within its image row
+    const int q0 = s0 & ~3;
+    constexpr int ndw = (G::rowb + 3 + 3) / 4;      // dwords covering the row's bytes
+    const int rowend = W * C;
+    for (int i = tid; i < G::rows * ndw; i += 256) {
+      const int r = i / ndw, w = i - r * ndw;
+      const int yy = min(max(y0 - RAD + r, 0), H - 1);
+      const uint8_t* row = img + (int64_t)yy * pitch;
+      const int q = q0 + 4 * w;
+      uint32_t v = 0u;
+      if (q + 3 < rowend) {
+        v = *(const uint32_t*)(row + q);
+      } else {
+        for (int j = 0; j < 4; ++j)
+          if (q + j < rowend) v |= (uint32_t)row[q + j] << (8 * j);
+      }
+      for (int j = 0; j < 4; ++j) {
+        const int b = q + j - s0;
+        if (b >= 0 && b < G::rowb) ib[r * G::rowbp + b] = (uint8_t)(v >> (8 * j));
+      }
+    }
+  } else {
+    for (int b = tid; b < G::rows * G::rowb; b += 256) {
+      const int r = b / G::rowb, jc = b - r * G::rowb, j = jc / C;
+      const int yy = min(max(y0 - RAD + r, 0), H - 1), xx = min(max(x0 - RAD + j, 0), W - 1);
+      ib[r * G::rowbp + jc] = img[(int64_t)yy * pitch + (int64_t)xx * C + (jc - j * C)];
+    }
+  }
+  __syncthreads();
+
+  // horizontal pass: item = (run of 8 columns, row, channel), rows and
+  // channels varying fastest across lanes
+  constexpr int hitems = (kBlurTX / kBlurRun) * G::rows * C;
+  for (int i = tid; i < hitems; i += 256) {
+    const int run = i / (G::rows * C), rc = i - run * (G::rows * C);
+    const int r = rc / C, c = rc - r * C;
+    const uint8_t* src = ib + r * G::rowbp + run * kBlurRun * C + c;   // column run*8 + j - RAD at src[j * C]
+    float v[kBlurRun + 2 * RAD];
+#pragma unroll
+    for (int j = 0; j < kBlurRun + 2 * RAD; ++j) v[j] = (float)src[j * C];
+    float* dst = hb + r * G::hrow + run * kBlurRun * C + c;
+#pragma unroll
+    for (int o = 0; o < kBlurRun; ++o) {
+      float s = 0.f;
+#pragma unroll
+      for (int k = -RAD; k <= RAD; ++k) s += a.g[k + RAD] * v[o + k + RAD];
+      dst[o * C] = s;
+    }
+  }
+  __syncthreads();
+
+  // vertical pass: item = (run of 8 rows, column x channel), columns varying fastest
+  constexpr int vitems = (kBlurTY / kBlurRun) * kBlurTX * C;
+  for (int i = tid; i < vitems; i += 256) {
+    const int run = i / (kBlurTX * C), xc = i - run * (kBlurTX * C);
+    const int x = xc / C;
+    if (x0 + x >= W) continue;
+    const float* col = hb + run * kBlurRun * G::hrow + xc;   // row run*8 + j - RAD (tile rows) at col[j * hrow]
+    float v[kBlurRun + 2 * RAD];
+#pragma unroll
+    for (int j = 0; j < kBlurRun + 2 * RAD; ++j) v[j] = col[j * G::hrow];
+#pragma unroll
+    for (int o = 0; o < kBlurRun; ++o) {
+      const int y = run * kBlurRun + o;
+      if (y0 + y >= H) break;
+      float s;
+      if (keep[y * kBlurTX + x]) {
+        s = (float)ib[(y + RAD) * G::rowbp + (x + RAD) * C + (xc - x * C)];
+      } else {
+        s = 0.f;
+#pragma unroll
+        for (int k = -RAD; k <= RAD; ++k) s += a.g[k + RAD] * v[o + k + RAD];
+      }
+      out[((int64_t)(y0 + y) * W + x0) * C + xc] = s;
+    }
   }
 }
 
 template <int C, int RAD>
-void launch_blur_tile(dim3 grid, size_t lds, hipStream_t s, const uint8_t* img, const uint8_t* depth, int32_t W,
-                      int32_t H, int64_t pitch, int32_t ty, const BlurArgs& a, float* out) {
-  hipLaunchKernelGGL((k_blur_tile<C, RAD>), grid, dim3(256), lds, s, img, depth, W, H, pitch, ty, a, out);
+void launch_blur_tile(dim3 grid, hipStream_t s, const uint8_t* img, const uint8_t* depth, int32_t W, int32_t H,
+                      int64_t pitch, int32_t aligned, const BlurArgs& a, float* out) {
+  constexpr size_t lds = BlurTileGeom<C, RAD>::lds;
+  hipLaunchKernelGGL((k_blur_tile<C, RAD>), grid, dim3(256), lds, s, img, depth, W, H, pitch, aligned, a, out);
 }
 
 template <int C, int... R>
-void blur_tile_dispatch(int rad, std::integer_sequence<int, R...>, dim3 grid, size_t lds, hipStream_t s,
-                        const uint8_t* img, const uint8_t* depth, int32_t W, int32_t H, int64_t pitch, int32_t ty,
-                        const BlurArgs& a, float* out) {
-  ((rad == R + 1 ? launch_blur_tile<C, R + 1>(grid, lds, s, img, depth, W, H, pitch, ty, a, out) : void()), ...);
+void blur_tile_dispatch(int rad, std::integer_sequence<int, R...>, dim3 grid, hipStream_t s, const uint8_t* img,
+                        const uint8_t* depth, int32_t W, int32_t H, int64_t pitch, int32_t aligned, const BlurArgs& a,
+                        float* out) {
+  ((rad == R + 1 ? launch_blur_tile<C, R + 1>(grid, s, img, depth, W, H, pitch, aligned, a, out) : void()), ...);
 }
 
 int fail(int st, const char* fmt, ...) {
@@ -339,8 +448,8 @@ int sbs_reconstruct(const uint32_t* idx, const uint8_t* disp, int64_t n, int32_t
   int16_t* seg_last = seg_first + (int64_t)nseg * W;
   const dim3 cg((W + 255) / 256, nseg);
   hipLaunchKernelGGL(k_rc_colseg, cg, dim3(256), 0, s, f, W, H, seglen, seg_first, seg_last);
-  hipLaunchKernelGGL(k_rc_peek, cg, dim3(256), 0, s, f, W, H, threshold, seglen, seg_first, seg_last, nseg, up,
-                     out_map);
+  hipLaunchKernelGGL(k_rc_segscan, dim3((W + 255) / 256), dim3(256), 0, s, W, nseg, seg_first, seg_last);
+  hipLaunchKernelGGL(k_rc_peek, cg, dim3(256), 0, s, f, W, H, threshold, seglen, seg_last, seg_first, up, out_map);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(SBS_ERR_HIP, "reconstruct: %s", hipGetErrorString(e));
   return SBS_OK;
@@ -373,13 +482,11 @@ int sbs_selective_blur(const uint8_t* img, int32_t W, int32_t H, int32_t C, int6
   hipStream_t s = (hipStream_t)stream;
   if (rad <= kBlurTileRad) {
     const int64_t tx = (W + kBlurTX - 1) / kBlurTX;
-    const int ty = 16;
-    const int rows = ty + 2 * rad, cols = kBlurTX + 2 * rad;
-    const size_t lds = (size_t)rows * kBlurTX * C * 4 + (size_t)rows * cols * C;
-    const dim3 grid((unsigned)tx, (unsigned)((H + ty - 1) / ty));
+    const dim3 grid((unsigned)tx, (unsigned)((H + kBlurTY - 1) / kBlurTY));
+    const int32_t aligned = (((uintptr_t)img | (uintptr_t)pitch) & 3) == 0 ? 1 : 0;
     const auto radii = std::make_integer_sequence<int, kBlurTileRad>{};
-    if (C == 3) blur_tile_dispatch<3>(rad, radii, grid, lds, s, img, depth, W, H, pitch, ty, a, out);
-    else blur_tile_dispatch<1>(rad, radii, grid, lds, s, img, depth, W, H, pitch, ty, a, out);
+    if (C == 3) blur_tile_dispatch<3>(rad, radii, grid, s, img, depth, W, H, pitch, aligned, a, out);
+    else blur_tile_dispatch<1>(rad, radii, grid, s, img, depth, W, H, pitch, aligned, a, out);
   } else {
     float* tmp = (float*)workspace;
     hipLaunchKernelGGL(k_blur_h, dim3(2048), dim3(256), 0, s, img, W, H, C, pitch, a, tmp);

@@ -47,11 +47,14 @@ def test_reconstruct_unordered_duplicates_and_edges(mods):
 
 def test_reconstruct_sparse_columns_across_segments(mods):
     """Few listed pixels on tall images: the column pass resolves rows from
-    determined pixels many 64-row segments away, in columns with one, several
-    or no determined pixels; heights on and off a multiple of 64."""
+    determined pixels many 16-row segments away (the segment scan carries the
+    nearest value above and below across a thousand empty segments), in
+    columns with one, several or no determined pixels; heights on and off a
+    multiple of 16 and 64."""
     torch, sbs = mods
     rng = np.random.default_rng(6)
-    for (W, H, n) in [(130, 700, 40), (3, 1000, 5), (64, 128, 10), (257, 64, 7), (90, 1, 3), (77, 641, 400)]:
+    for (W, H, n) in [(130, 700, 40), (3, 1000, 5), (64, 128, 10), (257, 64, 7), (90, 1, 3), (77, 641, 400),
+                      (5, 20001, 6), (2, 9000, 1)]:
         idx = np.sort(rng.choice(W * H, n, replace=False)).astype(np.uint32)
         disp = rng.integers(0, 40, n).astype(np.uint8)
         for threshold in (0, 3):
@@ -94,3 +97,33 @@ def test_blur_pitched_rows_over_many_tiles(mods, sigma):
     torch.cuda.synchronize()
     np.testing.assert_allclose(got.cpu().numpy(), exp, atol=1e-3, rtol=0)
 
+
+
+@pytest.mark.parametrize("C,sigma", [(3, 2.0), (1, 1.2), (3, 4.6)])
+def test_blur_tiles_in_focus_and_aligned_rows(mods, C, sigma):
+    """Depth maps made of 64 x 32 blocks (the blur's tiles): whole tiles in
+    focus (their pixels converted only), whole tiles out of focus, and mixed
+    tiles; images with 4-byte-aligned rows wide enough for interior tiles
+    (read as aligned dwords) as well as the clamped edge tiles."""
+    torch, sbs = mods
+    rng = np.random.default_rng(13)
+    H, W = 200, 512
+    shape = (H, W) if C == 1 else (H, W, C)
+    img = rng.integers(0, 256, shape, dtype=np.uint8)
+    blocks = rng.integers(0, 3, ((H + 31) // 32, W // 64))
+    depth = np.empty((H, W), np.uint8)
+    for by in range(blocks.shape[0]):
+        for bx in range(blocks.shape[1]):
+            sl = (slice(32 * by, 32 * by + 32), slice(64 * bx, 64 * bx + 64))
+            kind = blocks[by, bx]
+            if kind == 0:      # in focus
+                depth[sl] = 5
+            elif kind == 1:    # blurred
+                depth[sl] = 50
+            else:              # mixed
+                depth[sl] = rng.choice([5, 50], depth[sl].shape)
+    ranges = [(0, 10)]
+    exp = oracle.blur(img, depth, ranges, sigma)
+    got = sbs.selective_blur(torch.from_numpy(img).cuda(), torch.from_numpy(depth).cuda(), ranges, sigma)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(got.cpu().numpy(), exp, atol=1e-3, rtol=0)

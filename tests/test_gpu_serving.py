@@ -109,3 +109,37 @@ def test_raw_frames_through_the_device_front_end(env):
         d1, c1 = sbs.sad_disparity(r.left, r.right, r.idx, r.block, r.dmax)
         torch.cuda.synchronize()
         assert torch.equal(r.disp, d1) and torch.equal(r.cost, c1)
+
+
+def test_mixed_full_resolutions_alone_and_in_the_mix(env):
+    """The serving mix's own request classes at their real sizes (640x480
+    block 11 dmax 31, 1920x1080 block 21 dmax 63, 4096x2304 block 31 dmax
+    127), each request with its own boundary fraction drawn from [0.12, 0.24]
+    and its list from the device front end: every result equals the same
+    request run alone, and sampled entries (first and last included) equal
+    the oracle."""
+    torch, sbs, Request, Server, BudgetError, pool = env
+    rng = np.random.default_rng(105)
+    reqs = []
+    for ci, name in enumerate(("serve_vga", "serve_fhd", "serve_uhd")):
+        spec = scenes.PRESETS[name]
+        for k in range(3):
+            sp = scenes.scaled(spec, seed=spec.seed + 1000 * ci + k)
+            f = scenes.make_frame(sp)
+            L, R = torch.from_numpy(f.left).cuda(), torch.from_numpy(f.right).cuda()
+            frac = float(rng.uniform(0.12, 0.24))
+            i = len(reqs)
+            idx = sbs.boundaries(L, K=4, mode=0, min_cc=50, frac=frac, seed=sp.seed + i).clone()
+            reqs.append(Request(i, L, R, idx, sp.block, sp.dmax, 0.0, name))
+    order = rng.permutation(len(reqs))
+    srv = Server(budget_bytes=2 << 30, max_inflight=2, max_batch=4)
+    srv.run_trace([reqs[i] for i in order])
+    for r in reqs:
+        d1, c1 = sbs.sad_disparity(r.left, r.right, r.idx, r.block, r.dmax)
+        torch.cuda.synchronize()
+        assert torch.equal(r.disp, d1) and torch.equal(r.cost, c1), f"request {r.rid} ({r.klass})"
+        idx = r.idx.cpu().numpy().view(np.uint32)
+        pick = np.unique(np.concatenate([rng.choice(idx.size, 300, replace=False), [0, idx.size - 1]]))
+        d, c, _ = oracle.sad(r.left.cpu().numpy(), r.right.cpu().numpy(), idx[pick], r.block, r.dmax)
+        np.testing.assert_array_equal(r.disp.cpu().numpy()[pick], d, err_msg=f"request {r.rid} ({r.klass})")
+        np.testing.assert_array_equal(r.cost.cpu().numpy().view(np.uint32)[pick], c)
