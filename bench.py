@@ -113,6 +113,8 @@ def main():
                     help="oracle timings on the host: all threads and 1 thread, brute force and summed-area tables")
     ap.add_argument("--paper", action="store_true",
                     help="the paper's whole chain (Table 3 setting) per frame: stage times and Eq. 3 on synthetic GT")
+    ap.add_argument("--paper-only", default="", metavar="WORKLOAD",
+                    help="with --paper: run only this workload (tsukuba_gray, middlebury_rgb or uhd_rgb)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run one plain device copy of MIB mebibytes (HBM counter calibration)")
     args = ap.parse_args()
@@ -500,6 +502,8 @@ def paper_main(args):
 
     out = {"metric": "paper chain: stage ms per frame; bad-pixel % (Eq. 3)", "workloads": {}}
     for name, dmax, thr in [("tsukuba_gray", 15, 0), ("middlebury_rgb", 63, 1), ("uhd_rgb", 127, 1)]:
+        if args.paper_only and name != args.paper_only:
+            continue
         spec = scenes.PRESETS[name]
         f = scenes.make_frame(spec)
         L = torch.from_numpy(f.left).cuda()

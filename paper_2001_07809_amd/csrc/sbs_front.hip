@@ -851,11 +851,12 @@ __global__ __launch_bounds__(kBlock) void k_fc_class(ScanCtx c, uint8_t* cls, un
 }
 
 // Which class the want-th pixel falls in, and the rank wanted inside it.
-__global__ void k_fc_plan(FracState* f, const unsigned long long* n1, long long want, long long n0) {
+__global__ void k_fc_plan(FracState* f, const unsigned long long* n1, long long want, long long n0,
+                          unsigned long long s1_prefix) {
   f->want = want;
   f->n0 = n0;
   f->n1 = (long long)*n1;
-  f->s1 = RadixSel{0, 0, 0};
+  f->s1 = RadixSel{s1_prefix, 0, 0};
   f->s2 = RadixSel{0, 0, 0};
   f->s3 = RadixSel{0, 0, 0};
   if (f->want <= f->n0) { f->mode = 0; return; }
@@ -875,12 +876,10 @@ __device__ __forceinline__ bool rs_key(const ScanCtx& c, int64_t i, unsigned lon
   if constexpr (SEL == 1) {
     if (c.cls[i] != 1) return false;
     key = ~(uint32_t)comp_size(c, i);
-  } else if constexpr (SEL == 2) {
+  } else {
+    static_assert(SEL == 2, "the hash select runs over compacted candidates (k_rs_hist_cands)");
     if (c.cls[i] != 2) return false;
     key = (uint32_t)c.dist[i];
-  } else {
-    if (c.cls[i] != 2 || (uint32_t)c.dist[i] != (uint32_t)c.fc->s2.prefix) return false;
-    key = mix64((unsigned long long)i ^ c.seed);
   }
   return true;
 }
@@ -930,6 +929,53 @@ __global__ __launch_bounds__(256) void k_rs_pick(RadixSel* rs, int shift, uint32
     rs->below = before;
   }
   hist[d] = 0;   // ready for the next pass
+}
+
+// The candidates of the hash select (other pixels at the selected distance),
+// compacted once, so that its eight passes read a short list instead of the
+// class and distance of every pixel. Order in the list does not matter: the
+// select only counts keys, and the final list comes from the raster-order
+// scan. One atomic per wavefront and step.
+__global__ __launch_bounds__(kBlock) void k_fc_cands(ScanCtx c, int32_t* cand, unsigned long long* ncand) {
+  const FracState* f = c.fc;
+  if (f->mode != 2) return;
+  const uint32_t dsel = (uint32_t)f->s2.prefix;
+  const int lane = threadIdx.x & 63;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t kb = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63); kb < c.N; kb += stride) {  // per wavefront
+    const int64_t i = kb + lane;
+    const bool m = i < c.N && c.cls[i] == 2 && (uint32_t)c.dist[i] == dsel;
+    const uint64_t b = __builtin_amdgcn_ballot_w64(m);
+    if (!b) continue;
+    unsigned long long base = 0;
+    if (lane == 0) base = atomicAdd(ncand, (unsigned long long)__builtin_popcountll(b));
+    base = __shfl(base, 0, 64);
+    if (m) cand[base + __builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0u))] =
+        (int32_t)i;
+  }
+}
+
+// One hash-select pass over the compacted candidates (as k_rs_hist).
+__global__ __launch_bounds__(kBlock) void k_rs_hist_cands(const int32_t* cand, const unsigned long long* ncand,
+                                                          unsigned long long seed, const RadixSel* rs, int shift,
+                                                          uint32_t* hist) {
+  __shared__ uint32_t h[kHistCopies][257];
+  for (int i = threadIdx.x; i < kHistCopies * 257; i += blockDim.x) (&h[0][0])[i] = 0u;
+  __syncthreads();
+  uint32_t* mine = h[threadIdx.x & (kHistCopies - 1)];
+  const unsigned long long pre = rs->prefix;
+  const int hi = shift + 8;
+  const int64_t n = (int64_t)*ncand;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride) {
+    const unsigned long long key = mix64((unsigned long long)cand[k] ^ seed);
+    if (hi < 64 && (key >> hi) != (pre >> hi)) continue;
+    atomicAdd(&mine[(uint32_t)((key >> shift) & 0xFF)], 1u);
+  }
+  __syncthreads();
+  uint32_t t = 0;
+  for (int k = 0; k < kHistCopies; ++k) t += h[k][threadIdx.x];
+  if (t) atomicAdd(&hist[threadIdx.x], t);
 }
 
 // Chessboard distance to the border columns and kept pixels: per column the
@@ -993,25 +1039,58 @@ __global__ __launch_bounds__(kBlock) void k_dt_col(ScanCtx c, int32_t H, int32_t
   }
 }
 
-// One block per row; rows up to kRowLds pixels wide are searched in LDS.
+// One block per row; rows up to kRowLds pixels wide are searched in LDS,
+// with the minimum of every 16 consecutive entries beside them: the search
+// outwards from x skips a whole 16-entry block when even its nearest
+// position and its smallest entry cannot beat the best found
+// (max(|x - x'|, g(x')) >= max(distance to the block, block minimum)), so a
+// pixel far from the selected set costs about d/16 + 32 steps, not d.
 constexpr int kRowLds = 8192;
+constexpr int kDtBlk = 16;
 __global__ __launch_bounds__(kBlock) void k_dt_row(ScanCtx c, int32_t H, const int32_t* g, int32_t* dist) {
   __shared__ int32_t row[kRowLds];
-  const bool in_lds = c.W <= kRowLds;
+  __shared__ int32_t bmin[kRowLds / kDtBlk];
+  const int W = c.W;
+  const bool in_lds = W <= kRowLds;
+  const int nb = (W + kDtBlk - 1) / kDtBlk;
   for (int y = blockIdx.x; y < H; y += gridDim.x) {
-    const int32_t* grow = g + (int64_t)y * c.W;
+    const int32_t* grow = g + (int64_t)y * W;
     if (in_lds) {
-      for (int x = threadIdx.x; x < c.W; x += blockDim.x) row[x] = grow[x];
+      for (int x = threadIdx.x; x < W; x += blockDim.x) row[x] = grow[x];
       __syncthreads();
-    }
-    const int32_t* src = in_lds ? row : grow;
-    for (int x = threadIdx.x; x < c.W; x += blockDim.x) {
-      int d = src[x];
-      for (int k = 1; k < d; ++k) {
-        if (x - k >= 0) d = min(d, max(k, src[x - k]));
-        if (x + k < c.W) d = min(d, max(k, src[x + k]));
+      for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+        int m = kFar;
+        for (int x = b * kDtBlk; x < min(W, (b + 1) * kDtBlk); ++x) m = min(m, row[x]);
+        bmin[b] = m;
       }
-      dist[(int64_t)y * c.W + x] = d;
+      __syncthreads();
+      for (int x = threadIdx.x; x < W; x += blockDim.x) {
+        int d = row[x];
+        // right of x, then left of x; a block is skipped when its nearest
+        // position is at least d away or its minimum is at least d
+        for (int p = x + 1; p < W && p - x < d;) {
+          const int b = p / kDtBlk;
+          if (bmin[b] >= d) { p = (b + 1) * kDtBlk; continue; }
+          d = min(d, max(p - x, row[p]));
+          ++p;
+        }
+        for (int p = x - 1; p >= 0 && x - p < d;) {
+          const int b = p / kDtBlk;
+          if (bmin[b] >= d) { p = b * kDtBlk - 1; continue; }
+          d = min(d, max(x - p, row[p]));
+          --p;
+        }
+        dist[(int64_t)y * W + x] = d;
+      }
+    } else {
+      for (int x = threadIdx.x; x < W; x += blockDim.x) {
+        int d = grow[x];
+        for (int k = 1; k < d; ++k) {
+          if (x - k >= 0) d = min(d, max(k, grow[x - k]));
+          if (x + k < W) d = min(d, max(k, grow[x + k]));
+        }
+        dist[(int64_t)y * W + x] = d;
+      }
     }
     __syncthreads();
   }
@@ -1226,11 +1305,14 @@ int sbs_boundaries(const uint8_t* img, int32_t W, int32_t H, int32_t C, int64_t 
     hipLaunchKernelGGL(k_fill, dim3(1), dim3(kBlock), 0, s, (uint8_t*)rhist, (int64_t)(256 * 4), (uint8_t)0);
     uint8_t* cls = lab2;   // free once the refinement is done
     hipLaunchKernelGGL(k_fc_class, dim3(g), dim3(kBlock), 0, s, c, cls, n1);
-    hipLaunchKernelGGL(k_fc_plan, dim3(1), dim3(1), 0, s, fs, n1, want, n0);
+    // Component sizes are at most N: with N below 2^24 the top digit of ~size is
+    // 0xFF for every kept pixel, so it is set here and its pass skipped.
+    const bool small = N < (1LL << 24);
+    hipLaunchKernelGGL(k_fc_plan, dim3(1), dim3(1), 0, s, fs, n1, want, n0, small ? 0xFF000000ull : 0ull);
     c.fc = fs; c.dist = dist; c.frank = frank; c.seed = (unsigned long long)seed; c.cls = cls;
     // radix-select histograms: at most 512 blocks (each ends with up to 256 global adds)
     const int gr = std::min(g, 512);
-    for (int sh = 24; sh >= 0; sh -= 8) {      // kept pixels: size descending
+    for (int sh = small ? 16 : 24; sh >= 0; sh -= 8) {      // kept pixels: size descending
       hipLaunchKernelGGL(k_rs_hist<1>, dim3(gr), dim3(kBlock), 0, s, c, &fs->s1, sh, rhist);
       hipLaunchKernelGGL(k_rs_pick, dim3(1), dim3(256), 0, s, &fs->s1, sh, rhist);
     }
@@ -1260,8 +1342,14 @@ int sbs_boundaries(const uint8_t* img, int32_t W, int32_t H, int32_t C, int64_t 
       hipLaunchKernelGGL(k_rs_pick, dim3(1), dim3(256), 0, s, &fs->s2, sh, rhist);
     }
     hipLaunchKernelGGL(k_fc_after_dist, dim3(1), dim3(1), 0, s, fs);
-    for (int sh = 56; sh >= 0; sh -= 8) {      // other pixels at that distance: hash
-      hipLaunchKernelGGL(k_rs_hist<3>, dim3(gr), dim3(kBlock), 0, s, c, &fs->s3, sh, rhist);
+    // other pixels at that distance: hash, over their compacted list (in the
+    // column-distance buffer, free once the row pass has run)
+    int32_t* cand = gcol;
+    unsigned long long* ncand = (unsigned long long*)(misc + 640);
+    hipLaunchKernelGGL(k_fc_cands, dim3(gr), dim3(kBlock), 0, s, c, cand, ncand);
+    for (int sh = 56; sh >= 0; sh -= 8) {
+      hipLaunchKernelGGL(k_rs_hist_cands, dim3(std::min(gr, 64)), dim3(kBlock), 0, s, cand, ncand,
+                         (unsigned long long)seed, &fs->s3, sh, rhist);
       hipLaunchKernelGGL(k_rs_pick, dim3(1), dim3(256), 0, s, &fs->s3, sh, rhist);
     }
     hipLaunchKernelGGL(k_scan_count<3>, dim3((unsigned)nb), dim3(kBlock), 0, s, c, bsum);

@@ -262,6 +262,7 @@ __global__ __launch_bounds__(256) void k_blur_v(const uint8_t* img, const uint8_
 // travels through HBM.
 constexpr int kBlurTX = 64, kBlurTY = 32, kBlurTileRad = 14;
 constexpr int kBlurRun = 8;   // outputs per thread and pass
+constexpr int kBlurThreads = 512;   // eight wavefronts per tile: 24 per CU at three tiles
 
 template <int C, int RAD>
 struct BlurTileGeom {
@@ -274,8 +275,9 @@ struct BlurTileGeom {
 };
 
 template <int C, int RAD>
-__global__ __launch_bounds__(256) void k_blur_tile(const uint8_t* img, const uint8_t* depth, int32_t W, int32_t H,
-                                                   int64_t pitch, int32_t aligned, BlurArgs a, float* out) {
+__global__ __launch_bounds__(kBlurThreads) void k_blur_tile(const uint8_t* img, const uint8_t* depth, int32_t W,
+                                                            int32_t H, int64_t pitch, int32_t aligned, BlurArgs a,
+                                                            float* out) {
   using G = BlurTileGeom<C, RAD>;
   extern __shared__ __attribute__((aligned(16))) unsigned char blur_lds[];
   float* hb = (float*)blur_lds;                                          // rows x hrow
@@ -286,7 +288,7 @@ __global__ __launch_bounds__(256) void k_blur_tile(const uint8_t* img, const uin
 
   // in-focus flags of the tile's pixels (1 outside the image: nothing to do there)
   bool need = false;
-  for (int i = tid; i < kBlurTX * kBlurTY; i += 256) {
+  for (int i = tid; i < kBlurTX * kBlurTY; i += kBlurThreads) {
     const int y = i / kBlurTX, x = i - y * kBlurTX;
     bool k = true;
     if (y0 + y < H && x0 + x < W) {
@@ -299,7 +301,7 @@ __global__ __launch_bounds__(256) void k_blur_tile(const uint8_t* img, const uin
   }
   if (!__syncthreads_or(need)) {
     // every pixel in focus: the image itself, as floats
-    for (int i = tid; i < kBlurTY * kBlurTX * C; i += 256) {
+    for (int i = tid; i < kBlurTY * kBlurTX * C; i += kBlurThreads) {
       const int y = i / (kBlurTX * C), xc = i - y * (kBlurTX * C);
       if (y0 + y < H && x0 * C + xc < W * C)
         out[((int64_t)(y0 + y) * W + x0) * C + xc] = (float)img[(int64_t)(y0 + y) * pitch + (int64_t)x0 * C + xc];
@@ -313,7 +315,7 @@ __global__ __launch_bounds__(256) void k_blur_tile(const uint8_t* img, const uin
     const int q0 = s0 & ~3;
     constexpr int ndw = (G::rowb + 3 + 3) / 4;      // dwords covering the row's bytes
     const int rowend = W * C;
-    for (int i = tid; i < G::rows * ndw; i += 256) {
+    for (int i = tid; i < G::rows * ndw; i += kBlurThreads) {
       const int r = i / ndw, w = i - r * ndw;
       const int yy = min(max(y0 - RAD + r, 0), H - 1);
       const uint8_t* row = img + (int64_t)yy * pitch;
@@ -331,7 +333,7 @@ __global__ __launch_bounds__(256) void k_blur_tile(const uint8_t* img, const uin
       }
     }
   } else {
-    for (int b = tid; b < G::rows * G::rowb; b += 256) {
+    for (int b = tid; b < G::rows * G::rowb; b += kBlurThreads) {
       const int r = b / G::rowb, jc = b - r * G::rowb, j = jc / C;
       const int yy = min(max(y0 - RAD + r, 0), H - 1), xx = min(max(x0 - RAD + j, 0), W - 1);
       ib[r * G::rowbp + jc] = img[(int64_t)yy * pitch + (int64_t)xx * C + (jc - j * C)];
@@ -342,7 +344,7 @@ __global__ __launch_bounds__(256) void k_blur_tile(const uint8_t* img, const uin
   // horizontal pass: item = (run of 8 columns, row, channel), rows and
   // channels varying fastest across lanes
   constexpr int hitems = (kBlurTX / kBlurRun) * G::rows * C;
-  for (int i = tid; i < hitems; i += 256) {
+  for (int i = tid; i < hitems; i += kBlurThreads) {
     const int run = i / (G::rows * C), rc = i - run * (G::rows * C);
     const int r = rc / C, c = rc - r * C;
     const uint8_t* src = ib + r * G::rowbp + run * kBlurRun * C + c;   // column run*8 + j - RAD at src[j * C]
@@ -362,7 +364,7 @@ __global__ __launch_bounds__(256) void k_blur_tile(const uint8_t* img, const uin
 
   // vertical pass: item = (run of 8 rows, column x channel), columns varying fastest
   constexpr int vitems = (kBlurTY / kBlurRun) * kBlurTX * C;
-  for (int i = tid; i < vitems; i += 256) {
+  for (int i = tid; i < vitems; i += kBlurThreads) {
     const int run = i / (kBlurTX * C), xc = i - run * (kBlurTX * C);
     const int x = xc / C;
     if (x0 + x >= W) continue;
@@ -391,7 +393,8 @@ template <int C, int RAD>
 void launch_blur_tile(dim3 grid, hipStream_t s, const uint8_t* img, const uint8_t* depth, int32_t W, int32_t H,
                       int64_t pitch, int32_t aligned, const BlurArgs& a, float* out) {
   constexpr size_t lds = BlurTileGeom<C, RAD>::lds;
-  hipLaunchKernelGGL((k_blur_tile<C, RAD>), grid, dim3(256), lds, s, img, depth, W, H, pitch, aligned, a, out);
+  hipLaunchKernelGGL((k_blur_tile<C, RAD>), grid, dim3(kBlurThreads), lds, s, img, depth, W, H, pitch, aligned, a,
+                     out);
 }
 
 template <int C, int... R>
