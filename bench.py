@@ -114,9 +114,14 @@ def main():
     ap.add_argument("--paper", action="store_true",
                     help="the paper's whole chain (Table 3 setting) per frame: stage times and Eq. 3 on synthetic GT")
     ap.add_argument("--paper-only", default="", metavar="WORKLOAD",
-                    help="with --paper: run only this workload (tsukuba_gray, middlebury_rgb or uhd_rgb)")
+                    help="with --paper: run only this workload (tsukuba_paper, middlebury_paper or uhd_rgb)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run one plain device copy of MIB mebibytes (HBM counter calibration)")
+    ap.add_argument("--front-end", action="store_true",
+                    help="only time the device front end with fraction control on frame 0 of the video "
+                         "(6 warm-up and 10 timed calls)")
+    ap.add_argument("--probe-alu", action="store_true",
+                    help="only measure the v_sad_u8 issue rate the tile kernel's roofline assumes")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -143,6 +148,31 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": nbytes}), flush=True)
+        return
+    if args.front_end:
+        spec = scenes.PRESETS["uhd_video"]
+        fr = scenes.video_fracs(spec, 0, 1)
+        left, _, _ = scenes.make_video(spec, 0, 1, fr)
+        L = torch.from_numpy(left[0]).cuda()
+        call = lambda: sbs.boundaries(L, K=FRONT_K, mode=0, min_cc=FRONT_MIN_CC, frac=float(fr[0]), seed=spec.seed)
+        for _ in range(6):
+            lst = call()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(10):
+            lst = call()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 100.0
+        print(json.dumps({"front_end_ms_per_frame": ms, "frame": "uhd_video frame 0", "frac": float(fr[0]),
+                          "listed": int(lst.numel())}), flush=True)
+        return
+    if args.probe_alu:
+        peak = 256 * 64 * 2.4e9
+        runs = [sbs.probe_sad_rate(blocks=b, trips=2000) for b in (4096, 8192, 16384)]
+        best = max(r["lane_ops_per_s"] for r in runs)
+        print(json.dumps({"probe": "v_sad_u8 lane-ops/s, 16 independent chains per lane", "runs": runs,
+                          "best_lane_ops_per_s": best, "roofline_peak": peak, "best_over_peak": best / peak}),
+              flush=True)
         return
     sbs.lib()
     if args.tuning and os.path.exists(args.tuning):
@@ -501,7 +531,7 @@ def paper_main(args):
     import scenes
 
     out = {"metric": "paper chain: stage ms per frame; bad-pixel % (Eq. 3)", "workloads": {}}
-    for name, dmax, thr in [("tsukuba_gray", 15, 0), ("middlebury_rgb", 63, 1), ("uhd_rgb", 127, 1)]:
+    for name, dmax, thr in [("tsukuba_paper", 15, 0), ("middlebury_paper", 63, 1), ("uhd_rgb", 127, 1)]:
         if args.paper_only and name != args.paper_only:
             continue
         spec = scenes.PRESETS[name]

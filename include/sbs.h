@@ -220,6 +220,18 @@ int sbs_kernel_timing(int32_t enable);
 int32_t sbs_kernel_times(float* ms, int32_t cap);
 
 /*
+ * Issue-rate probe (diagnostic; not part of the disparity path): runs
+ * `blocks` one-wavefront workgroups, each lane issuing trips * 128 v_sad_u8
+ * (16 independent chains, 8 steps per trip) back to back, and reports the
+ * v_sad_u8 lane operations per second and the kernel's duration (HIP events,
+ * after one warm-up launch, on the null stream; synchronous). This is the
+ * rate the tile kernel's integer-ALU roofline assumes: 256 CUs x 64 lanes
+ * per clock. Allocates a small output buffer. SBS_ERR_INVALID_ARG for
+ * blocks or trips < 1 or NULL outputs.
+ */
+int sbs_probe_sad_rate(int32_t blocks, int32_t trips, double* lane_ops_per_s, double* ms);
+
+/*
  * Disparity map reconstruction (Sec. III "Disparity Map Reconstruction from
  * Boundaries"): the listed pixels' disparities are spread to a dense u8 map.
  * Stage 1 (Algorithm 1, fill along scan lines): in each row, every pixel
@@ -301,8 +313,9 @@ int sbs_lightness(const uint8_t* img, int32_t W, int32_t H, int32_t C, int64_t p
  *                without the border columns
  *   out_labels   device W*H bytes or NULL: the label image the boundary map
  *                is taken from (after open/close in mode 0)
- *   workspace    device, >= sbs_boundaries_workspace_bytes(W, H) bytes; the
- *                library keeps nothing in it between calls
+ *   workspace    device, >= sbs_boundaries_workspace_bytes(W, H) bytes,
+ *                256-byte aligned (as hipMalloc returns); the library keeps
+ *                nothing in it between calls
  * W*H <= 2^31 - 1 and H <= 262140 (else SBS_ERR_UNSUPPORTED). Asynchronous
  * on `stream`; SBS_ERR_INVALID_ARG for bad arguments (nothing is launched then).
  */

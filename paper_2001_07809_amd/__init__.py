@@ -46,7 +46,7 @@ def build() -> str:
     """Compile libsbs.so for gfx950 (always recompiles)."""
     srcs = [os.path.join(_CSRC, "sbs_kernels.hip"), os.path.join(_CSRC, "sbs_api.hip"),
             os.path.join(_CSRC, "sbs_post.hip"), os.path.join(_CSRC, "sbs_front.hip"),
-            os.path.join(_CSRC, "sbs_noalloc.hip")]
+            os.path.join(_CSRC, "sbs_noalloc.hip"), os.path.join(_CSRC, "sbs_probe.hip")]
     cmd = [HIPCC, *HIP_FLAGS, *srcs, "-o", _SO + ".tmp"]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
@@ -105,6 +105,8 @@ def lib():
         "sbs_kernel_times": ([ctypes.POINTER(ctypes.c_float), I32], I32),
         "sbs_lightness": ([V, I32, I32, I32, I64, V, V], ctypes.c_int),
         "sbs_boundaries_workspace_bytes": ([I32, I32], SZ),
+        "sbs_probe_sad_rate": ([I32, I32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)],
+                               ctypes.c_int),
         "sbs_boundaries": ([V, I32, I32, I32, I64, I32, I32, I32, ctypes.c_double, ctypes.c_uint64, V, V, V, V, V,
                             SZ, V], ctypes.c_int),
     }
@@ -222,6 +224,14 @@ def sad_disparity_ref(left, right, idx, block: int, dmax: int, out=None, cost=No
     _check(lib().sbs_sad_disparity_ref(f.left, f.right, f.W, f.H, f.C, f.pitch_bytes, f.boundary_idx, f.n,
                                        f.block, f.dmax, f.out_disp, f.out_cost, _stream_handle(stream)))
     return out, cost
+
+
+def probe_sad_rate(blocks: int = 8192, trips: int = 2000) -> dict:
+    """v_sad_u8 lane operations per second with every wavefront slot busy
+    (sbs_probe_sad_rate; synchronous)."""
+    rate, ms = ctypes.c_double(), ctypes.c_double()
+    _check(lib().sbs_probe_sad_rate(blocks, trips, ctypes.byref(rate), ctypes.byref(ms)))
+    return {"lane_ops_per_s": rate.value, "ms": ms.value, "blocks": blocks, "trips": trips}
 
 
 def workspace_bytes(frames) -> int:

@@ -38,6 +38,8 @@ constexpr int kBlock = 256;
 constexpr int kScanPer = 1024;     // elements per block in the device-wide scans
 constexpr int kMaxK = 64;
 constexpr int kMaxPasses = 1000;
+constexpr int kN1Parts = 64;        // partial counts of kept pixels (fraction control)
+constexpr int kMiscBytes = 2048;    // small device state of one call, cleared at its start
 
 // ---------------------------------------------------------------------------
 // Lightness. sRGB decode of each channel, luminance Y = 0.2126 R + 0.7152 G +
@@ -563,14 +565,31 @@ __global__ __launch_bounds__(kBlock) void k_drop_count(const int32_t* __restrict
   if (threadIdx.x == 0) part = 0;
   __syncthreads();
   unsigned long long mine = 0;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
-    if (parent[i] != (int32_t)i) continue;   // roots only
+  auto count_root = [&](int64_t i) {
     const int32_t s = size[i];
     mine += (unsigned long long)s;
     if (s < kSmall) atomicAdd(&small[s], 1);
     else atomicAdd(&cnt[s], 1);
+  };
+  // four pixels per thread and step (one 16-byte load of parents: the grid
+  // is small, so each thread needs several loads in flight), then the tail
+  const int64_t nq = N >> 2;
+  const int4* pq = (const int4*)parent;   // 16-byte aligned: in the 256-byte aligned workspace
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nq; q += (int64_t)gridDim.x * blockDim.x) {
+    const int4 p = pq[q];
+    const int64_t i = q << 2;
+    if (p.x == (int32_t)i) count_root(i);   // roots only
+    if (p.y == (int32_t)(i + 1)) count_root(i + 1);
+    if (p.z == (int32_t)(i + 2)) count_root(i + 2);
+    if (p.w == (int32_t)(i + 3)) count_root(i + 3);
   }
-  atomicAdd(&part, mine);
+  if (blockIdx.x == 0)
+    for (int64_t i = (nq << 2) + threadIdx.x; i < N; i += blockDim.x)
+      if (parent[i] == (int32_t)i) count_root(i);
+  // one LDS add per wavefront (adds to one word from every lane serialise)
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) mine += __shfl_xor(mine, off, 64);
+  if ((threadIdx.x & 63) == 0 && mine) atomicAdd(&part, mine);
   __syncthreads();
   for (int j = threadIdx.x; j < kSmall && j <= N; j += blockDim.x)
     if (small[j]) atomicAdd(&cnt[j], small[j]);
@@ -669,8 +688,8 @@ struct ScanCtx {
   const uint8_t* cls;     // fraction control: 0 border column, 1 kept, 2 other
 };
 
-__device__ __forceinline__ bool kept(const ScanCtx& c, int64_t i) {
-  const int32_t r = c.parent[i];
+// Kept: the pixel's component (root r, -1 for no boundary pixel) passes the filter.
+__device__ __forceinline__ bool kept_root(const ScanCtx& c, int32_t r) {
   if (r < 0) return false;
   const int32_t s = c.size[r];
   if (!c.rule) return s >= c.min_cc;
@@ -678,6 +697,7 @@ __device__ __forceinline__ bool kept(const ScanCtx& c, int64_t i) {
   if (s == c.rule->s_star) return c.rank[r] >= c.rule->m;
   return true;
 }
+__device__ __forceinline__ bool kept(const ScanCtx& c, int64_t i) { return kept_root(c, c.parent[i]); }
 
 // SplitMix64's output function (Steele, Lea and Flood; constants as
 // published by Vigna), on the raster index xor the seed.
@@ -835,19 +855,61 @@ __global__ __launch_bounds__(kBlock) void k_scan_apply(ScanCtx c, const uint32_t
 // ---------------------------------------------------------------------------
 // Fraction control kernels.
 // Class of every pixel (0 border column, 1 kept, 2 other) and the kept count.
+// Class of every pixel: 0 border column, 1 kept, 2 other; and the count of
+// kept pixels. Four pixels per thread and step: one 16-byte load of their
+// parents, one word of classes written (the workspace keeps both arrays
+// 256-byte aligned), the column of the first one divided out once.
 __global__ __launch_bounds__(kBlock) void k_fc_class(ScanCtx c, uint8_t* cls, unsigned long long* n1) {
   __shared__ unsigned long long part;
   if (threadIdx.x == 0) part = 0;
   __syncthreads();
   unsigned long long mine = 0;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < c.N; i += (int64_t)gridDim.x * blockDim.x) {
-    const uint8_t k = border(c, i) ? 0 : (kept(c, i) ? 1 : 2);
-    cls[i] = k;
-    mine += k == 1 ? 1ull : 0ull;
+  auto cls_of = [&](int x, int32_t r) -> uint32_t {
+    return (x == 0 || x == c.W - 1) ? 0u : (kept_root(c, r) ? 1u : 2u);
+  };
+  // the filter's fields once; the four component sizes of a quad gathered
+  // together (from index 0 for pixels without a component), so a quad costs
+  // two round trips to memory, not five
+  const bool rule = c.rule != nullptr;
+  const int32_t s_star = rule ? c.rule->s_star : 0, m_star = rule ? c.rule->m : 0;
+  const int64_t nq = c.N >> 2;
+  const int4* pq = (const int4*)c.parent;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nq; q += (int64_t)gridDim.x * blockDim.x) {
+    const int4 p = pq[q];
+    int x = (int)((uint32_t)(q << 2) % (uint32_t)c.W);   // W * H < 2^31: 32-bit division suffices
+    const int32_t r[4] = {p.x, p.y, p.z, p.w};
+    int32_t sz[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) sz[b] = c.size[r[b] < 0 ? 0 : r[b]];
+    uint32_t w = 0u;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      bool kp = r[b] >= 0;
+      if (kp) {
+        if (!rule) kp = sz[b] >= c.min_cc;
+        else kp = sz[b] > s_star || (sz[b] == s_star && c.rank[r[b]] >= m_star);
+      }
+      const uint32_t k = (x == 0 || x == c.W - 1) ? 0u : (kp ? 1u : 2u);
+      w |= k << (8 * b);
+      mine += k == 1u ? 1ull : 0ull;
+      x = x + 1 == c.W ? 0 : x + 1;
+    }
+    ((uint32_t*)cls)[q] = w;
   }
-  atomicAdd(&part, mine);
+  if (blockIdx.x == 0)
+    for (int64_t i = (nq << 2) + threadIdx.x; i < c.N; i += blockDim.x) {
+      const uint32_t k = cls_of((int)((uint32_t)i % (uint32_t)c.W), c.parent[i]);
+      cls[i] = (uint8_t)k;
+      mine += k == 1u ? 1ull : 0ull;
+    }
+  // one LDS add per wavefront (adds to one word from every lane serialise)
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) mine += __shfl_xor(mine, off, 64);
+  if ((threadIdx.x & 63) == 0 && mine) atomicAdd(&part, mine);
   __syncthreads();
-  if (threadIdx.x == 0) atomicAdd(n1, part);
+  // one of kN1Parts counters per block: adds to a single word from thousands
+  // of blocks queue up one after another at the memory side
+  if (threadIdx.x == 0 && part) atomicAdd(&n1[blockIdx.x % kN1Parts], part);
 }
 
 // Which class the want-th pixel falls in, and the rank wanted inside it.
@@ -855,7 +917,9 @@ __global__ void k_fc_plan(FracState* f, const unsigned long long* n1, long long 
                           unsigned long long s1_prefix) {
   f->want = want;
   f->n0 = n0;
-  f->n1 = (long long)*n1;
+  long long nk = 0;
+  for (int k = 0; k < kN1Parts; ++k) nk += (long long)n1[k];
+  f->n1 = nk;
   f->s1 = RadixSel{s1_prefix, 0, 0};
   f->s2 = RadixSel{0, 0, 0};
   f->s3 = RadixSel{0, 0, 0};
@@ -897,12 +961,40 @@ __global__ __launch_bounds__(kBlock) void k_rs_hist(ScanCtx c, const RadixSel* r
   const unsigned long long pre = rs->prefix;
   const int hi = shift + 8;   // digits above this one must match the prefix
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < c.N; i += stride) {
+  auto count = [&](int64_t i) {
     unsigned long long key = 0;
     bool cand = rs_key<SEL>(c, i, key);
     if (cand && hi < 64 && (key >> hi) != (pre >> hi)) cand = false;
     if (cand) atomicAdd(&mine[(uint32_t)((key >> shift) & 0xFF)], 1u);
+  };
+  // four pixels per thread and step, their classes in one word (the grid is
+  // small, so each thread needs several loads in flight), then the tail
+  const int64_t nq = c.N >> 2;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nq; q += stride) {
+    const uint32_t k4 = ((const uint32_t*)c.cls)[q];   // 4-byte aligned: in the 256-byte aligned workspace
+    // classes 0, 1, 2: bit 0 marks class 1, bit 1 class 2
+    if (!(k4 & (SEL == 1 ? 0x01010101u : 0x02020202u))) continue;
+    // the quad's keys: (kept) four parents then four sizes, each group
+    // loaded together; (other) four distances in one load
+    uint32_t key[4];
+    if constexpr (SEL == 1) {
+      const int4 p = ((const int4*)c.parent)[q];
+      const int32_t r[4] = {p.x, p.y, p.z, p.w};
+#pragma unroll
+      for (int b = 0; b < 4; ++b) key[b] = ~(uint32_t)c.size[r[b] < 0 ? 0 : r[b]];
+    } else {
+      const int4 d = ((const int4*)c.dist)[q];
+      key[0] = (uint32_t)d.x; key[1] = (uint32_t)d.y; key[2] = (uint32_t)d.z; key[3] = (uint32_t)d.w;
+    }
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      if (((k4 >> (8 * b)) & 0xFFu) != (SEL == 1 ? 1u : 2u)) continue;
+      if (hi < 64 && ((unsigned long long)key[b] >> hi) != (pre >> hi)) continue;
+      atomicAdd(&mine[(key[b] >> shift) & 0xFFu], 1u);
+    }
   }
+  if (blockIdx.x == 0)
+    for (int64_t i = (nq << 2) + threadIdx.x; i < c.N; i += blockDim.x) count(i);
   __syncthreads();
   uint32_t t = 0;
   for (int k = 0; k < kHistCopies; ++k) t += h[k][threadIdx.x];
@@ -910,20 +1002,13 @@ __global__ __launch_bounds__(kBlock) void k_rs_hist(ScanCtx c, const RadixSel* r
 }
 
 __global__ __launch_bounds__(256) void k_rs_pick(RadixSel* rs, int shift, uint32_t* hist) {
-  __shared__ unsigned long long sc[256];
+  __shared__ uint32_t wtot[4];
   const int d = threadIdx.x;
-  const unsigned long long v = hist[d];
-  sc[d] = v;
-  __syncthreads();
-  for (int off = 1; off < 256; off <<= 1) {
-    const unsigned long long a = d >= off ? sc[d - off] : 0ull;
-    __syncthreads();
-    sc[d] += a;
-    __syncthreads();
-  }
+  const uint32_t v = hist[d];
   const long long need = rs->need, below = rs->below;
-  const long long before = below + (long long)(sc[d] - v);   // candidates with a smaller digit
-  __syncthreads();
+  // the scan's barriers also order every thread's reads of rs before the write below
+  uint32_t total = 0u;   // counts add up to at most N < 2^31
+  const long long before = below + (long long)block_scan_excl<4>(v, wtot, total);   // smaller digits
   if (need > 0 && before < need && need <= before + (long long)v) {
     rs->prefix |= (unsigned long long)d << shift;
     rs->below = before;
@@ -935,23 +1020,52 @@ __global__ __launch_bounds__(256) void k_rs_pick(RadixSel* rs, int shift, uint32
 // compacted once, so that its eight passes read a short list instead of the
 // class and distance of every pixel. Order in the list does not matter: the
 // select only counts keys, and the final list comes from the raster-order
-// scan. One atomic per wavefront and step.
+// scan. Each block takes kCandPer pixels a step, each thread four adjacent
+// ones per load (a word of classes, 16 bytes of distances), and reserves
+// their places with one atomic (a few hundred per image: adds to one word
+// queue up one after another at the memory side).
+constexpr int kCandPer = 16384;
 __global__ __launch_bounds__(kBlock) void k_fc_cands(ScanCtx c, int32_t* cand, unsigned long long* ncand) {
+  constexpr int kQuads = kCandPer / (4 * kBlock);   // quads per thread and step
+  static_assert(kQuads * 4 * kBlock == kCandPer && 4 * kQuads <= 64, "one mask word per thread");
+  __shared__ uint32_t wtot[kBlock / 64];
+  __shared__ unsigned long long base;
   const FracState* f = c.fc;
   if (f->mode != 2) return;
-  const uint32_t dsel = (uint32_t)f->s2.prefix;
-  const int lane = threadIdx.x & 63;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t kb = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63); kb < c.N; kb += stride) {  // per wavefront
-    const int64_t i = kb + lane;
-    const bool m = i < c.N && c.cls[i] == 2 && (uint32_t)c.dist[i] == dsel;
-    const uint64_t b = __builtin_amdgcn_ballot_w64(m);
-    if (!b) continue;
-    unsigned long long base = 0;
-    if (lane == 0) base = atomicAdd(ncand, (unsigned long long)__builtin_popcountll(b));
-    base = __shfl(base, 0, 64);
-    if (m) cand[base + __builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0u))] =
-        (int32_t)i;
+  const int32_t dsel = (int32_t)f->s2.prefix;
+  const int64_t nq = c.N >> 2;
+  const uint32_t* cw = (const uint32_t*)c.cls;   // 256-byte aligned workspace arrays
+  const int4* dq = (const int4*)c.dist;
+  for (int64_t b0 = (int64_t)blockIdx.x * kCandPer; b0 < c.N; b0 += (int64_t)gridDim.x * kCandPer) {
+    uint64_t m = 0u;   // bit 4k + b: pixel 4 (q0 + k kBlock) + b is a candidate
+    const int64_t q0 = (b0 >> 2) + threadIdx.x;
+#pragma unroll
+    for (int k = 0; k < kQuads; ++k) {
+      const int64_t q = q0 + (int64_t)k * kBlock;
+      if (q < nq) {
+        const uint32_t k4 = cw[q];
+        if (k4 & 0x02020202u) {   // some class-2 pixel among the four
+          const int4 d = dq[q];
+          const int32_t dv[4] = {d.x, d.y, d.z, d.w};
+#pragma unroll
+          for (int b = 0; b < 4; ++b)
+            if (((k4 >> (8 * b)) & 0xFFu) == 2u && dv[b] == dsel) m |= 1ull << (4 * k + b);
+        }
+      } else if (q == nq) {   // the last N % 4 pixels
+        for (int64_t i = q << 2; i < c.N; ++i)
+          if (c.cls[i] == 2 && c.dist[i] == dsel) m |= 1ull << (4 * k + (int)(i - (q << 2)));
+      }
+    }
+    const uint32_t cnt = (uint32_t)__builtin_popcountll(m);
+    uint32_t total = 0u;
+    const uint32_t before = block_scan_excl<kBlock / 64>(cnt, wtot, total);
+    if (threadIdx.x == 0) base = total ? atomicAdd(ncand, (unsigned long long)total) : 0ull;
+    __syncthreads();
+    unsigned long long pos = base + before;
+    for (int k = 0; k < kQuads; ++k)
+      for (int b = 0; b < 4; ++b)
+        if (m >> (4 * k + b) & 1ull) cand[pos++] = (int32_t)(((q0 + (int64_t)k * kBlock) << 2) + b);
+    __syncthreads();   // base is rewritten by the next step
   }
 }
 
@@ -999,44 +1113,71 @@ __global__ __launch_bounds__(kBlock) void k_dt_seg(ScanCtx c, int32_t H, int32_t
   first[t] = fi;
 }
 
-// Per column: the nearest selected row above each segment and below it.
-__global__ __launch_bounds__(kBlock) void k_dt_carry(int32_t W, int32_t nseg, const int32_t* last, const int32_t* first,
-                                                     int32_t* up, int32_t* down) {
+// Per column: the nearest selected row above each segment and below it. The
+// records are read kCarryBatch at a time before any result is written, so a
+// thread has that many loads in flight instead of one round trip per segment.
+constexpr int kCarryBatch = 16;
+__global__ __launch_bounds__(kBlock) void k_dt_carry(int32_t W, int32_t nseg, const int32_t* __restrict__ last,
+                                                     const int32_t* __restrict__ first, int32_t* __restrict__ up,
+                                                     int32_t* __restrict__ down) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   if (x >= W) return;
   int u = -kFar;
-  for (int sg = 0; sg < nseg; ++sg) {
-    up[(int64_t)sg * W + x] = u;
-    const int l = last[(int64_t)sg * W + x];
-    if (l >= 0) u = l;
+  for (int s0 = 0; s0 < nseg; s0 += kCarryBatch) {
+    int v[kCarryBatch];
+#pragma unroll
+    for (int k = 0; k < kCarryBatch; ++k) v[k] = s0 + k < nseg ? last[(int64_t)(s0 + k) * W + x] : -1;
+#pragma unroll
+    for (int k = 0; k < kCarryBatch; ++k) {
+      if (s0 + k >= nseg) break;
+      up[(int64_t)(s0 + k) * W + x] = u;
+      if (v[k] >= 0) u = v[k];
+    }
   }
   int d = kFar;
-  for (int sg = nseg - 1; sg >= 0; --sg) {
-    down[(int64_t)sg * W + x] = d;
-    const int f = first[(int64_t)sg * W + x];
-    if (f < kFar) d = f;
+  for (int s1 = nseg - 1; s1 >= 0; s1 -= kCarryBatch) {   // segments s1, s1 - 1, ...
+    int v[kCarryBatch];
+#pragma unroll
+    for (int k = 0; k < kCarryBatch; ++k) v[k] = s1 - k >= 0 ? first[(int64_t)(s1 - k) * W + x] : kFar;
+#pragma unroll
+    for (int k = 0; k < kCarryBatch; ++k) {
+      if (s1 - k < 0) break;
+      down[(int64_t)(s1 - k) * W + x] = d;
+      if (v[k] < kFar) d = v[k];
+    }
   }
 }
 
-// g = vertical distance to the nearest selected pixel of the column.
+// g = vertical distance to the nearest selected pixel of the column. The
+// segment's selection bits are read first (all loads in flight at once),
+// then both passes run on registers and the results are written once.
 __global__ __launch_bounds__(kBlock) void k_dt_col(ScanCtx c, int32_t H, int32_t nseg, const int32_t* up,
                                                    const int32_t* down, int32_t* g) {
+  static_assert(kSegRows <= 32, "one mask word per segment");
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= (int64_t)nseg * c.W) return;
   const int x = (int)((uint32_t)t % (uint32_t)c.W), sg = (int)((uint32_t)t / (uint32_t)c.W);   // t < N < 2^31
-  const int y0 = sg * kSegRows, y1 = min(H, (sg + 1) * kSegRows);
+  const int y0 = sg * kSegRows, n = min(H - y0, kSegRows);
+  uint32_t sel = 0u;   // bit k: row y0 + k is selected
+#pragma unroll
+  for (int k = 0; k < kSegRows; ++k)
+    if (k < n && in_set(c, (int64_t)(y0 + k) * c.W + x)) sel |= 1u << k;
+  int gv[kSegRows];
   int u = up[t];
-  for (int y = y0; y < y1; ++y) {
-    const int64_t i = (int64_t)y * c.W + x;
-    if (in_set(c, i)) u = y;
-    g[i] = u < 0 ? kFar : y - u;
+#pragma unroll
+  for (int k = 0; k < kSegRows; ++k) {
+    if (sel >> k & 1u) u = y0 + k;
+    gv[k] = u < 0 ? kFar : y0 + k - u;
   }
   int d = down[t];
-  for (int y = y1 - 1; y >= y0; --y) {
-    const int64_t i = (int64_t)y * c.W + x;
-    if (in_set(c, i)) d = y;
-    if (d < kFar) g[i] = min(g[i], d - y);
+#pragma unroll
+  for (int k = kSegRows - 1; k >= 0; --k) {
+    if (sel >> k & 1u) d = y0 + k;
+    if (d < kFar) gv[k] = min(gv[k], d - (y0 + k));
   }
+#pragma unroll
+  for (int k = 0; k < kSegRows; ++k)
+    if (k < n) g[(int64_t)(y0 + k) * c.W + x] = gv[k];
 }
 
 // One block per row; rows up to kRowLds pixels wide are searched in LDS,
@@ -1096,6 +1237,106 @@ __global__ __launch_bounds__(kBlock) void k_dt_row(ScanCtx c, int32_t H, const i
   }
 }
 
+// The same row pass for rows up to 4096 pixels (and columns up to 65535
+// rows, so that g fits 16 bits), without a search per pixel. For k >= 0,
+// d(x) <= k exactly when some x' with |x - x'| <= k has g(x') <= k, i.e. when
+// the minimum of g over [x - k, x + k] (cut to the row) is at most k. A sparse
+// table of minima over power-of-two ranges gives that minimum with two LDS
+// reads. Each thread takes a run of adjacent pixels: the first by binary
+// search over k, each next one from its left neighbour, since d changes by
+// at most 1 from a pixel to the next (a minimum of functions of slope at most
+// 1), which leaves at most two tests: k = d - 1, then k = d.
+// The same pass counts the distances of the other pixels (class 2), whose
+// select then needs one pick over the counts (k_fc_dist_pick) instead of
+// radix passes over every pixel: distances are below W (the border columns
+// are selected), so the counts have at most 4096 bins.
+constexpr int kStW = 4096;
+constexpr int kStLevels = 13;   // ranges of 1 .. 4096
+constexpr int kStBlock = 1024;
+__global__ __launch_bounds__(kStBlock) void k_dt_row_st(int32_t W, int32_t H, const int32_t* g, int32_t* dist,
+                                                        const uint8_t* cls, uint32_t* dhist) {
+  __shared__ uint16_t st[kStLevels][kStW];
+  __shared__ uint32_t hloc[kStW];
+  for (int b = threadIdx.x; b < kStW; b += kStBlock) hloc[b] = 0u;
+  const int levels = 32 - __builtin_clz((unsigned)W);   // 2^(levels-1) <= W
+  const int run = (W + kStBlock - 1) / kStBlock;
+  for (int y = blockIdx.x; y < H; y += gridDim.x) {
+    const int32_t* grow = g + (int64_t)y * W;
+    for (int x = threadIdx.x; x < W; x += kStBlock) st[0][x] = (uint16_t)min(grow[x], 65535);
+    __syncthreads();
+    for (int j = 1; j < levels; ++j) {
+      const int h = 1 << (j - 1);
+      for (int x = threadIdx.x; x + 2 * h <= W; x += kStBlock) st[j][x] = min(st[j - 1][x], st[j - 1][x + h]);
+      __syncthreads();
+    }
+    // minimum of g over [l, r], 0 <= l <= r < W
+    auto rmq = [&](int l, int r) -> int {
+      const int j = 31 - __builtin_clz((unsigned)(r - l + 1));
+      return (int)min(st[j][l], st[j][r - (1 << j) + 1]);
+    };
+    // d(x) <= k
+    auto within = [&](int x, int k) -> bool { return rmq(max(0, x - k), min(W - 1, x + k)) <= k; };
+    const int rowmin = rmq(0, W - 1);
+    const int x0 = threadIdx.x * run, x1 = min(W, x0 + run);
+    int32_t* drow = dist + (int64_t)y * W;
+    if (rowmin == 65535) {
+      // no selected pixel in any column of the image
+      for (int x = x0; x < x1; ++x) drow[x] = kFar;
+    } else if (x0 < x1) {
+      // d(x0) lies in [0, hi]: the pixel's own column bounds it, and so does
+      // the column holding the row minimum
+      const int gx = st[0][x0];
+      int lo = 0, hi = min(gx == 65535 ? kFar : gx, max(W - 1, rowmin));
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (within(x0, mid)) hi = mid;
+        else lo = mid + 1;
+      }
+      const uint8_t* crow = cls + (int64_t)y * W;
+      int d = lo;
+      drow[x0] = d;
+      if (crow[x0] == 2) atomicAdd(&hloc[d], 1u);
+      for (int x = x0 + 1; x < x1; ++x) {
+        if (d > 0 && within(x, d - 1)) d = d - 1;
+        else if (!within(x, d)) d = d + 1;
+        drow[x] = d;
+        if (crow[x] == 2) atomicAdd(&hloc[d], 1u);
+      }
+    }
+    __syncthreads();
+  }
+  for (int b = threadIdx.x; b < W; b += kStBlock)
+    if (hloc[b]) atomicAdd(&dhist[b], hloc[b]);
+}
+
+// The distance select from the counts of k_dt_row_st: the smallest distance
+// D whose running count reaches s2.need, and the count below it (what the
+// radix passes would leave in s2). One block; each thread sums four bins.
+__global__ __launch_bounds__(kStBlock) void k_fc_dist_pick(FracState* f, const uint32_t* dhist, int32_t W) {
+  static_assert(kStW == 4 * kStBlock, "four bins per thread");
+  __shared__ uint32_t wtot[kStBlock / 64];
+  const long long need = f->s2.need;
+  const int b0 = threadIdx.x * 4;
+  uint32_t v[4], sum = 0u;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    v[k] = b0 + k < W ? dhist[b0 + k] : 0u;
+    sum += v[k];
+  }
+  uint32_t total = 0u;
+  long long before = (long long)block_scan_excl<kStBlock / 64>(sum, wtot, total);
+  if (need <= 0 || !(before < need && need <= before + (long long)sum)) return;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    if (need <= before + (long long)v[k]) {
+      f->s2.prefix = (unsigned long long)(b0 + k);
+      f->s2.below = before;
+      return;
+    }
+    before += v[k];
+  }
+}
+
 int fail(int st, const char* fmt, ...) {
   char buf[256];
   va_list ap;
@@ -1108,7 +1349,7 @@ int fail(int st, const char* fmt, ...) {
 size_t a256(size_t v) { return (v + 255) / 256 * 256; }
 
 struct Layout {
-  size_t L8, lab, lab2, B, B2, parent, size, cnt, bsum, hist, g, dist, frank, rhist, lut, misc, end;
+  size_t L8, lab, lab2, B, B2, parent, size, cnt, bsum, hist, g, dist, frank, rhist, dhist, lut, misc, end;
 };
 
 Layout layout(int32_t W, int32_t H) {
@@ -1132,8 +1373,9 @@ Layout layout(int32_t W, int32_t H) {
   o.dist = take((size_t)std::max<int64_t>(N, seg_words) * 4);
   o.frank = take((size_t)N * 4);
   o.rhist = take(256 * 4);
+  o.dhist = take(kStW * 4);
   o.lut = take(256);
-  o.misc = take(1024);
+  o.misc = take(kMiscBytes);
   o.end = off;
   return o;
 }
@@ -1225,6 +1467,7 @@ int sbs_boundaries(const uint8_t* img, int32_t W, int32_t H, int32_t C, int64_t 
   const int64_t N = (int64_t)W * H;
   const Layout Lo = layout(W, H);
   if (workspace_bytes < Lo.end) return fail(SBS_ERR_INVALID_ARG, "workspace too small");
+  if ((uintptr_t)workspace & 255) return fail(SBS_ERR_INVALID_ARG, "workspace not 256-byte aligned");
   hipStream_t s = (hipStream_t)stream;
   char* base = (char*)workspace;
   uint8_t* L8 = (uint8_t*)(base + Lo.L8);
@@ -1243,7 +1486,7 @@ int sbs_boundaries(const uint8_t* img, int32_t W, int32_t H, int32_t C, int64_t 
   unsigned long long* total = (unsigned long long*)(misc + 128);
   DropRule* rule = (DropRule*)(misc + 192);
   FracState* fs = (FracState*)(misc + 256);
-  unsigned long long* n1 = (unsigned long long*)(misc + 512);
+  unsigned long long* n1 = (unsigned long long*)(misc + 1024);   // kN1Parts partial counts
   int32_t* gcol = (int32_t*)(base + Lo.g);
   int32_t* dist = (int32_t*)(base + Lo.dist);
   int32_t* frank = (int32_t*)(base + Lo.frank);
@@ -1253,7 +1496,7 @@ int sbs_boundaries(const uint8_t* img, int32_t W, int32_t H, int32_t C, int64_t 
 
   // Clear the small counters with kernels (no memset nodes if the caller captures the stream).
   hipLaunchKernelGGL(k_fill, dim3(1), dim3(kBlock), 0, s, (uint8_t*)hist, (int64_t)(256 * 8), (uint8_t)0);
-  hipLaunchKernelGGL(k_fill, dim3(1), dim3(kBlock), 0, s, (uint8_t*)misc, (int64_t)1024, (uint8_t)0);
+  hipLaunchKernelGGL(k_fill, dim3(1), dim3(kBlock), 0, s, (uint8_t*)misc, (int64_t)kMiscBytes, (uint8_t)0);
   launch_light(img, W, H, C, pitch, L8, g, s);
   // at most 512 blocks: each ends with up to 256 global adds
   hipLaunchKernelGGL(k_hist, dim3(std::min(grid_for((N + 15) / 16), 512)), dim3(kBlock), 0, s, L8, N, hist);
@@ -1332,21 +1575,30 @@ int sbs_boundaries(const uint8_t* img, int32_t W, int32_t H, int32_t C, int64_t 
       hipLaunchKernelGGL(k_dt_carry, dim3((W + kBlock - 1) / kBlock), dim3(kBlock), 0, s, W, nseg, last, first, up, down);
       hipLaunchKernelGGL(k_dt_col, dim3(gs), dim3(kBlock), 0, s, c, H, nseg, up, down, gcol);
     }
-    hipLaunchKernelGGL(k_dt_row, dim3(H < 16384 ? H : 16384), dim3(kBlock), 0, s, c, H, gcol, dist);
-    for (int sh = 24; sh >= 0; sh -= 8) {      // other pixels: distance
-      // Distances are below W (the border columns are selected), so digits at
-      // and above a power of two >= W are 0 for every candidate: the pick
-      // would add 0 to the prefix and to the count below, so the pass is skipped.
-      if (sh >= 8 && (int64_t)W <= (1LL << sh)) continue;
-      hipLaunchKernelGGL(k_rs_hist<2>, dim3(gr), dim3(kBlock), 0, s, c, &fs->s2, sh, rhist);
-      hipLaunchKernelGGL(k_rs_pick, dim3(1), dim3(256), 0, s, &fs->s2, sh, rhist);
+    if (W <= kStW && H <= 65535) {
+      // one block per CU (the table takes most of the LDS), each over rows in turn
+      uint32_t* dhist = (uint32_t*)(base + Lo.dhist);
+      hipLaunchKernelGGL(k_fill, dim3(1), dim3(kBlock), 0, s, (uint8_t*)dhist, (int64_t)(kStW * 4), (uint8_t)0);
+      hipLaunchKernelGGL(k_dt_row_st, dim3(H < 256 ? H : 256), dim3(kStBlock), 0, s, W, H, gcol, dist, cls, dhist);
+      hipLaunchKernelGGL(k_fc_dist_pick, dim3(1), dim3(kStBlock), 0, s, fs, dhist, W);
+    } else {
+      hipLaunchKernelGGL(k_dt_row, dim3(H < 16384 ? H : 16384), dim3(kBlock), 0, s, c, H, gcol, dist);
+      for (int sh = 24; sh >= 0; sh -= 8) {      // other pixels: distance
+        // Distances are below W (the border columns are selected), so digits at
+        // and above a power of two >= W are 0 for every candidate: the pick
+        // would add 0 to the prefix and to the count below, so the pass is skipped.
+        if (sh >= 8 && (int64_t)W <= (1LL << sh)) continue;
+        hipLaunchKernelGGL(k_rs_hist<2>, dim3(gr), dim3(kBlock), 0, s, c, &fs->s2, sh, rhist);
+        hipLaunchKernelGGL(k_rs_pick, dim3(1), dim3(256), 0, s, &fs->s2, sh, rhist);
+      }
     }
     hipLaunchKernelGGL(k_fc_after_dist, dim3(1), dim3(1), 0, s, fs);
     // other pixels at that distance: hash, over their compacted list (in the
     // column-distance buffer, free once the row pass has run)
     int32_t* cand = gcol;
     unsigned long long* ncand = (unsigned long long*)(misc + 640);
-    hipLaunchKernelGGL(k_fc_cands, dim3(gr), dim3(kBlock), 0, s, c, cand, ncand);
+    hipLaunchKernelGGL(k_fc_cands, dim3((unsigned)std::min<int64_t>((N + kCandPer - 1) / kCandPer, 8192)),
+                       dim3(kBlock), 0, s, c, cand, ncand);
     for (int sh = 56; sh >= 0; sh -= 8) {
       hipLaunchKernelGGL(k_rs_hist_cands, dim3(std::min(gr, 64)), dim3(kBlock), 0, s, cand, ncand,
                          (unsigned long long)seed, &fs->s3, sh, rhist);

@@ -136,23 +136,36 @@ __global__ __launch_bounds__(256) void k_rc_colseg(const int16_t* f, int32_t W, 
 
 // In place: seg_last[sg] becomes the nearest determined value above segment
 // sg (the last one of the segments before it), seg_first[sg] the nearest
-// below it (the first one of the segments after it); -1 where none.
+// below it (the first one of the segments after it); -1 where none. The
+// records are read kScanBatch at a time before any of them is written, so a
+// thread has that many loads in flight instead of one round trip per segment.
+constexpr int kScanBatch = 16;
 __global__ __launch_bounds__(256) void k_rc_segscan(int32_t W, int32_t nseg, int16_t* seg_first, int16_t* seg_last) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   if (x >= W) return;
   int16_t carry = -1;
-  for (int sg = 0; sg < nseg; ++sg) {
-    const int64_t q = (int64_t)sg * W + x;
-    const int16_t v = seg_last[q];
-    seg_last[q] = carry;
-    if (v >= 0) carry = v;
+  for (int s0 = 0; s0 < nseg; s0 += kScanBatch) {
+    int16_t v[kScanBatch];
+#pragma unroll
+    for (int k = 0; k < kScanBatch; ++k) v[k] = s0 + k < nseg ? seg_last[(int64_t)(s0 + k) * W + x] : (int16_t)-1;
+#pragma unroll
+    for (int k = 0; k < kScanBatch; ++k) {
+      if (s0 + k >= nseg) break;
+      seg_last[(int64_t)(s0 + k) * W + x] = carry;
+      if (v[k] >= 0) carry = v[k];
+    }
   }
   carry = -1;
-  for (int sg = nseg - 1; sg >= 0; --sg) {
-    const int64_t q = (int64_t)sg * W + x;
-    const int16_t v = seg_first[q];
-    seg_first[q] = carry;
-    if (v >= 0) carry = v;
+  for (int s1 = nseg - 1; s1 >= 0; s1 -= kScanBatch) {   // segments s1, s1 - 1, ...
+    int16_t v[kScanBatch];
+#pragma unroll
+    for (int k = 0; k < kScanBatch; ++k) v[k] = s1 - k >= 0 ? seg_first[(int64_t)(s1 - k) * W + x] : (int16_t)-1;
+#pragma unroll
+    for (int k = 0; k < kScanBatch; ++k) {
+      if (s1 - k < 0) break;
+      seg_first[(int64_t)(s1 - k) * W + x] = carry;
+      if (v[k] >= 0) carry = v[k];
+    }
   }
 }
 
@@ -166,6 +179,36 @@ __global__ __launch_bounds__(256) void k_rc_peek(const int16_t* f, int32_t W, in
   // nearest determined value above the segment, and below it (k_rc_segscan)
   int16_t last = above_seg[(int64_t)sg * W + x];
   int16_t below = below_seg[(int64_t)sg * W + x];
+  auto resolve = [&](int a, int b) -> uint8_t {
+    int r;
+    if (a < 0 && b < 0) r = 0;
+    else if (a < 0) r = b;
+    else if (b < 0) r = a;
+    else if (abs(a - b) > threshold) r = min(a, b);
+    else r = (a + b + 1) / 2;
+    return (uint8_t)r;
+  };
+  if (seglen == kColSeg) {
+    // the segment's values read at once, the nearest value above each row
+    // kept in registers
+    int16_t v[kColSeg], a[kColSeg];
+#pragma unroll
+    for (int k = 0; k < kColSeg; ++k) v[k] = y0 + k < y1 ? f[(int64_t)(y0 + k) * W + x] : (int16_t)-1;
+#pragma unroll
+    for (int k = 0; k < kColSeg; ++k) {
+      a[k] = last;
+      if (v[k] >= 0) last = v[k];
+    }
+#pragma unroll
+    for (int k = kColSeg - 1; k >= 0; --k) {
+      if (y0 + k >= y1) continue;
+      uint8_t r;
+      if (v[k] >= 0) { r = (uint8_t)v[k]; below = v[k]; }
+      else r = resolve(a[k], below);
+      out[(int64_t)(y0 + k) * W + x] = r;
+    }
+    return;
+  }
   for (int y = y0; y < y1; ++y) {
     const int16_t v = f[(int64_t)y * W + x];
     up[(int64_t)y * W + x] = last;
@@ -179,14 +222,7 @@ __global__ __launch_bounds__(256) void k_rc_peek(const int16_t* f, int32_t W, in
       below = v;
       continue;
     }
-    const int a = up[q], b = below;
-    int r;
-    if (a < 0 && b < 0) r = 0;
-    else if (a < 0) r = b;
-    else if (b < 0) r = a;
-    else if (abs(a - b) > threshold) r = min(a, b);
-    else r = (a + b + 1) / 2;
-    out[q] = (uint8_t)r;
+    out[q] = resolve(up[q], below);
   }
 }
 

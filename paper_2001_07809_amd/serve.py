@@ -15,11 +15,14 @@ inputs stay resident in HBM from arrival to completion). The server:
   latency (completion minus arrival).
 
 A request may also come as a raw frame without a list (``idx=None``, with a
-boundary fraction ``frac``): the server then runs the front end on the batch's
-stream first (lightness, histogram K-means, refinement, components, fraction
-control) into a list of exactly round(frac * W * H) pixels, whose length is
-known on the host, so nothing waits for the device. One front-end workspace
-per stream serves the batch's frames in turn and counts against the budget.
+boundary fraction ``frac``): the server then runs the front end first
+(lightness, histogram K-means, refinement, components, fraction control) into
+a list of exactly round(frac * W * H) pixels, whose length is known on the
+host, so nothing waits for the device. A batch's raw frames are dealt over
+``fe_lanes`` streams (its own and side streams shared by all batches), each
+with one front-end workspace for its frames in turn, so the many short
+front-end kernels of small frames overlap; the batch's stream waits for all
+lanes before the disparity search. The workspaces count against the budget.
 
 Each request's result depends only on its own frame: it is the same alone and
 in any mix (the GPU tests check this bit for bit).
@@ -70,7 +73,7 @@ class BudgetError(RuntimeError):
 
 class Server:
     def __init__(self, budget_bytes: int, max_inflight: int = 2, max_batch: int = 64, device=None,
-                 with_cost: bool = True):
+                 with_cost: bool = True, fe_lanes: int = 3):
         import torch
         self.torch = torch
         self.device = device or torch.device("cuda")
@@ -79,6 +82,8 @@ class Server:
         self.max_batch = max_batch
         self.with_cost = with_cost
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(max_inflight)]
+        # front-end side streams (default priority), shared by all batches
+        self.fe_side = [torch.cuda.Stream(device=self.device) for _ in range(max(0, fe_lanes - 1))]
         self._next_stream = 0
         self.waiting: list[Request] = []
         self.inflight: list[_Batch] = []
@@ -156,23 +161,39 @@ class Server:
         stream.wait_stream(torch.cuda.current_stream())   # inputs and outputs were made on the caller's stream
         frames = []
         keep = []
+        raw = [r for r in take if r.idx is None]
+        if raw:
+            # lists of the raw frames, dealt over the front-end lanes; each lane
+            # starts once the batch's stream has its inputs, and the batch's
+            # stream waits for every lane before the search
+            lanes = [stream] + self.fe_side[:len(raw) - 1]
+            ready = torch.cuda.Event()
+            ready.record(stream)
+            for li, lane in enumerate(lanes):
+                mine = raw[li::len(lanes)]
+                if lane is not stream:
+                    lane.wait_event(ready)
+                with torch.cuda.stream(lane):
+                    fw = max(int(sbs.lib().sbs_boundaries_workspace_bytes(*sbs._image_args(r.left)[:2])) for r in mine)
+                    fws = torch.empty(max(fw, 256), dtype=torch.uint8, device=self.device)
+                    cnt = torch.empty(1, dtype=torch.int64, device=self.device)
+                    keep += [fws, cnt]
+                    for r in mine:
+                        W, H, C, pitch = sbs._image_args(r.left)
+                        r.idx = torch.empty(self.list_length(r), dtype=torch.int32, device=self.device)
+                        if lane is not stream:
+                            r.idx.record_stream(stream)   # read by the search on the batch's stream
+                        if r.idx.numel() == 0:
+                            continue
+                        sbs._check(sbs.lib().sbs_boundaries(r.left.data_ptr(), W, H, C, pitch, r.K, 0, 50,
+                                                            float(r.frac), r.seed & (2**64 - 1), r.idx.data_ptr(),
+                                                            cnt.data_ptr(), None, None, fws.data_ptr(), fws.numel(),
+                                                            ctypes.c_void_p(lane.cuda_stream)))
+                if lane is not stream:
+                    done = torch.cuda.Event()
+                    done.record(lane)
+                    stream.wait_event(done)
         with torch.cuda.stream(stream):
-            raw = [r for r in take if r.idx is None]
-            if raw:
-                # lists of the raw frames, on this stream, one shared workspace
-                fw = max(int(sbs.lib().sbs_boundaries_workspace_bytes(*sbs._image_args(r.left)[:2])) for r in raw)
-                fws = torch.empty(max(fw, 256), dtype=torch.uint8, device=self.device)
-                cnt = torch.empty(1, dtype=torch.int64, device=self.device)
-                keep += [fws, cnt]
-                for r in raw:
-                    W, H, C, pitch = sbs._image_args(r.left)
-                    r.idx = torch.empty(self.list_length(r), dtype=torch.int32, device=self.device)
-                    if r.idx.numel() == 0:
-                        continue
-                    sbs._check(sbs.lib().sbs_boundaries(r.left.data_ptr(), W, H, C, pitch, r.K, 0, 50, float(r.frac),
-                                                        r.seed & (2**64 - 1), r.idx.data_ptr(), cnt.data_ptr(), None,
-                                                        None, fws.data_ptr(), fws.numel(),
-                                                        ctypes.c_void_p(stream.cuda_stream)))
             for r in take:
                 n = r.idx.numel()
                 r.disp = torch.empty(n, dtype=torch.uint8, device=self.device)

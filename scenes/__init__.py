@@ -11,6 +11,10 @@ are used:
   * ``middlebury_rgb``: 1390x1110 RGB, 20 regions, disparity 0..63, one
     0..8 px ramp, Gaussian-smoothed texture, additive noise sigma 2,
     block 21, dmax 63.
+  * ``tsukuba_paper``, ``middlebury_paper``: the same shapes with 60
+    regions of per-region mean lightness (and Gaussian texture), for the
+    paper's whole chain: its refinement keeps 16-19% of their pixels, the
+    share the paper reports for its Table 3 images.
   * ``uhd_rgb``: 4096x2304 RGB (the paper's video frame size), 40 regions,
     disparity 0..127, per-region mean lightness, block 31, dmax 127.
   * ``uhd_video``: 250 frames of ``uhd_rgb``-like scenes; regions step up to
@@ -71,6 +75,12 @@ PRESETS = {
     "tsukuba_gray": SceneSpec(384, 288, 1, 6, 15, texture=0, seed=101, block=15, dmax=15),
     "middlebury_rgb": SceneSpec(1390, 1110, 3, 20, 63, texture=1, ramp=1, noise_sigma=2.0,
                                 seed=102, block=21, dmax=63),
+    # the paper chain's inputs at the Tsukuba and Middlebury shapes: more
+    # regions with per-region mean lightness, so that K = 10 and the paper's
+    # refinement keep 16-19% of the pixels, as the paper reports for its images
+    "tsukuba_paper": SceneSpec(384, 288, 1, 60, 15, texture=1, mean_shift=1, seed=101, block=15, dmax=15),
+    "middlebury_paper": SceneSpec(1390, 1110, 3, 60, 63, texture=1, mean_shift=1, ramp=1, noise_sigma=2.0,
+                                  seed=102, block=21, dmax=63),
     "uhd_rgb": SceneSpec(4096, 2304, 3, 40, 127, texture=0, mean_shift=1, seed=103,
                          block=31, dmax=127),
     "uhd_video": SceneSpec(4096, 2304, 3, 40, 127, texture=0, mean_shift=1, motion=4, drift=1,

@@ -76,16 +76,18 @@ def test_injected_launch_failure_reported(monkeypatch):
     assert _call(W=0) == 1
 
 
-def _front(W=16, H=8, C=3, pitch=None, K=4, mode=0, min_cc=50, frac=-1.0, ptr=1, ws=None):
+def _front(W=16, H=8, C=3, pitch=None, K=4, mode=0, min_cc=50, frac=-1.0, ptr=1, ws=None, wsptr=256):
     lib = sbs.lib()
     p = ctypes.c_void_p(ptr) if ptr else None
+    w = ctypes.c_void_p(wsptr) if ptr else None
     need = lib.sbs_boundaries_workspace_bytes(W, H)
     return lib.sbs_boundaries(p, W, H, C, W * C if pitch is None else pitch, K, mode, min_cc, frac, 0, p, p, None,
-                              None, p, need if ws is None else ws, None)
+                              None, w, need if ws is None else ws, None)
 
 
 @pytest.mark.parametrize("kw", [dict(W=0), dict(H=0), dict(C=2), dict(pitch=10), dict(K=0), dict(K=65),
-                                dict(mode=2), dict(min_cc=-1), dict(ptr=0), dict(ws=16), dict(frac=1.5)])
+                                dict(mode=2), dict(min_cc=-1), dict(ptr=0), dict(ws=16), dict(frac=1.5),
+                                dict(wsptr=256 + 16)])
 def test_front_end_invalid_arguments_rejected_on_host(kw):
     assert _front(**kw) == 1
     assert sbs.lib().sbs_last_error().decode() != ""
@@ -109,3 +111,11 @@ def test_noalloc_rejects_frames_beyond_the_scratch_on_host():
     # invalid arguments still come first
     assert lib.sbs_sad_disparity_noalloc(p, p, 0, 8, 1, 8, p, 1, 3, 2, p, None, None) == 1
     assert lib.sbs_sad_disparity_noalloc(None, None, 8, 8, 1, 8, None, 0, 3, 2, None, None, None) == 0
+
+
+def test_probe_rejects_bad_arguments_on_host():
+    lib = sbs.lib()
+    r, t = ctypes.c_double(), ctypes.c_double()
+    assert lib.sbs_probe_sad_rate(0, 10, ctypes.byref(r), ctypes.byref(t)) == 1
+    assert lib.sbs_probe_sad_rate(10, 0, ctypes.byref(r), ctypes.byref(t)) == 1
+    assert lib.sbs_probe_sad_rate(10, 10, None, ctypes.byref(t)) == 1

@@ -144,3 +144,20 @@ def test_fraction_control_benchmark_frame(torch, sbs):
     got = sbs.boundaries(d, K=4, mode=0, min_cc=50, frac=0.18, seed=spec.seed).cpu().numpy().view(np.uint32)
     exp = oracle.boundaries(f.left, K=4, mode=0, min_cc=50, frac=0.18, seed=spec.seed)
     assert np.array_equal(got, exp)
+
+
+def test_fraction_control_wide_rows_and_far_pixels(torch, sbs):
+    """Fraction control into the distance class on rows wider than 4096 pixels
+    (searched outwards from each pixel) and up to 4096 (range minima), on
+    images whose few blobs leave most pixels far from any kept pixel."""
+    rng = np.random.default_rng(11)
+    for (H, W) in [(48, 4500), (96, 4096), (300, 257), (7, 4097)]:
+        img = np.full((H, W, 3), 60, np.uint8)
+        for _ in range(5):
+            y, x = int(rng.integers(0, H)), int(rng.integers(0, W))
+            img[max(0, y - 6):y + 6, max(0, x - 9):x + 9] = 200
+        d = torch.from_numpy(img).cuda()
+        for frac in (0.3, 0.6, 0.95):
+            got = sbs.boundaries(d, K=2, mode=0, min_cc=1, frac=frac, seed=5).cpu().numpy().view(np.uint32)
+            exp = oracle.boundaries(img, K=2, mode=0, min_cc=1, frac=frac, seed=5)
+            assert np.array_equal(got, exp), f"{H}x{W} frac {frac}"

@@ -18,7 +18,8 @@ def torch():
     return t
 
 
-@pytest.mark.parametrize("name,dmax,threshold", [("tsukuba_gray", 15, 0), ("middlebury_rgb", 63, 1)])
+@pytest.mark.parametrize("name,dmax,threshold", [("tsukuba_gray", 15, 0), ("middlebury_rgb", 63, 1),
+                                                  ("tsukuba_paper", 15, 0), ("middlebury_paper", 63, 1)])
 def test_paper_chain_matches_oracle_chain(torch, name, dmax, threshold):
     from paper_2001_07809_amd import pipeline
     f = scenes.make_frame(scenes.PRESETS[name])

@@ -50,11 +50,12 @@ def test_reconstruct_sparse_columns_across_segments(mods):
     determined pixels many 16-row segments away (the segment scan carries the
     nearest value above and below across a thousand empty segments), in
     columns with one, several or no determined pixels; heights on and off a
-    multiple of 16 and 64."""
+    multiple of 16 and 64; and over a million rows, where segments grow past
+    16 rows so that they fit the grid."""
     torch, sbs = mods
     rng = np.random.default_rng(6)
     for (W, H, n) in [(130, 700, 40), (3, 1000, 5), (64, 128, 10), (257, 64, 7), (90, 1, 3), (77, 641, 400),
-                      (5, 20001, 6), (2, 9000, 1)]:
+                      (5, 20001, 6), (2, 9000, 1), (2, 1100003, 40000)]:
         idx = np.sort(rng.choice(W * H, n, replace=False)).astype(np.uint32)
         disp = rng.integers(0, 40, n).astype(np.uint8)
         for threshold in (0, 3):

@@ -5,7 +5,7 @@ import pytest
 import scenes
 
 
-@pytest.mark.parametrize("name", ["tsukuba_gray", "serve_vga"])
+@pytest.mark.parametrize("name", ["tsukuba_gray", "serve_vga", "tsukuba_paper"])
 def test_unoccluded_pixels_match_across_views(name):
     spec = scenes.PRESETS[name]
     f = scenes.make_frame(spec)
