@@ -20,7 +20,7 @@
 
 namespace sbs {
 hipError_t launch_put_desc(FrameDev* table, const FrameDev* host, int nframes, hipStream_t s);
-hipError_t launch_prologue(const FrameDev* table, int f0, int nf, int max_rows, int max_tptr, WsHeader* hdr,
+hipError_t launch_prologue(const FrameDev* table, int f0, int nf, int max_rows, WsHeader* hdr,
                            hipStream_t s);
 hipError_t launch_finalize(const FrameDev* table, int f0, int nf, hipStream_t s);
 hipError_t launch_tile_grid(const FrameDev* table, int fi, int64_t nitems, int chunk, bool wide, hipStream_t s);
@@ -369,7 +369,7 @@ int run(const sbs_frame* frames, int nframes, void* workspace, size_t ws_bytes, 
   size_t off = kHeaderBytes + table_bytes(nframes);
   int64_t items = 0;
   QueueTotals qt{};
-  int max_rows = 1, max_tptr = 1;
+  int max_rows = 1;
   for (int i = 0; i < nframes; ++i) {
     const sbs_frame& f = frames[i];
     FrameLayout L = frame_layout(f, off, span[(size_t)i]);
@@ -414,14 +414,13 @@ int run(const sbs_frame* frames, int nframes, void* workspace, size_t ws_bytes, 
       qt.t[q] += tq * d.nch;
     }
     max_rows = std::max(max_rows, L.ph);
-    max_tptr = std::max(max_tptr, f.H * L.tpw);
   }
   hipError_t e = launch_put_desc(table, host.data(), nframes, s);
   if (e != hipSuccess) return hip_fail(e, "descriptor upload");
   if (mode == kPerFrame || mode == kSingle) {
     for (int i = 0; i < nframes; ++i) {
       if (frames[i].n == 0) continue;
-      e = launch_prologue(table, i, 1, host[(size_t)i].ph, frames[i].H * host[(size_t)i].tpw, hdr, s);
+      e = launch_prologue(table, i, 1, host[(size_t)i].ph, hdr, s);
       if (e != hipSuccess) return hip_fail(e, "prologue");
       hipEvent_t ev = nullptr;
       if (timed) timing_begin(s, &ev);
@@ -432,7 +431,7 @@ int run(const sbs_frame* frames, int nframes, void* workspace, size_t ws_bytes, 
       if (e != hipSuccess) return hip_fail(e, "finalize");
     }
   } else {
-    e = launch_prologue(table, 0, nframes, max_rows, max_tptr, hdr, s);
+    e = launch_prologue(table, 0, nframes, max_rows, hdr, s);
     if (e != hipSuccess) return hip_fail(e, "prologue");
     const bool wide = std::find(cpl.begin(), cpl.end(), 8) != cpl.end();
     // wide launches hold at most 12 wavefronts per CU (3 per SIMD)

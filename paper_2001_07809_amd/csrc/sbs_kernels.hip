@@ -7,9 +7,11 @@
 // the same rows, with replicate padding and ties to the smaller d.
 //
 // Tiled path (per frame; every kernel also runs over a whole batch of frames):
-//   k_check     clears the result keys, answers indices >= W*H, and finds out
+//   k_check     clears the result keys, answers indices >= W*H, finds out
 //               whether the list is in strictly increasing raster order
-//               (a repeated index sends it down the pixel-map path).
+//               (a repeated index sends it down the pixel-map path), and for
+//               each row and tile column the first list slot at or after the
+//               tile's first pixel (read by the tile kernel on ordered lists).
 //   k_prep      replicate-padded RGBx copy of the right image (one u32 per
 //               pixel, so one v_sad_u8 covers all channels of a pixel), and of
 //               the left image: whole, or only the edge bands that tiles
@@ -18,8 +20,6 @@
 //               list it also clears the pixel->slot map and row bits.
 //   k_scatter   unordered lists: map[p] = largest slot k with idx[k] == p, and
 //               per row one bit per 64-column group that holds a listed pixel.
-//   k_tptr      ordered lists: for each row and tile column, the first list
-//               slot at or after the tile's first pixel (binary search).
 //   k_tile_*    the column-sum kernel. One wavefront owns a tile of output
 //               columns x rows and a chunk of disparities. Each lane owns four
 //               adjacent window columns. Walking down the tile's rows it keeps,
@@ -80,7 +80,13 @@ __global__ void k_reset_head(WsHeader* h) {
 }
 
 // Keys cleared, out-of-range entries answered (and the first such slot
-// recorded), order checked.
+// recorded), order checked, and the (row, tile column) list ranges of
+// ordered lists found in the same pass: tptr[j] for the cell j = y * tpw + t
+// (key K_j = y W + min(t txo, W)) is the first slot whose index reaches K_j,
+// so entry k writes k into the cells whose keys lie in (idx[k-1], idx[k]]
+// and the last entry writes n into the cells after it. For a list that
+// turns out unordered the cells hold whatever its entries wrote; they are
+// not read then.
 // Four list entries per thread and step: 16-byte loads and stores where the
 // caller's arrays allow them (idx 16-byte aligned; keys live in the
 // workspace), entry by entry otherwise.
@@ -91,6 +97,30 @@ __global__ __launch_bounds__(256) void k_check(const FrameDev* __restrict__ tabl
   uint32_t* keys = f.keys;
   const bool vec = ((uintptr_t)idx & 15u) == 0;
   bool unsorted = false;
+  // cells with key <= p: y tpw + floor(x / txo) + 1 for p = y W + x < N
+  // (the quotients from fp64 reciprocals, then corrected by one step)
+  const int64_t cells = (int64_t)f.H * f.tpw;
+  const uint32_t W = (uint32_t)f.W, txo = (uint32_t)f.txo;
+  const double rw = 1.0 / (double)W, rt = 1.0 / (double)txo;
+  auto cells_upto = [&](uint32_t p) -> int64_t {
+    if ((int64_t)p >= N) return cells;
+    uint32_t y = (uint32_t)((double)p * rw);
+    if ((uint64_t)y * W > p) --y;
+    else if ((uint64_t)(y + 1) * W <= p) ++y;
+    const uint32_t x = p - y * W;
+    uint32_t t = (uint32_t)((double)x * rt);
+    if (t * txo > x) --t;
+    else if ((t + 1) * txo <= x) ++t;
+    return (int64_t)y * f.tpw + t + 1;
+  };
+  auto ranges = [&](int64_t k, int64_t lo, uint32_t p) {   // entry k holds p; cells from lo get k
+    const int64_t hi = cells_upto(p);
+    for (int64_t j = lo; j < hi; ++j) f.tptr[j] = (int32_t)k;
+    if (k == n - 1)
+      for (int64_t j = hi; j < cells; ++j) f.tptr[j] = (int32_t)n;
+  };
+  if (n == 0 && blockIdx.x == 0)
+    for (int64_t j = threadIdx.x; j < cells; j += blockDim.x) f.tptr[j] = 0;
   for (int64_t k = 4 * ((int64_t)blockIdx.x * blockDim.x + threadIdx.x); k < n; k += 4 * (int64_t)gridDim.x * blockDim.x) {
     uint32_t p[4] = {0u, 0u, 0u, 0u};
     if (vec && k + 3 < n) {
@@ -102,11 +132,13 @@ __global__ __launch_bounds__(256) void k_check(const FrameDev* __restrict__ tabl
       for (int j = 0; j < 4; ++j)
         if (k + j < n) { p[j] = idx[k + j]; keys[k + j] = 0xFFFFFFFFu; }
     }
-    if (k > 0 && idx[k - 1] >= p[0]) unsorted = true;
+    const uint32_t prev = k > 0 ? idx[k - 1] : 0u;
+    if (k > 0 && prev >= p[0]) unsorted = true;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       if (k + j >= n) break;
       if (j < 3 && k + j + 1 < n && p[j] >= p[j + 1]) unsorted = true;
+      ranges(k + j, k + j == 0 ? 0 : cells_upto(j == 0 ? prev : p[j - 1]), p[j]);
       if ((int64_t)p[j] >= N) {
         f.out_disp[k + j] = 255;
         if (f.out_cost) f.out_cost[k + j] = 0xFFFFFFFFu;
@@ -147,6 +179,7 @@ __device__ __forceinline__ u32x4 pack_group(const uint8_t* row, int ic0, int W, 
   return o;
 }
 
+constexpr int kPrepBatch = 5;   // right-copy groups per thread in flight (a 4096-pixel row: 1128 groups)
 __global__ __launch_bounds__(256) void k_prep(const FrameDev* __restrict__ table, int f0) {
   const FrameDev& f = table[f0 + blockIdx.y];
   const int W = f.W, H = f.H, C = f.C, r = f.r;
@@ -170,7 +203,37 @@ __global__ __launch_bounds__(256) void k_prep(const FrameDev* __restrict__ table
       const int gg = g < band0 ? g : g - band0 + band1;
       lo[gg] = pack_group(lrow, 4 * gg - f.lpad, W, C, la);
     }
-    for (int g = threadIdx.x; g < (f.rpw >> 2); g += blockDim.x) ro[g] = pack_group(rrow, 4 * g - f.rpad, W, C, ra);
+    const int ng = f.rpw >> 2;
+    if (C == 3 && ra) {
+      // RGB rows on 4-byte boundaries: kPrepBatch groups per thread with all
+      // their 12-byte loads in flight together (one round trip to memory
+      // for several groups, not one per group), border groups pixel by pixel
+      for (int g0 = 0; g0 < ng; g0 += kPrepBatch * (int)blockDim.x) {
+        u32x3 q[kPrepBatch];
+#pragma unroll
+        for (int u = 0; u < kPrepBatch; ++u) {
+          const int g = g0 + u * (int)blockDim.x + (int)threadIdx.x, ic0 = 4 * g - f.rpad;
+          if (g < ng && ic0 >= 0 && ic0 + 3 < W) q[u] = *(g_uint3*)(rrow + (int64_t)ic0 * 3);
+        }
+#pragma unroll
+        for (int u = 0; u < kPrepBatch; ++u) {
+          const int g = g0 + u * (int)blockDim.x + (int)threadIdx.x, ic0 = 4 * g - f.rpad;
+          if (g >= ng) break;
+          if (ic0 >= 0 && ic0 + 3 < W) {
+            u32x4 o;
+            o.x = q[u].x & 0xFFFFFFu;
+            o.y = (q[u].x >> 24) | ((q[u].y & 0xFFFFu) << 8);
+            o.z = (q[u].y >> 16) | ((q[u].z & 0xFFu) << 16);
+            o.w = q[u].z >> 8;
+            ro[g] = o;
+          } else {
+            ro[g] = pack_group(rrow, ic0, W, C, ra);
+          }
+        }
+      }
+    } else {
+      for (int g = threadIdx.x; g < ng; g += blockDim.x) ro[g] = pack_group(rrow, 4 * g - f.rpad, W, C, ra);
+    }
     if (unsorted && v >= r && v < r + H) {
       int32_t* mrow = f.map + (int64_t)(v - r) * W;
       for (int u = threadIdx.x; u < W; u += blockDim.x) mrow[u] = -1;
@@ -212,23 +275,6 @@ __global__ __launch_bounds__(256) void k_scatter(const FrameDev* __restrict__ ta
       if ((int)(threadIdx.x & 63) == leader) atomicOr((unsigned long long*)&f.rowbits[lw], (unsigned long long)acc);
       if (mine) pending = false;
     }
-  }
-}
-
-// Ordered lists: tptr[y * tpw + t] = first slot k with idx[k] >= y*W + min(t*txo, W).
-__global__ __launch_bounds__(256) void k_tptr(const FrameDev* __restrict__ table, int f0) {
-  const FrameDev& f = table[f0 + blockIdx.y];
-  if (*f.state & kUnsorted) return;
-  const int64_t total = (int64_t)f.H * f.tpw;
-  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < total; j += (int64_t)gridDim.x * blockDim.x) {
-    const int y = (int)(j / f.tpw), t = (int)(j % f.tpw);
-    const uint32_t key = (uint32_t)y * (uint32_t)f.W + (uint32_t)min(t * f.txo, f.W);
-    int64_t lo = 0, hi = f.n;
-    while (lo < hi) {
-      const int64_t mid = (lo + hi) >> 1;
-      if (f.idx[mid] < key) lo = mid + 1; else hi = mid;
-    }
-    f.tptr[j] = (int32_t)lo;
   }
 }
 
@@ -1104,17 +1150,13 @@ hipError_t launch_put_desc(FrameDev* table, const FrameDev* host, int nframes, h
   return hipGetLastError();
 }
 
-hipError_t launch_prologue(const FrameDev* table, int f0, int nf, int max_rows, int max_tptr, WsHeader* hdr,
+hipError_t launch_prologue(const FrameDev* table, int f0, int nf, int max_rows, WsHeader* hdr,
                            hipStream_t s) {
   hipLaunchKernelGGL(k_check, dim3(64, nf), dim3(256), 0, s, table, f0, hdr);
   int gx = max_rows < 2048 ? max_rows : 2048;
   if (gx < 1) gx = 1;
   hipLaunchKernelGGL(k_prep, dim3(gx, nf), dim3(256), 0, s, table, f0);
   hipLaunchKernelGGL(k_scatter, dim3(256, nf), dim3(256), 0, s, table, f0);
-  int gt = (max_tptr + 255) / 256;
-  if (gt > 1024) gt = 1024;
-  if (gt < 1) gt = 1;
-  hipLaunchKernelGGL(k_tptr, dim3(gt, nf), dim3(256), 0, s, table, f0);
   return hipGetLastError();
 }
 
