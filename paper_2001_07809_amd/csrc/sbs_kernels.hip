@@ -90,6 +90,7 @@ __global__ void k_reset_head(WsHeader* h) {
 // Four list entries per thread and step: 16-byte loads and stores where the
 // caller's arrays allow them (idx 16-byte aligned; keys live in the
 // workspace), entry by entry otherwise.
+constexpr int64_t kShortRange = 8;   // list-range cells one thread writes alone
 __global__ __launch_bounds__(256) void k_check(const FrameDev* __restrict__ table, int f0, WsHeader* hdr) {
   const FrameDev& f = table[f0 + blockIdx.y];
   const int64_t N = (int64_t)f.W * f.H, n = f.n;
@@ -113,12 +114,6 @@ __global__ __launch_bounds__(256) void k_check(const FrameDev* __restrict__ tabl
     else if ((t + 1) * txo <= x) ++t;
     return (int64_t)y * f.tpw + t + 1;
   };
-  auto ranges = [&](int64_t k, int64_t lo, uint32_t p) {   // entry k holds p; cells from lo get k
-    const int64_t hi = cells_upto(p);
-    for (int64_t j = lo; j < hi; ++j) f.tptr[j] = (int32_t)k;
-    if (k == n - 1)
-      for (int64_t j = hi; j < cells; ++j) f.tptr[j] = (int32_t)n;
-  };
   if (n == 0 && blockIdx.x == 0)
     for (int64_t j = threadIdx.x; j < cells; j += blockDim.x) f.tptr[j] = 0;
   for (int64_t k = 4 * ((int64_t)blockIdx.x * blockDim.x + threadIdx.x); k < n; k += 4 * (int64_t)gridDim.x * blockDim.x) {
@@ -134,11 +129,52 @@ __global__ __launch_bounds__(256) void k_check(const FrameDev* __restrict__ tabl
     }
     const uint32_t prev = k > 0 ? idx[k - 1] : 0u;
     if (k > 0 && prev >= p[0]) unsorted = true;
+    // cell ranges: entry k + j gets the cells from cells_upto(its predecessor)
+    // to cells_upto(its index); the last entry's range reaches the end with
+    // value n. Short ranges are written by their thread; long ones (a gap of
+    // many empty rows) by all active lanes of the wavefront together.
+    int64_t rlo[5], rhi[5];
+    int32_t rv[5];
+    {
+      int64_t below = k == 0 ? 0 : cells_upto(prev);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        rlo[j] = rhi[j] = 0;
+        rv[j] = (int32_t)(k + j);
+        if (k + j < n) {
+          const int64_t up = cells_upto(p[j]);
+          rlo[j] = below;
+          rhi[j] = up;
+          below = up;
+        }
+      }
+      const bool last = k <= n - 1 && n - 1 <= k + 3;
+      rlo[4] = last ? below : 0;
+      rhi[4] = last ? cells : 0;
+      rv[4] = (int32_t)n;
+    }
+#pragma unroll
+    for (int j = 0; j < 5; ++j)
+      if (rhi[j] - rlo[j] <= kShortRange)
+        for (int64_t c = rlo[j]; c < rhi[j]; ++c) f.tptr[c] = rv[j];
+    const uint64_t act = __builtin_amdgcn_ballot_w64(true);
+    const int rank = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(act >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)act, 0u));
+    const int nact = __builtin_popcountll(act);
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+      uint64_t m = __builtin_amdgcn_ballot_w64(rhi[j] - rlo[j] > kShortRange);
+      while (m) {
+        const int lead = __builtin_ctzll(m);
+        const int64_t lo = __shfl(rlo[j], lead, 64), hi = __shfl(rhi[j], lead, 64);
+        const int32_t v = __shfl(rv[j], lead, 64);
+        for (int64_t c = lo + rank; c < hi; c += nact) f.tptr[c] = v;
+        m &= m - 1;
+      }
+    }
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       if (k + j >= n) break;
       if (j < 3 && k + j + 1 < n && p[j] >= p[j + 1]) unsorted = true;
-      ranges(k + j, k + j == 0 ? 0 : cells_upto(j == 0 ? prev : p[j - 1]), p[j]);
       if ((int64_t)p[j] >= N) {
         f.out_disp[k + j] = 255;
         if (f.out_cost) f.out_cost[k + j] = 0xFFFFFFFFu;

@@ -197,6 +197,33 @@ def test_edge_cases(torch, sbs):
     assert d.size == 0
 
 
+def test_sparse_ordered_lists_with_long_gaps(torch, sbs):
+    """Ordered lists whose entries sit many rows apart: the check writes the
+    per-tile list ranges of the empty rows between two entries (and after the
+    last one) with the whole wavefront, and every tile row still finds its
+    entries. Also a list that is dense in one band and empty elsewhere, and
+    lists at the image's first and last pixels."""
+    rng = np.random.default_rng(12)
+    H, W = 1300, 2100
+    L = rng.integers(0, 256, (H, W, 3), dtype=np.uint8)
+    R = rng.integers(0, 256, (H, W, 3), dtype=np.uint8)
+    N = W * H
+    band = np.arange(600 * W, 603 * W, 5)
+    cases = {
+        "seven spread": np.sort(rng.choice(N, 7, replace=False)),
+        "first and last": np.array([0, N - 1]),
+        "first only": np.array([0]),
+        "last only": np.array([N - 1]),
+        "one in the middle": np.array([N // 2 + 17]),
+        "dense band": band,
+        "band and corners": np.concatenate([[3], band, [N - 2]]),
+    }
+    for name, idx in cases.items():
+        idx = idx.astype(np.uint32)
+        exp = oracle.sad(L, R, idx, 9, 40)
+        assert_parity(run_gpu(torch, sbs, L, R, idx, 9, 40), exp, name)
+
+
 def test_row_pitch_and_no_cost_and_stream(torch, sbs):
     rng = np.random.default_rng(6)
     big = rng.integers(0, 256, (60, 120, 3), dtype=np.uint8)
