@@ -1260,15 +1260,31 @@ __global__ __launch_bounds__(kStBlock) void k_dt_row_st(int32_t W, int32_t H, co
   for (int b = threadIdx.x; b < kStW; b += kStBlock) hloc[b] = 0u;
   const int levels = 32 - __builtin_clz((unsigned)W);   // 2^(levels-1) <= W
   const int run = (W + kStBlock - 1) / kStBlock;
+  // the next row's column distances are loaded while this row is searched
+  constexpr int kPer = kStW / kStBlock;
+  int32_t nxt[kPer];
+  auto fetch = [&](int yy) {
+    const int32_t* grow = g + (int64_t)yy * W;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int x = threadIdx.x + k * kStBlock;
+      nxt[k] = x < W ? grow[x] : 0;
+    }
+  };
+  if ((int)blockIdx.x < H) fetch(blockIdx.x);
   for (int y = blockIdx.x; y < H; y += gridDim.x) {
-    const int32_t* grow = g + (int64_t)y * W;
-    for (int x = threadIdx.x; x < W; x += kStBlock) st[0][x] = (uint16_t)min(grow[x], 65535);
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int x = threadIdx.x + k * kStBlock;
+      if (x < W) st[0][x] = (uint16_t)min(nxt[k], 65535);
+    }
     __syncthreads();
     for (int j = 1; j < levels; ++j) {
       const int h = 1 << (j - 1);
       for (int x = threadIdx.x; x + 2 * h <= W; x += kStBlock) st[j][x] = min(st[j - 1][x], st[j - 1][x + h]);
       __syncthreads();
     }
+    if (y + (int)gridDim.x < H) fetch(y + gridDim.x);
     // minimum of g over [l, r], 0 <= l <= r < W
     auto rmq = [&](int l, int r) -> int {
       const int j = 31 - __builtin_clz((unsigned)(r - l + 1));

@@ -48,6 +48,7 @@ __global__ __launch_bounds__(256) void k_rc_scatter(const uint32_t* idx, int64_t
 // right-to-left pass finds the nearest listed pixel on the right the same
 // way, takes the one on the left from the quarters before where it was
 // missing, and decides. Output: f[p] = disparity or -1 (undetermined).
+constexpr int kFillChunks = 16;   // 64-pixel chunks per quarter held in registers (rows up to 4096 pixels)
 __global__ __launch_bounds__(kRowThreads) void k_rc_fill(const int32_t* slot, const uint8_t* disp, int32_t W,
                                                            int32_t H, int16_t* f) {
   constexpr int kWaves = kRowThreads / 64;
@@ -57,6 +58,57 @@ __global__ __launch_bounds__(kRowThreads) void k_rc_fill(const int32_t* slot, co
   const int c0 = min(wv * per, nch), c1 = min(c0 + per, nch);
   const uint64_t upto = (2ull << lane) - 1ull;    // bits 0 .. lane
   const uint64_t from = ~((1ull << lane) - 1ull); // bits lane .. 63
+  if (per <= kFillChunks) {
+    // a quarter of at most kFillChunks chunks: its slots are loaded at once,
+    // then its disparities, and both passes run on registers (one round trip
+    // to memory for each, and the row is written once)
+    for (int y = blockIdx.x; y < H; y += gridDim.x) {
+      const int32_t* srow = slot + (int64_t)y * W;
+      int16_t* frow = f + (int64_t)y * W;
+      int v[kFillChunks];
+#pragma unroll
+      for (int i = 0; i < kFillChunks; ++i) {
+        const int x = ((c0 + i) << 6) + lane;
+        v[i] = (c0 + i < c1 && x < W) ? srow[x] : -1;   // slot here, disparity below
+      }
+#pragma unroll
+      for (int i = 0; i < kFillChunks; ++i) v[i] = v[i] >= 0 ? (int)disp[v[i]] : -1;
+      int lft[kFillChunks];   // nearest listed value at or left of the pixel within the quarter, -2: none
+      int carry = -2, first = -1;
+#pragma unroll
+      for (int i = 0; i < kFillChunks; ++i) {
+        const uint64_t m = __builtin_amdgcn_ballot_w64(v[i] >= 0);
+        const uint64_t b = m & upto;
+        const int left = __shfl(v[i], b ? 63 - __builtin_clzll(b) : 0);
+        lft[i] = b ? left : carry;
+        if (m) {
+          if (first < 0) first = __shfl(v[i], __builtin_ctzll(m));
+          carry = __shfl(v[i], 63 - __builtin_clzll(m));
+        }
+      }
+      if (lane == 0) { q_first[wv] = first; q_last[wv] = carry < 0 ? -1 : carry; }
+      __syncthreads();
+      int cl = -1, cr = -1;   // nearest listed value in the quarters to the left / right
+      for (int j = wv - 1; j >= 0 && cl < 0; --j) cl = q_last[j];
+      for (int j = wv + 1; j < kWaves && cr < 0; ++j) cr = q_first[j];
+      __syncthreads();   // the next row rewrites q_first / q_last
+      carry = cr;
+#pragma unroll
+      for (int i = kFillChunks - 1; i >= 0; --i) {
+        const int x = ((c0 + i) << 6) + lane;
+        const uint64_t m = __builtin_amdgcn_ballot_w64(v[i] >= 0);
+        const uint64_t b = m & from;
+        const int right = b ? __shfl(v[i], __builtin_ctzll(b)) : carry;
+        if (c0 + i < c1 && x < W) {
+          int left = lft[i];
+          if (left == -2) left = cl;
+          frow[x] = (int16_t)(v[i] >= 0 ? v[i] : ((left >= 0 && left == right) ? left : -1));
+        }
+        if (m) carry = __shfl(v[i], __builtin_ctzll(m));
+      }
+    }
+    return;
+  }
   for (int y = blockIdx.x; y < H; y += gridDim.x) {
     const int32_t* srow = slot + (int64_t)y * W;
     int16_t* frow = f + (int64_t)y * W;

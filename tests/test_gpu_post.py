@@ -30,6 +30,26 @@ def test_reconstruct_matches_oracle(mods, threshold):
     np.testing.assert_array_equal(got.cpu().numpy(), exp)
 
 
+@pytest.mark.parametrize("W", [4096, 4097, 6000])
+def test_reconstruct_row_fill_at_and_past_4096_columns(mods, W):
+    """Rows of up to 4096 pixels keep a quarter row per wavefront in
+    registers; wider rows walk it chunk by chunk. Runs of equal disparities
+    between listed pixels, listed pixels at both row ends, empty rows."""
+    torch, sbs = mods
+    rng = np.random.default_rng(W)
+    H = 24
+    idx = np.sort(rng.choice(W * H, W * H // 9, replace=False))
+    idx = np.unique(np.concatenate([idx, np.arange(H // 2) * W, np.arange(H // 2) * W + W - 1])).astype(np.uint32)
+    idx = idx[(idx // W) % 7 != 3]                                # some rows without listed pixels
+    disp = rng.integers(0, 4, idx.size).astype(np.uint8)           # few values: many equal neighbours
+    for threshold in (0, 2):
+        exp = oracle.reconstruct(idx, disp, W, H, threshold)
+        got = sbs.reconstruct(torch.from_numpy(idx.view(np.int32)).cuda(), torch.from_numpy(disp).cuda(), W, H,
+                              threshold)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(got.cpu().numpy(), exp, err_msg=f"{W}x{H} t {threshold}")
+
+
 def test_reconstruct_unordered_duplicates_and_edges(mods):
     torch, sbs = mods
     rng = np.random.default_rng(5)
