@@ -244,129 +244,169 @@ __global__ __launch_bounds__(kBlock) void k_label(const uint8_t* __restrict__ L8
 }
 
 // ---------------------------------------------------------------------------
-// 3x3 stencils.
-//   op 0: erosion (min), op 1: dilation (max), replicate border;
-//   op 2: Moore boundary (1 iff an in-image 8-neighbour differs);
-//   op 3: 'fill' (a 0 whose eight neighbours are all 1 becomes 1; outside = 0);
-//   op 4: 'remove' (a 1 whose four 4-neighbours are all 1 becomes 0; outside = 0).
-// One pixel, with every border rule spelled out.
-template <int OP>
-__device__ __forceinline__ uint8_t stencil_px(const uint8_t* __restrict__ in, int32_t W, int32_t H, int x, int y) {
-  const uint8_t v = in[(int64_t)y * W + x];
-  auto at = [&](int yy, int xx) -> int { return in[(int64_t)yy * W + xx]; };
-  uint8_t r = v;
-  if constexpr (OP == 0 || OP == 1) {
-    for (int j = -1; j <= 1; ++j)
-      for (int i = -1; i <= 1; ++i) {
-        const int u = at(min(max(y + j, 0), H - 1), min(max(x + i, 0), W - 1));
-        r = OP == 0 ? (uint8_t)min((int)r, u) : (uint8_t)max((int)r, u);
-      }
-  } else if constexpr (OP == 2) {
-    r = 0;
-    for (int j = -1; j <= 1; ++j)
-      for (int i = -1; i <= 1; ++i) {
-        const int yy = y + j, xx = x + i;
-        if ((i || j) && yy >= 0 && yy < H && xx >= 0 && xx < W && at(yy, xx) != v) r = 1;
-      }
-  } else if constexpr (OP == 3) {
-    if (!v) {
-      bool all = true;
-      for (int j = -1; j <= 1; ++j)
-        for (int i = -1; i <= 1; ++i) {
-          const int yy = y + j, xx = x + i;
-          if ((i || j) && (yy < 0 || yy >= H || xx < 0 || xx >= W || !at(yy, xx))) all = false;
+// 3x3 refinement stencils (one fused kernel per mode below):
+//   erosion (min) and dilation (max) with replicate borders;
+//   Moore boundary: 1 iff an in-image 8-neighbour differs;
+//   'fill': a 0 whose eight neighbours are all 1 becomes 1 (outside = 0);
+//   'remove': a 1 whose four 4-neighbours are all 1 becomes 0 (outside = 0).
+
+// The configured refinement in one pass over the image: erode, dilate
+// (open), dilate, erode (close) with replicate borders, then the Moore
+// boundary, per tile of kMorphT x kMorphT pixels with a 5-pixel halo held in
+// LDS (one HBM read of the labels and one write of the boundary map, instead
+// of five of each). Each step runs on a box one pixel narrower on every side
+// than the one before, so its neighbours are always in the box. Clamping a
+// neighbour into the image is the same as reading a frame whose cells
+// outside the image repeat the nearest cell inside: the labels are loaded
+// that way, and on tiles at an image edge every step's result is repeated
+// into its outside cells before the next step reads them. The boundary step
+// ignores neighbours outside the image. `closed`
+// (optional) receives the labels after the close.
+constexpr int kMorphT = 64, kMorphHalo = 5, kMorphF = kMorphT + 2 * kMorphHalo;   // frame: 74 x 74
+constexpr int kMorphP = kMorphF + 2;   // LDS row pitch
+__global__ __launch_bounds__(kBlock) void k_morph_refine(const uint8_t* __restrict__ lab, int32_t W, int32_t H,
+                                                         uint8_t* __restrict__ B, uint8_t* __restrict__ closed) {
+  __shared__ uint8_t buf[2][kMorphF * kMorphP];
+  const int x0 = blockIdx.x * kMorphT - kMorphHalo, y0 = blockIdx.y * kMorphT - kMorphHalo;   // frame origin
+  const bool edge = x0 < 0 || y0 < 0 || x0 + kMorphF > W || y0 + kMorphF > H;
+  for (int c = threadIdx.x; c < kMorphF * kMorphF; c += kBlock) {
+    const int fy = c / kMorphF, fx = c - fy * kMorphF;
+    const int gy = min(max(y0 + fy, 0), H - 1), gx = min(max(x0 + fx, 0), W - 1);
+    buf[0][fy * kMorphP + fx] = lab[(int64_t)gy * W + gx];
+  }
+  __syncthreads();
+  // steps 1..4 on the frame inset by k: erode, dilate, dilate, erode
+#pragma unroll
+  for (int k = 1; k <= 4; ++k) {
+    const uint8_t* src = buf[(k - 1) & 1];
+    uint8_t* dst = buf[k & 1];
+    const bool mx = k == 2 || k == 3;
+    const int n = kMorphF - 2 * k;
+    for (int c = threadIdx.x; c < n * n; c += kBlock) {
+      const int fy = k + c / n, fx = k + c % n;
+      const int gy = y0 + fy, gx = x0 + fx;
+      if (edge && (gy < 0 || gy >= H || gx < 0 || gx >= W)) continue;   // filled below
+      const uint8_t* q = src + fy * kMorphP + fx;
+      int r = q[0];
+#pragma unroll
+      for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+        for (int dx = -1; dx <= 1; ++dx) {
+          const int u = q[dy * kMorphP + dx];
+          r = mx ? max(r, u) : min(r, u);
         }
-      r = all ? 1 : 0;
+      dst[fy * kMorphP + fx] = (uint8_t)r;
     }
-  } else {
-    auto in_at = [&](int yy, int xx) -> int { return (yy < 0 || yy >= H || xx < 0 || xx >= W) ? 0 : at(yy, xx); };
-    if (v && in_at(y - 1, x) && in_at(y + 1, x) && in_at(y, x - 1) && in_at(y, x + 1)) r = 0;
-  }
-  return r;
-}
-
-// One thread per pixel of a 2-D grid (any width).
-template <int OP>
-__global__ __launch_bounds__(kBlock) void k_stencil(const uint8_t* __restrict__ in, int32_t W, int32_t H,
-                                                    uint8_t* __restrict__ out) {
-  const int x = blockIdx.x * 64 + (threadIdx.x & 63);
-  const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
-  if (x >= W || y >= H) return;
-  out[(int64_t)y * W + x] = stencil_px<OP>(in, W, H, x, y);
-}
-
-// Widths that are a multiple of 4: four pixels per thread (256 columns x 4
-// rows per block). Away from the image's edges a thread reads three aligned
-// words per row (the four pixels and one word on each side for the
-// neighbours) and writes one word; threads touching an edge take the
-// per-pixel rules.
-template <int OP>
-__global__ __launch_bounds__(kBlock) void k_stencil4(const uint8_t* __restrict__ in, int32_t W, int32_t H,
-                                                     uint8_t* __restrict__ out) {
-  const int x = (blockIdx.x * 64 + (threadIdx.x & 63)) * 4;
-  const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
-  if (x >= W || y >= H) return;
-  if (x < 4 || x + 8 > W || y < 1 || y + 1 >= H) {
-    uint32_t w = 0;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) w |= (uint32_t)stencil_px<OP>(in, W, H, x + i, y) << (8 * i);
-    *(uint32_t*)(out + (int64_t)y * W + x) = w;
-    return;
-  }
-  // q[j][0 .. 5]: row y - 1 + j, columns x - 1 .. x + 4
-  int q[3][6];
-#pragma unroll
-  for (int j = 0; j < 3; ++j) {
-    const uint32_t* row = (const uint32_t*)(in + (int64_t)(y - 1 + j) * W + x);
-    const uint32_t a = row[-1], b = row[0], c = row[1];
-    q[j][0] = (int)(a >> 24);
-#pragma unroll
-    for (int i = 0; i < 4; ++i) q[j][1 + i] = (int)((b >> (8 * i)) & 0xFFu);
-    q[j][5] = (int)(c & 0xFFu);
-  }
-  uint32_t w = 0;
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int v = q[1][1 + i];
-    int r = v;
-    if constexpr (OP == 0 || OP == 1) {
-#pragma unroll
-      for (int j = 0; j < 3; ++j)
-#pragma unroll
-        for (int k = 0; k < 3; ++k) r = OP == 0 ? min(r, q[j][i + k]) : max(r, q[j][i + k]);
-    } else if constexpr (OP == 2) {
-      bool d = false;
-#pragma unroll
-      for (int j = 0; j < 3; ++j)
-#pragma unroll
-        for (int k = 0; k < 3; ++k) d |= q[j][i + k] != v;
-      r = d ? 1 : 0;
-    } else if constexpr (OP == 3) {
-      if (!v) {
-        bool all = true;
-#pragma unroll
-        for (int j = 0; j < 3; ++j)
-#pragma unroll
-          for (int k = 0; k < 3; ++k)
-            if (j != 1 || k != 1) all = all && q[j][i + k] != 0;
-        r = all ? 1 : 0;
+    __syncthreads();
+    if (edge) {
+      for (int c = threadIdx.x; c < n * n; c += kBlock) {
+        const int fy = k + c / n, fx = k + c % n;
+        const int gy = y0 + fy, gx = x0 + fx;
+        if (gy >= 0 && gy < H && gx >= 0 && gx < W) continue;
+        const int cy = min(max(gy, 0), H - 1) - y0, cx = min(max(gx, 0), W - 1) - x0;
+        dst[fy * kMorphP + fx] = dst[cy * kMorphP + cx];
       }
-    } else {
-      if (v && q[0][1 + i] && q[2][1 + i] && q[1][i] && q[1][i + 2]) r = 0;
+      __syncthreads();
     }
-    w |= (uint32_t)r << (8 * i);
   }
-  *(uint32_t*)(out + (int64_t)y * W + x) = w;
+  // boundary of the tile (frame cells halo .. halo + T - 1) from the closed labels in buf[0]
+  const uint8_t* lb = buf[0];
+  for (int c = threadIdx.x; c < kMorphT * kMorphT; c += kBlock) {
+    const int ty = c / kMorphT, tx = c - ty * kMorphT;
+    const int fy = kMorphHalo + ty, fx = kMorphHalo + tx;
+    const int gy = y0 + fy, gx = x0 + fx;
+    if (gy >= H || gx >= W) continue;
+    const uint8_t* q = lb + fy * kMorphP + fx;
+    const int v = q[0];
+    bool d = false;
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+      for (int dx = -1; dx <= 1; ++dx) {
+        if (!dy && !dx) continue;
+        const bool in = !edge || (gy + dy >= 0 && gy + dy < H && gx + dx >= 0 && gx + dx < W);
+        d |= in && q[dy * kMorphP + dx] != v;
+      }
+    B[(int64_t)gy * W + gx] = d ? 1 : 0;
+    if (closed) closed[(int64_t)gy * W + gx] = (uint8_t)v;
+  }
 }
 
-// Launches op OP over the image: four pixels per thread where rows are
-// 4-byte aligned, one otherwise.
-template <int OP>
-void launch_stencil(const uint8_t* in, int32_t W, int32_t H, uint8_t* out, hipStream_t s) {
-  if ((W & 3) == 0 && ((uintptr_t)in & 3) == 0 && ((uintptr_t)out & 3) == 0)
-    hipLaunchKernelGGL(k_stencil4<OP>, dim3((W / 4 + 63) / 64, (H + 3) / 4), dim3(kBlock), 0, s, in, W, H, out);
-  else
-    hipLaunchKernelGGL(k_stencil<OP>, dim3((W + 63) / 64, (H + 3) / 4), dim3(kBlock), 0, s, in, W, H, out);
+// The paper's refinement in one pass over the image: the Moore boundary of
+// the labels, then 'fill', then 'remove', per tile
+// of kMorphT x kMorphT pixels with a 3-pixel halo in LDS. The boundary step
+// ignores neighbours outside the image; 'fill' and 'remove' take them as 0,
+// so every step's cells outside the image are set to 0 before the next
+// step reads them.
+constexpr int kPaperHalo = 3, kPaperF = kMorphT + 2 * kPaperHalo, kPaperP = kPaperF + 2;   // frame: 70 x 70
+__global__ __launch_bounds__(kBlock) void k_paper_refine(const uint8_t* __restrict__ lab, int32_t W, int32_t H,
+                                                         uint8_t* __restrict__ B) {
+  __shared__ uint8_t buf[2][kPaperF * kPaperP];
+  const int x0 = blockIdx.x * kMorphT - kPaperHalo, y0 = blockIdx.y * kMorphT - kPaperHalo;   // frame origin
+  const bool edge = x0 < 0 || y0 < 0 || x0 + kPaperF > W || y0 + kPaperF > H;
+  auto inside = [&](int gy, int gx) { return gy >= 0 && gy < H && gx >= 0 && gx < W; };
+  for (int c = threadIdx.x; c < kPaperF * kPaperF; c += kBlock) {
+    const int fy = c / kPaperF, fx = c - fy * kPaperF;
+    const int gy = min(max(y0 + fy, 0), H - 1), gx = min(max(x0 + fx, 0), W - 1);
+    buf[0][fy * kPaperP + fx] = lab[(int64_t)gy * W + gx];
+  }
+  __syncthreads();
+  // step 1: boundary (in-image neighbours only) on the frame inset by 1
+  {
+    constexpr int n = kPaperF - 2;
+    for (int c = threadIdx.x; c < n * n; c += kBlock) {
+      const int fy = 1 + c / n, fx = 1 + c % n;
+      const int gy = y0 + fy, gx = x0 + fx;
+      uint8_t r = 0;
+      if (!edge || inside(gy, gx)) {
+        const uint8_t* q = buf[0] + fy * kPaperP + fx;
+        const int v = q[0];
+        bool d = false;
+#pragma unroll
+        for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+          for (int dx = -1; dx <= 1; ++dx)
+            if (dy || dx) d |= (!edge || inside(gy + dy, gx + dx)) && q[dy * kPaperP + dx] != v;
+        r = d ? 1 : 0;
+      }
+      buf[1][fy * kPaperP + fx] = r;   // 0 outside the image
+    }
+  }
+  __syncthreads();
+  // step 2: 'fill' (a 0 whose eight neighbours are all 1 becomes 1) on the frame inset by 2
+  {
+    constexpr int n = kPaperF - 4;
+    for (int c = threadIdx.x; c < n * n; c += kBlock) {
+      const int fy = 2 + c / n, fx = 2 + c % n;
+      const uint8_t* q = buf[1] + fy * kPaperP + fx;
+      uint8_t r = 0;
+      if (!edge || inside(y0 + fy, x0 + fx)) {
+        r = q[0];
+        if (!r) {
+          bool all = true;
+#pragma unroll
+          for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+            for (int dx = -1; dx <= 1; ++dx)
+              if (dy || dx) all &= q[dy * kPaperP + dx] != 0;
+          r = all ? 1 : 0;
+        }
+      }
+      buf[0][fy * kPaperP + fx] = r;   // 0 outside the image
+    }
+  }
+  __syncthreads();
+  // step 3: 'remove' (a 1 whose four 4-neighbours are all 1 becomes 0) on the tile
+  for (int c = threadIdx.x; c < kMorphT * kMorphT; c += kBlock) {
+    const int ty = c / kMorphT, tx = c - ty * kMorphT;
+    const int fy = kPaperHalo + ty, fx = kPaperHalo + tx;
+    const int gy = y0 + fy, gx = x0 + fx;
+    if (gy >= H || gx >= W) continue;
+    const uint8_t* q = buf[0] + fy * kPaperP + fx;
+    uint8_t r = q[0];
+    if (r && q[-kPaperP] && q[kPaperP] && q[-1] && q[1]) r = 0;
+    B[(int64_t)gy * W + gx] = r;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1365,7 +1405,7 @@ int fail(int st, const char* fmt, ...) {
 size_t a256(size_t v) { return (v + 255) / 256 * 256; }
 
 struct Layout {
-  size_t L8, lab, lab2, B, B2, parent, size, cnt, bsum, hist, g, dist, frank, rhist, dhist, lut, misc, end;
+  size_t L8, lab, lab2, B, parent, size, cnt, bsum, hist, g, dist, frank, rhist, dhist, lut, misc, end;
 };
 
 Layout layout(int32_t W, int32_t H) {
@@ -1379,7 +1419,6 @@ Layout layout(int32_t W, int32_t H) {
   o.lab = take(N);
   o.lab2 = take(N);
   o.B = take(N);
-  o.B2 = take(N);
   o.parent = take((size_t)N * 4);
   o.size = take((size_t)N * 4);
   o.cnt = take(((size_t)N + 1) * 4);
@@ -1490,7 +1529,6 @@ int sbs_boundaries(const uint8_t* img, int32_t W, int32_t H, int32_t C, int64_t 
   uint8_t* lab = (uint8_t*)(base + Lo.lab);
   uint8_t* lab2 = (uint8_t*)(base + Lo.lab2);
   uint8_t* B = (uint8_t*)(base + Lo.B);
-  uint8_t* B2 = (uint8_t*)(base + Lo.B2);
   int32_t* parent = (int32_t*)(base + Lo.parent);
   int32_t* size = (int32_t*)(base + Lo.size);
   int32_t* cnt = (int32_t*)(base + Lo.cnt);
@@ -1520,18 +1558,17 @@ int sbs_boundaries(const uint8_t* img, int32_t W, int32_t H, int32_t C, int64_t 
   hipLaunchKernelGGL(k_label, dim3(g), dim3(kBlock), 0, s, L8, N, lut, lab);
   const uint8_t* labels = lab;
   if (mode == 0) {
-    launch_stencil<0>(lab, W, H, lab2, s);    // erode
-    launch_stencil<1>(lab2, W, H, lab, s);    // dilate: open
-    launch_stencil<1>(lab, W, H, lab2, s);    // dilate
-    launch_stencil<0>(lab2, W, H, lab, s);    // erode: close
-    launch_stencil<2>(lab, W, H, B, s);       // boundary
+    // open, close and boundary in one pass; the closed labels go straight to
+    // out_labels when asked for
+    const dim3 gm((W + kMorphT - 1) / kMorphT, (H + kMorphT - 1) / kMorphT);
+    hipLaunchKernelGGL(k_morph_refine, gm, dim3(kBlock), 0, s, lab, W, H, B, out_labels);
+    labels = nullptr;
   } else {
-    launch_stencil<2>(lab, W, H, B2, s);      // boundary
-    launch_stencil<3>(B2, W, H, B, s);        // fill
-    launch_stencil<4>(B, W, H, B2, s);        // remove
-    B = B2;
+    // boundary, fill and remove in one pass
+    const dim3 gm((W + kMorphT - 1) / kMorphT, (H + kMorphT - 1) / kMorphT);
+    hipLaunchKernelGGL(k_paper_refine, gm, dim3(kBlock), 0, s, lab, W, H, B);
   }
-  if (out_labels) {
+  if (out_labels && labels) {
     const hipError_t ce = hipMemcpyAsync(out_labels, labels, (size_t)N, hipMemcpyDeviceToDevice, s);
     if (ce != hipSuccess) return fail(SBS_ERR_HIP, "boundaries: %s", hipGetErrorString(ce));
   }
