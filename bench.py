@@ -542,6 +542,11 @@ def paper_main(args):
         p = pipeline.PaperParams(dmax=dmax, threshold=thr, ranges=((0, dmax // 3),))
         stages = ["lightness", "front_end", "sad", "reconstruct", "blur"]
         times = {k: [] for k in stages}
+        # the disparity search's plan (the default for a single frame)
+        l8 = sbs.lightness(L); r8 = sbs.lightness(R)
+        lst = sbs.boundaries(l8, K=p.K, mode=p.mode)
+        d0 = torch.empty(lst.numel(), dtype=torch.uint8, device="cuda")
+        plan = sbs.get_plan(sbs.make_frame(l8, r8, lst, p.block, p.dmax, d0, None))
         for it in range(args.warmup + args.steps):
             ev = [torch.cuda.Event(enable_timing=True) for _ in range(len(stages) + 1)]
             ev[0].record()
@@ -565,7 +570,7 @@ def paper_main(args):
         b_list = pipeline.bad_pixel_percent(dl, f.gt.reshape(-1)[idx], mask=occ[idx] == 0)
         b_dense = pipeline.bad_pixel_percent(dense.cpu().numpy().reshape(-1), f.gt.reshape(-1), mask=occ == 0)
         rec = {"size": f"{W}x{H}x{spec.C}", "block": p.block, "dmax": dmax, "K": p.K, "threshold": thr,
-               "listed_fraction": round(idx.size / (W * H), 4),
+               "listed_fraction": round(idx.size / (W * H), 4), "sad_plan": plan,
                "stage_ms": {k: round(float(np.median(v)), 4) for k, v in times.items()},
                "total_ms": round(float(sum(np.median(v) for v in times.values())), 4),
                "bad_pixel_pct_listed": round(b_list, 3), "bad_pixel_pct_dense": round(b_dense, 3)}

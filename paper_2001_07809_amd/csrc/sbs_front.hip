@@ -263,149 +263,292 @@ __global__ __launch_bounds__(kBlock) void k_label(const uint8_t* __restrict__ L8
 // ignores neighbours outside the image. `closed`
 // (optional) receives the labels after the close.
 constexpr int kMorphT = 64, kMorphHalo = 5, kMorphF = kMorphT + 2 * kMorphHalo;   // frame: 74 x 74
-constexpr int kMorphP = kMorphF + 2;   // LDS row pitch
+constexpr int kMorphP = 84;   // LDS row pitch: a multiple of 4 with room for the word-wide reads past the frame
+
+// Per-byte minimum / maximum of four labels packed in a word (labels < 128:
+// (a | 0x80) - b keeps each byte apart, and its bit 7 says a >= b).
+__device__ __forceinline__ uint32_t ge_mask4(uint32_t a, uint32_t b) {
+  return ((((a | 0x80808080u) - b) >> 7) & 0x01010101u) * 0xFFu;
+}
+__device__ __forceinline__ uint32_t min4(uint32_t a, uint32_t b) { const uint32_t m = ge_mask4(a, b); return (b & m) | (a & ~m); }
+__device__ __forceinline__ uint32_t max4(uint32_t a, uint32_t b) { const uint32_t m = ge_mask4(a, b); return (a & m) | (b & ~m); }
+
+// Four cells per thread and step, from two aligned LDS words per row and
+// byte shifts. A step on the box inset by k reads its source from column
+// fx - 1; the buffer it writes keeps frame column c at byte c + (-k mod 4),
+// so that the next step's reads start on a word again (the loaded frame has
+// offset 0, and so has the closed frame the boundary step reads). Groups at
+// a box's right end spill up to three cells past it; no later step reads
+// those. Frames inside the image with rows of whole words load and store
+// words; the others load bytes with clamped coordinates and store bytes,
+// and at an image edge every step's cells outside the image are then set to
+// the nearest cell inside, and the boundary of cells on the image's border
+// rows and columns is taken again without the neighbours outside.
 __global__ __launch_bounds__(kBlock) void k_morph_refine(const uint8_t* __restrict__ lab, int32_t W, int32_t H,
-                                                         uint8_t* __restrict__ B, uint8_t* __restrict__ closed) {
-  __shared__ uint8_t buf[2][kMorphF * kMorphP];
+                                                         uint8_t* __restrict__ B, uint8_t* __restrict__ closed,
+                                                         int32_t words) {
+  __shared__ __attribute__((aligned(16))) uint8_t buf[2][kMorphF * kMorphP];
   const int x0 = blockIdx.x * kMorphT - kMorphHalo, y0 = blockIdx.y * kMorphT - kMorphHalo;   // frame origin
   const bool edge = x0 < 0 || y0 < 0 || x0 + kMorphF > W || y0 + kMorphF > H;
-  for (int c = threadIdx.x; c < kMorphF * kMorphF; c += kBlock) {
-    const int fy = c / kMorphF, fx = c - fy * kMorphF;
-    const int gy = min(max(y0 + fy, 0), H - 1), gx = min(max(x0 + fx, 0), W - 1);
-    buf[0][fy * kMorphP + fx] = lab[(int64_t)gy * W + gx];
+  const bool wide = !edge && words;   // word loads and stores
+  if (wide) {
+    constexpr int kWords = (kMorphF + 3 + 3) / 4;   // global words covering a frame row from column x0 - 3
+    for (int c = threadIdx.x; c < kMorphF * kWords; c += kBlock) {
+      const int fy = c / kWords, w = c - fy * kWords;
+      const uint8_t* row = lab + (int64_t)(y0 + fy) * W;
+      const int g0 = x0 - 3 + 4 * w;   // a multiple of 4 (x0 = 64 bx - 5)
+      uint32_t v = 0u;
+      if (g0 + 3 < W) v = *(const uint32_t*)(row + g0);
+      else
+        for (int j = 0; j < 4; ++j)
+          if (g0 + j < W) v |= (uint32_t)row[g0 + j] << (8 * j);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int fx = 4 * w + j - 3;
+        if (fx >= 0 && fx < kMorphF) buf[0][fy * kMorphP + fx] = (uint8_t)(v >> (8 * j));
+      }
+    }
+  } else {
+    constexpr int kPer = (kMorphF * kMorphF + kBlock - 1) / kBlock;
+    uint8_t v[kPer];
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+      const int c = threadIdx.x + i * kBlock;
+      v[i] = 0;
+      if (c < kMorphF * kMorphF) {
+        const int fy = c / kMorphF, fx = c - fy * kMorphF;
+        const int gy = min(max(y0 + fy, 0), H - 1), gx = min(max(x0 + fx, 0), W - 1);
+        v[i] = lab[(int64_t)gy * W + gx];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+      const int c = threadIdx.x + i * kBlock;
+      if (c < kMorphF * kMorphF) buf[0][(c / kMorphF) * kMorphP + c % kMorphF] = v[i];
+    }
   }
   __syncthreads();
-  // steps 1..4 on the frame inset by k: erode, dilate, dilate, erode
 #pragma unroll
   for (int k = 1; k <= 4; ++k) {
     const uint8_t* src = buf[(k - 1) & 1];
     uint8_t* dst = buf[k & 1];
+    const int os = (1 - k) & 3, od = (-k) & 3;   // byte offsets of frame column 0
     const bool mx = k == 2 || k == 3;
-    const int n = kMorphF - 2 * k;
-    for (int c = threadIdx.x; c < n * n; c += kBlock) {
-      const int fy = k + c / n, fx = k + c % n;
-      const int gy = y0 + fy, gx = x0 + fx;
-      if (edge && (gy < 0 || gy >= H || gx < 0 || gx >= W)) continue;   // filled below
-      const uint8_t* q = src + fy * kMorphP + fx;
-      int r = q[0];
+    constexpr int kMaxGroups = (kMorphF - 2 + 3) / 4;
+    const int n = kMorphF - 2 * k, ng = (n + 3) / 4;
+    for (int c = threadIdx.x; c < n * kMaxGroups; c += kBlock) {
+      const int fy = k + c / kMaxGroups, g = c % kMaxGroups;
+      if (g >= ng) continue;
+      const int fx = k + 4 * g;
+      uint32_t h[3];
 #pragma unroll
-      for (int dy = -1; dy <= 1; ++dy)
+      for (int j = 0; j < 3; ++j) {
+        const uint32_t* q = (const uint32_t*)(src + (fy - 1 + j) * kMorphP + fx - 1 + os);
+        const uint32_t a = q[0], b = q[1];
+        const uint32_t l = a, m = __builtin_amdgcn_alignbyte(b, a, 1), r = __builtin_amdgcn_alignbyte(b, a, 2);
+        h[j] = mx ? max4(max4(l, m), r) : min4(min4(l, m), r);
+      }
+      const uint32_t o = mx ? max4(max4(h[0], h[1]), h[2]) : min4(min4(h[0], h[1]), h[2]);
+      *(uint32_t*)(dst + fy * kMorphP + fx + od) = o;
+    }
+    __syncthreads();
+    if (edge) {
+      // the box's cells outside the image take the nearest cell inside
+      for (int c = threadIdx.x; c < n * n; c += kBlock) {
+        const int fy = k + c / n, fx = k + c % n;
+        const int gy = y0 + fy, gx = x0 + fx;
+        if (gy >= 0 && gy < H && gx >= 0 && gx < W) continue;
+        const int cy = min(max(gy, 0), H - 1) - y0, cx = min(max(gx, 0), W - 1) - x0;
+        dst[fy * kMorphP + fx + od] = dst[cy * kMorphP + cx + od];
+      }
+      __syncthreads();
+    }
+  }
+  // boundary of the tile from the closed labels (buf[0], offset 0)
+  const uint8_t* lb = buf[0];
+  constexpr int kTileGroups = kMorphT / 4;
+  for (int c = threadIdx.x; c < kMorphT * kTileGroups; c += kBlock) {
+    const int ty = c / kTileGroups, g = c % kTileGroups;
+    const int fy = kMorphHalo + ty, fx = kMorphHalo + 4 * g;
+    uint32_t nb[3][3];
 #pragma unroll
-        for (int dx = -1; dx <= 1; ++dx) {
-          const int u = q[dy * kMorphP + dx];
-          r = mx ? max(r, u) : min(r, u);
-        }
-      dst[fy * kMorphP + fx] = (uint8_t)r;
+    for (int j = 0; j < 3; ++j) {
+      const uint32_t* q = (const uint32_t*)(lb + (fy - 1 + j) * kMorphP + fx - 1);
+      const uint32_t a = q[0], b = q[1];
+      nb[j][0] = a; nb[j][1] = __builtin_amdgcn_alignbyte(b, a, 1); nb[j][2] = __builtin_amdgcn_alignbyte(b, a, 2);
+    }
+    const uint32_t v = nb[1][1];
+    uint32_t acc = 0u;   // bit 7 of a byte: some neighbour differs
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+        if (j != 1 || i != 1) acc |= ((nb[j][i] ^ v) + 0x7F7F7F7Fu) & 0x80808080u;
+    const uint32_t r = (acc >> 7) & 0x01010101u;
+    const int gy = y0 + fy, gx = x0 + fx;   // gx a multiple of 4
+    if (wide) {
+      *(uint32_t*)(B + (int64_t)gy * W + gx) = r;
+      if (closed) *(uint32_t*)(closed + (int64_t)gy * W + gx) = v;
+      continue;
+    }
+    if (gy >= H) continue;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int x = gx + j;
+      if (x >= W) break;
+      uint8_t bj = (uint8_t)(r >> (8 * j));
+      if (gy == 0 || gy == H - 1 || x == 0 || x == W - 1) {
+        // on the image's border: neighbours outside the image do not count
+        const uint8_t* q = lb + fy * kMorphP + fx + j;
+        const int cv = q[0];
+        bool d = false;
+        for (int dy = -1; dy <= 1; ++dy)
+          for (int dx = -1; dx <= 1; ++dx)
+            if ((dy || dx) && gy + dy >= 0 && gy + dy < H && x + dx >= 0 && x + dx < W)
+              d |= q[dy * kMorphP + dx] != cv;
+        bj = d ? 1 : 0;
+      }
+      B[(int64_t)gy * W + x] = bj;
+      if (closed) closed[(int64_t)gy * W + x] = (uint8_t)(v >> (8 * j));
+    }
+  }
+}
+
+// The paper's refinement in one pass over the image: the Moore boundary of
+// the labels, then 'fill', then 'remove', per tile of kMorphT x kMorphT
+// pixels with a 3-pixel halo in LDS, four cells per thread and step as in
+// k_morph_refine (the maps after the first step hold 0 and 1, so 'fill' and
+// 'remove' are plain bitwise ands and ors of neighbour words). The boundary
+// step ignores neighbours outside the image (cells on the image's border
+// rows and columns are taken again without them); 'fill' and 'remove' take
+// them as 0, so at an image edge every step's cells outside the image are
+// set to 0 before the next step reads them.
+constexpr int kPaperHalo = 3, kPaperF = kMorphT + 2 * kPaperHalo;   // frame: 70 x 70
+__global__ __launch_bounds__(kBlock) void k_paper_refine(const uint8_t* __restrict__ lab, int32_t W, int32_t H,
+                                                         uint8_t* __restrict__ B, int32_t words) {
+  __shared__ __attribute__((aligned(16))) uint8_t buf[2][kPaperF * kMorphP];
+  const int x0 = blockIdx.x * kMorphT - kPaperHalo, y0 = blockIdx.y * kMorphT - kPaperHalo;   // frame origin
+  const bool edge = x0 < 0 || y0 < 0 || x0 + kPaperF > W || y0 + kPaperF > H;
+  const bool wide = !edge && words;
+  auto inside = [&](int gy, int gx) { return gy >= 0 && gy < H && gx >= 0 && gx < W; };
+  if (wide) {
+    constexpr int kWords = (kPaperF + 1 + 3) / 4;   // global words covering a frame row from column x0 - 1
+    for (int c = threadIdx.x; c < kPaperF * kWords; c += kBlock) {
+      const int fy = c / kWords, w = c - fy * kWords;
+      const uint8_t* row = lab + (int64_t)(y0 + fy) * W;
+      const int g0 = x0 - 1 + 4 * w;   // a multiple of 4 (x0 = 64 bx - 3)
+      uint32_t v = 0u;
+      if (g0 + 3 < W) v = *(const uint32_t*)(row + g0);
+      else
+        for (int j = 0; j < 4; ++j)
+          if (g0 + j < W) v |= (uint32_t)row[g0 + j] << (8 * j);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int fx = 4 * w + j - 1;
+        if (fx >= 0 && fx < kPaperF) buf[0][fy * kMorphP + fx] = (uint8_t)(v >> (8 * j));
+      }
+    }
+  } else {
+    constexpr int kPer = (kPaperF * kPaperF + kBlock - 1) / kBlock;
+    uint8_t v[kPer];
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+      const int c = threadIdx.x + i * kBlock;
+      v[i] = 0;
+      if (c < kPaperF * kPaperF) {
+        const int fy = c / kPaperF, fx = c - fy * kPaperF;
+        const int gy = min(max(y0 + fy, 0), H - 1), gx = min(max(x0 + fx, 0), W - 1);
+        v[i] = lab[(int64_t)gy * W + gx];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+      const int c = threadIdx.x + i * kBlock;
+      if (c < kPaperF * kPaperF) buf[0][(c / kPaperF) * kMorphP + c % kPaperF] = v[i];
+    }
+  }
+  __syncthreads();
+  // the three neighbour words (left, centre, right) of a row of four cells
+  auto row3 = [&](const uint8_t* p, uint32_t& l, uint32_t& m, uint32_t& r) {
+    const uint32_t a = ((const uint32_t*)p)[0], b = ((const uint32_t*)p)[1];
+    l = a; m = __builtin_amdgcn_alignbyte(b, a, 1); r = __builtin_amdgcn_alignbyte(b, a, 2);
+  };
+  // steps 1 and 2 on the frame inset by k (k = 1: boundary, k = 2: fill); offsets as in k_morph_refine
+#pragma unroll
+  for (int k = 1; k <= 2; ++k) {
+    const uint8_t* src = buf[(k - 1) & 1];
+    uint8_t* dst = buf[k & 1];
+    const int os = (1 - k) & 3, od = (-k) & 3;
+    constexpr int kMaxGroups = (kPaperF - 2 + 3) / 4;
+    const int n = kPaperF - 2 * k, ng = (n + 3) / 4;
+    for (int c = threadIdx.x; c < n * kMaxGroups; c += kBlock) {
+      const int fy = k + c / kMaxGroups, g = c % kMaxGroups;
+      if (g >= ng) continue;
+      const int fx = k + 4 * g;
+      uint32_t nb[3][3];
+#pragma unroll
+      for (int j = 0; j < 3; ++j) row3(src + (fy - 1 + j) * kMorphP + fx - 1 + os, nb[j][0], nb[j][1], nb[j][2]);
+      const uint32_t v = nb[1][1];
+      uint32_t o;
+      if (k == 1) {
+        uint32_t acc = 0u;   // bit 7 of a byte: some neighbour differs (labels < 128)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+#pragma unroll
+          for (int i = 0; i < 3; ++i)
+            if (j != 1 || i != 1) acc |= ((nb[j][i] ^ v) + 0x7F7F7F7Fu) & 0x80808080u;
+        o = (acc >> 7) & 0x01010101u;
+      } else {
+        uint32_t all = 0x01010101u;   // every neighbour 1
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+#pragma unroll
+          for (int i = 0; i < 3; ++i)
+            if (j != 1 || i != 1) all &= nb[j][i];
+        o = v | all;
+      }
+      *(uint32_t*)(dst + fy * kMorphP + fx + od) = o;
     }
     __syncthreads();
     if (edge) {
       for (int c = threadIdx.x; c < n * n; c += kBlock) {
         const int fy = k + c / n, fx = k + c % n;
         const int gy = y0 + fy, gx = x0 + fx;
-        if (gy >= 0 && gy < H && gx >= 0 && gx < W) continue;
-        const int cy = min(max(gy, 0), H - 1) - y0, cx = min(max(gx, 0), W - 1) - x0;
-        dst[fy * kMorphP + fx] = dst[cy * kMorphP + cx];
+        uint8_t* d = dst + fy * kMorphP + fx + od;
+        if (!inside(gy, gx)) { *d = 0; continue; }   // outside: 0 for the steps that follow
+        if (k == 1 && (gy == 0 || gy == H - 1 || gx == 0 || gx == W - 1)) {
+          // on the image's border: the boundary without the neighbours outside
+          const uint8_t* q = src + fy * kMorphP + fx + os;
+          const int cv = q[0];
+          bool diff = false;
+          for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx)
+              if ((dy || dx) && inside(gy + dy, gx + dx)) diff |= q[dy * kMorphP + dx] != cv;
+          *d = diff ? 1 : 0;
+        }
       }
       __syncthreads();
     }
   }
-  // boundary of the tile (frame cells halo .. halo + T - 1) from the closed labels in buf[0]
-  const uint8_t* lb = buf[0];
-  for (int c = threadIdx.x; c < kMorphT * kMorphT; c += kBlock) {
-    const int ty = c / kMorphT, tx = c - ty * kMorphT;
-    const int fy = kMorphHalo + ty, fx = kMorphHalo + tx;
-    const int gy = y0 + fy, gx = x0 + fx;
-    if (gy >= H || gx >= W) continue;
-    const uint8_t* q = lb + fy * kMorphP + fx;
-    const int v = q[0];
-    bool d = false;
-#pragma unroll
-    for (int dy = -1; dy <= 1; ++dy)
-#pragma unroll
-      for (int dx = -1; dx <= 1; ++dx) {
-        if (!dy && !dx) continue;
-        const bool in = !edge || (gy + dy >= 0 && gy + dy < H && gx + dx >= 0 && gx + dx < W);
-        d |= in && q[dy * kMorphP + dx] != v;
-      }
-    B[(int64_t)gy * W + gx] = d ? 1 : 0;
-    if (closed) closed[(int64_t)gy * W + gx] = (uint8_t)v;
-  }
-}
-
-// The paper's refinement in one pass over the image: the Moore boundary of
-// the labels, then 'fill', then 'remove', per tile
-// of kMorphT x kMorphT pixels with a 3-pixel halo in LDS. The boundary step
-// ignores neighbours outside the image; 'fill' and 'remove' take them as 0,
-// so every step's cells outside the image are set to 0 before the next
-// step reads them.
-constexpr int kPaperHalo = 3, kPaperF = kMorphT + 2 * kPaperHalo, kPaperP = kPaperF + 2;   // frame: 70 x 70
-__global__ __launch_bounds__(kBlock) void k_paper_refine(const uint8_t* __restrict__ lab, int32_t W, int32_t H,
-                                                         uint8_t* __restrict__ B) {
-  __shared__ uint8_t buf[2][kPaperF * kPaperP];
-  const int x0 = blockIdx.x * kMorphT - kPaperHalo, y0 = blockIdx.y * kMorphT - kPaperHalo;   // frame origin
-  const bool edge = x0 < 0 || y0 < 0 || x0 + kPaperF > W || y0 + kPaperF > H;
-  auto inside = [&](int gy, int gx) { return gy >= 0 && gy < H && gx >= 0 && gx < W; };
-  for (int c = threadIdx.x; c < kPaperF * kPaperF; c += kBlock) {
-    const int fy = c / kPaperF, fx = c - fy * kPaperF;
-    const int gy = min(max(y0 + fy, 0), H - 1), gx = min(max(x0 + fx, 0), W - 1);
-    buf[0][fy * kPaperP + fx] = lab[(int64_t)gy * W + gx];
-  }
-  __syncthreads();
-  // step 1: boundary (in-image neighbours only) on the frame inset by 1
-  {
-    constexpr int n = kPaperF - 2;
-    for (int c = threadIdx.x; c < n * n; c += kBlock) {
-      const int fy = 1 + c / n, fx = 1 + c % n;
-      const int gy = y0 + fy, gx = x0 + fx;
-      uint8_t r = 0;
-      if (!edge || inside(gy, gx)) {
-        const uint8_t* q = buf[0] + fy * kPaperP + fx;
-        const int v = q[0];
-        bool d = false;
-#pragma unroll
-        for (int dy = -1; dy <= 1; ++dy)
-#pragma unroll
-          for (int dx = -1; dx <= 1; ++dx)
-            if (dy || dx) d |= (!edge || inside(gy + dy, gx + dx)) && q[dy * kPaperP + dx] != v;
-        r = d ? 1 : 0;
-      }
-      buf[1][fy * kPaperP + fx] = r;   // 0 outside the image
+  // step 3: 'remove' on the tile, from buf[0] (offset 2)
+  constexpr int kTileGroups = kMorphT / 4;
+  for (int c = threadIdx.x; c < kMorphT * kTileGroups; c += kBlock) {
+    const int ty = c / kTileGroups, g = c % kTileGroups;
+    const int fy = kPaperHalo + ty, fx = kPaperHalo + 4 * g;
+    uint32_t u, l, v, r, dn, t0, t1;
+    row3(buf[0] + (fy - 1) * kMorphP + fx - 1 + 2, t0, u, t1);
+    row3(buf[0] + fy * kMorphP + fx - 1 + 2, l, v, r);
+    row3(buf[0] + (fy + 1) * kMorphP + fx - 1 + 2, t0, dn, t1);
+    const uint32_t o = v & ~(u & dn & l & r);
+    const int gy = y0 + fy, gx = x0 + fx;   // gx a multiple of 4
+    if (wide) {
+      *(uint32_t*)(B + (int64_t)gy * W + gx) = o;
+      continue;
     }
-  }
-  __syncthreads();
-  // step 2: 'fill' (a 0 whose eight neighbours are all 1 becomes 1) on the frame inset by 2
-  {
-    constexpr int n = kPaperF - 4;
-    for (int c = threadIdx.x; c < n * n; c += kBlock) {
-      const int fy = 2 + c / n, fx = 2 + c % n;
-      const uint8_t* q = buf[1] + fy * kPaperP + fx;
-      uint8_t r = 0;
-      if (!edge || inside(y0 + fy, x0 + fx)) {
-        r = q[0];
-        if (!r) {
-          bool all = true;
+    if (gy >= H) continue;
 #pragma unroll
-          for (int dy = -1; dy <= 1; ++dy)
-#pragma unroll
-            for (int dx = -1; dx <= 1; ++dx)
-              if (dy || dx) all &= q[dy * kPaperP + dx] != 0;
-          r = all ? 1 : 0;
-        }
-      }
-      buf[0][fy * kPaperP + fx] = r;   // 0 outside the image
-    }
-  }
-  __syncthreads();
-  // step 3: 'remove' (a 1 whose four 4-neighbours are all 1 becomes 0) on the tile
-  for (int c = threadIdx.x; c < kMorphT * kMorphT; c += kBlock) {
-    const int ty = c / kMorphT, tx = c - ty * kMorphT;
-    const int fy = kPaperHalo + ty, fx = kPaperHalo + tx;
-    const int gy = y0 + fy, gx = x0 + fx;
-    if (gy >= H || gx >= W) continue;
-    const uint8_t* q = buf[0] + fy * kPaperP + fx;
-    uint8_t r = q[0];
-    if (r && q[-kPaperP] && q[kPaperP] && q[-1] && q[1]) r = 0;
-    B[(int64_t)gy * W + gx] = r;
+    for (int j = 0; j < 4; ++j)
+      if (gx + j < W) B[(int64_t)gy * W + gx + j] = (uint8_t)(o >> (8 * j));
   }
 }
 
@@ -1561,12 +1704,14 @@ int sbs_boundaries(const uint8_t* img, int32_t W, int32_t H, int32_t C, int64_t 
     // open, close and boundary in one pass; the closed labels go straight to
     // out_labels when asked for
     const dim3 gm((W + kMorphT - 1) / kMorphT, (H + kMorphT - 1) / kMorphT);
-    hipLaunchKernelGGL(k_morph_refine, gm, dim3(kBlock), 0, s, lab, W, H, B, out_labels);
+    // word-wide interior path: rows of whole words, the outputs word-aligned too
+    const int32_t words = (W & 3) == 0 && ((uintptr_t)out_labels & 3) == 0 ? 1 : 0;
+    hipLaunchKernelGGL(k_morph_refine, gm, dim3(kBlock), 0, s, lab, W, H, B, out_labels, words);
     labels = nullptr;
   } else {
     // boundary, fill and remove in one pass
     const dim3 gm((W + kMorphT - 1) / kMorphT, (H + kMorphT - 1) / kMorphT);
-    hipLaunchKernelGGL(k_paper_refine, gm, dim3(kBlock), 0, s, lab, W, H, B);
+    hipLaunchKernelGGL(k_paper_refine, gm, dim3(kBlock), 0, s, lab, W, H, B, (W & 3) == 0 ? 1 : 0);
   }
   if (out_labels && labels) {
     const hipError_t ce = hipMemcpyAsync(out_labels, labels, (size_t)N, hipMemcpyDeviceToDevice, s);
