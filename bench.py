@@ -96,8 +96,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the per-frame / graph comparisons")
     ap.add_argument("--no-tune", action="store_true", help="run the default plan (no autotuning before timing)")
-    ap.add_argument("--plan", default="", metavar="CHUNK,ROWS,WPC",
-                    help="force a plan (disparities per wavefront, tile rows, wavefronts per CU; implies --no-tune)")
+    ap.add_argument("--plan", default="", metavar="[CPL,]CHUNK,ROWS,WPC",
+                    help="force a plan ([window columns per lane,] disparities per wavefront, tile rows, "
+                         "wavefronts per CU; implies --no-tune)")
     ap.add_argument("--no-contour", action="store_true",
                     help="skip the secondary measurement on the generator's contour-band lists")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target oracle time for the CPU sample")
@@ -178,8 +179,9 @@ def main():
     if args.tuning and os.path.exists(args.tuning):
         sbs.load_tuning(args.tuning)
     if args.plan:
-        chunk, rows, wpc = (int(v) for v in args.plan.split(","))
-        sbs.set_plan(chunk=chunk, tile_rows=rows, waves_per_cu=wpc)
+        vals = [int(v) for v in args.plan.split(",")]
+        cpl, (chunk, rows, wpc) = (vals[0], vals[1:]) if len(vals) == 4 else (0, vals)
+        sbs.set_plan(cols_per_lane=cpl, chunk=chunk, tile_rows=rows, waves_per_cu=wpc)
         args.no_tune = True
     if args.serve:
         serve_main(args)
@@ -542,11 +544,16 @@ def paper_main(args):
         p = pipeline.PaperParams(dmax=dmax, threshold=thr, ranges=((0, dmax // 3),))
         stages = ["lightness", "front_end", "sad", "reconstruct", "blur"]
         times = {k: [] for k in stages}
-        # the disparity search's plan (the default for a single frame)
+        # the disparity search's plan: tuned on this frame's list, on the
+        # single-frame launch sequence the chain calls
         l8 = sbs.lightness(L); r8 = sbs.lightness(R)
         lst = sbs.boundaries(l8, K=p.K, mode=p.mode)
         d0 = torch.empty(lst.numel(), dtype=torch.uint8, device="cuda")
-        plan = sbs.get_plan(sbs.make_frame(l8, r8, lst, p.block, p.dmax, d0, None))
+        fr0 = sbs.make_frame(l8, r8, lst, p.block, p.dmax, d0, None)
+        default_plan = sbs.get_plan(fr0)
+        if not args.no_tune:
+            sbs.tune([fr0])
+        plan = sbs.get_plan(fr0)
         for it in range(args.warmup + args.steps):
             ev = [torch.cuda.Event(enable_timing=True) for _ in range(len(stages) + 1)]
             ev[0].record()
@@ -570,7 +577,7 @@ def paper_main(args):
         b_list = pipeline.bad_pixel_percent(dl, f.gt.reshape(-1)[idx], mask=occ[idx] == 0)
         b_dense = pipeline.bad_pixel_percent(dense.cpu().numpy().reshape(-1), f.gt.reshape(-1), mask=occ == 0)
         rec = {"size": f"{W}x{H}x{spec.C}", "block": p.block, "dmax": dmax, "K": p.K, "threshold": thr,
-               "listed_fraction": round(idx.size / (W * H), 4), "sad_plan": plan,
+               "listed_fraction": round(idx.size / (W * H), 4), "sad_plan": plan, "sad_plan_default": default_plan,
                "stage_ms": {k: round(float(np.median(v)), 4) for k, v in times.items()},
                "total_ms": round(float(sum(np.median(v) for v in times.values())), 4),
                "bad_pixel_pct_listed": round(b_list, 3), "bad_pixel_pct_dense": round(b_dense, 3)}

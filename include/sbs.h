@@ -151,6 +151,9 @@ int sbs_check_indices(const sbs_frame* frames, int32_t nframes, void* workspace,
  * frames per call rounded up to a power of two; taken from the first frame
  * with a non-empty list) in a JSON cache at cache_path (created or updated;
  * NULL: in memory only). Later calls with a matching key use the stored plan.
+ * One frame is timed as sbs_sad_disparity runs it (one grid launch of the
+ * tile kernel; the persistent grid size is then not searched), several
+ * frames as sbs_sad_disparity_batched runs them.
  * Synchronous; runs in a library-managed workspace (allocated on first use,
  * kept until the process ends). Outputs of the frames are written as a side
  * effect.

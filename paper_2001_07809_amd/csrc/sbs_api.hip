@@ -699,9 +699,15 @@ int sbs_tune(const sbs_frame* frames, int32_t nframes, const char* cache_path) {
   const int shapes[][2] = {{4, 8}, {4, 16}, {8, 8}};   // (columns per lane, disparity chunk)
   const int rows[] = {32, 64, 128, 256};
   const int wpcs[] = {4, 8, 16};
+  // one frame: timed on the single-frame path (its own launch sequence, the
+  // grid tile kernel), which calls on one frame take; more: the batched one
+  // (the grid tile kernel has no persistent grid, so one wavefront count)
+  const Mode tmode = nframes == 1 ? kSingle : kBatched;
+  const int nwpc = tmode == kSingle ? 1 : 3;
   for (const auto& sh : shapes)
     for (int ty : rows)
-      for (int w : wpcs) {
+      for (int wi = 0; wi < nwpc; ++wi) {
+        const int w = tmode == kSingle ? Plan().wpc : wpcs[wi];
         Plan p;
         p.cpl = sh[0]; p.chunk = sh[1]; p.ty = ty; p.wpc = w;
         {
@@ -709,11 +715,11 @@ int sbs_tune(const sbs_frame* frames, int32_t nframes, const char* cache_path) {
           g_forced = true;
           g_forced_plan = p;
         }
-        st = run(frames, nframes, nullptr, 0, nullptr, kBatched);  // warm-up (and workspace growth)
+        st = run(frames, nframes, nullptr, 0, nullptr, tmode);  // warm-up (and workspace growth)
         if (st != SBS_OK) goto done;
         hipEventRecord(a, nullptr);
         for (int rep = 0; rep < 3; ++rep) {
-          st = run(frames, nframes, nullptr, 0, nullptr, kBatched);
+          st = run(frames, nframes, nullptr, 0, nullptr, tmode);
           if (st != SBS_OK) goto done;
         }
         hipEventRecord(b, nullptr);

@@ -39,3 +39,34 @@ def test_tune_cache_roundtrip(tmp_path):
     torch.cuda.synchronize()
     for a, b in zip(before, runner.disp):
         assert torch.equal(a, b)
+
+
+def test_tune_single_frame(tmp_path):
+    """One frame is tuned on the single-frame launch sequence: its key ends
+    with /nf1, the persistent grid size keeps its default, sad_disparity
+    picks the stored plan up, and its output does not change."""
+    import torch
+    import paper_2001_07809_amd as sbs
+    spec = scenes.scaled(scenes.PRESETS["uhd_video"], W=640, H=360, n_regions=8)
+    fr = scenes.video_fracs(spec, 0, 1)
+    left, right, lists = scenes.make_video(spec, 0, 1, fr)
+    L = torch.from_numpy(left[0]).cuda()
+    R = torch.from_numpy(right[0]).cuda()
+    idx = torch.from_numpy(lists[0].view(np.int32)).cuda()
+    d0, c0 = sbs.sad_disparity(L, R, idx, spec.block, spec.dmax)
+    torch.cuda.synchronize()
+    d0, c0 = d0.clone(), c0.clone()
+    out = torch.empty_like(d0)
+    frame = sbs.make_frame(L, R, idx, spec.block, spec.dmax, out, None)
+    cache = tmp_path / "tuning.json"
+    sbs.tune([frame], str(cache))
+    data = json.loads(cache.read_text())
+    mine = {k: v for k, v in data.items() if k.startswith("gfx950/640x360x3/")}
+    assert len(mine) == 1
+    (key, plan), = mine.items()
+    assert key.endswith("/nf1") and plan["waves_per_cu"] == 16
+    assert sbs.get_plan(frame) == plan
+    d1, c1 = sbs.sad_disparity(L, R, idx, spec.block, spec.dmax)
+    torch.cuda.synchronize()
+    assert torch.equal(d0, d1) and torch.equal(c0, c1)
+    assert torch.equal(out, d0)
