@@ -492,6 +492,416 @@ void blur_tile_dispatch(int rad, std::integer_sequence<int, R...>, dim3 grid, hi
   ((rad == R + 1 ? launch_blur_tile<C, R + 1>(grid, s, img, depth, W, H, pitch, aligned, a, out) : void()), ...);
 }
 
+// The same blur on the matrix cores, for radii up to 8 (sigma <= 2.67). At
+// fp32 vector rates a 4096x2304 RGB frame's taps (13 + 13 per channel and
+// pixel at sigma 2) take longer than its 151 MB take to cross HBM, so both
+// tap passes run as 16x16x32 fp16 products with fp32 accumulation:
+//  - horizontal: rows of the input tile (bytes, exact in fp16) times the
+//    banded matrix of the taps, B[k][n] = g(k - n - (8 - radius));
+//  - vertical: the same banded matrix times the horizontal sums.
+// fp16 holds 11 significant bits, so the taps are split into a high and a
+// low fp16 part (t = hi + lo, relative error ~2^-22) and so are the
+// horizontal sums; the vertical pass adds hi*hi + lo*hi + hi*lo. The taps
+// are scaled by 2^10 (exactly undone afterwards) so that their low parts are
+// normal fp16 numbers. The products of the low parts are summed apart from
+// the main ones, so their roundings stay small. Worst-case error against
+// exact arithmetic: about 4e-4 on outputs in [0, 255] (per pass about 1e-4
+// from the fp32 sums, 1.2e-4 from truncating the horizontal sums' low parts,
+// 6e-5 for the low x low products left out).
+// One tile of 64 x 32 outputs per workgroup of four wavefronts; wavefront w
+// owns output columns 16w .. 16w + 15, so its horizontal sums feed only its
+// own vertical pass (through its own LDS, in the order it issues them; no
+// barrier). The input tile is 48 rows x 80 columns from image row y0 - 8 and
+// column x0 - 8 (clamped), converted once to planar fp16.
+typedef _Float16 h16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 h16x2 __attribute__((ext_vector_type(2)));
+typedef __fp16 fp16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int mu32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int mu32x3 __attribute__((ext_vector_type(3)));
+typedef __attribute__((address_space(1))) const mu32x3 g_mu32x3;
+typedef __attribute__((address_space(1))) const uint32_t g_mu32;
+typedef __attribute__((address_space(1))) mu32x3 g_mu32x3_rw;
+
+constexpr int kMxTX = 64, kMxTY = 32;   // output tile
+constexpr int kMxRad = 8;               // largest radius
+constexpr int kMxRows = kMxTY + 2 * kMxRad, kMxCols = kMxTX + 2 * kMxRad;   // 48 x 80 input tile
+constexpr int kMxPT = 56;               // fp16 per column of a wavefront's horizontal sums (48 used)
+constexpr int kMxThreads = 256;
+constexpr float kMxScale = 1024.f;
+
+template <int C>
+struct MxGeom {
+  static constexpr int plane = kMxRows * kMxCols;                 // fp16 per channel plane
+  static constexpr size_t planes = (size_t)C * plane * 2;
+  static constexpr size_t keep = (size_t)kMxTX * kMxTY;
+  static constexpr size_t hsum = (size_t)2 * 16 * kMxPT * 2;      // per wavefront: hi and lo parts
+  static constexpr size_t taps = 64 * 4;                           // 2^10 x the taps, zero-padded
+  static constexpr size_t lds = planes + keep + 4 * hsum + taps;
+};
+
+// in focus: depth inside one of the ranges
+__device__ __forceinline__ bool in_focus(int dv, const BlurArgs& a) {
+  bool k = false;
+  for (int t = 0; t < a.nranges; ++t) k |= (dv >= a.lo[t] && dv <= a.hi[t]);
+  return k;
+}
+
+// Two bytes b0, b1 as an fp16 pair: the perm puts each byte under an 0x64
+// high byte (fp16 1024 + b), the packed subtraction removes the 1024 exactly.
+__device__ __forceinline__ uint32_t byte_pair_f16(uint32_t word_with_64) {
+  h16x2 v = __builtin_bit_cast(h16x2, word_with_64);
+  v = v - (h16x2){(_Float16)1024.f, (_Float16)1024.f};
+  return __builtin_bit_cast(uint32_t, v);
+}
+
+// The tiles: interior tiles (input columns x0 - 8 .. x0 + 71 inside the
+// image, 4-byte-aligned image rows) load their input as dword groups;
+// edge tiles (and every tile of images whose rows are not aligned) byte by
+// byte with clamped columns. Edge tiles take one workgroup each; interior
+// tiles go to a persistent set of workgroups that load the next tile's
+// words into registers while they sum and write the current one. Every lane
+// of an interior tile issues the same loads and stores (rows clamped; the
+// stores of pixels outside the image go to a sink word), so the wait for the
+// next tile's loads never has to wait for the current tile's stores.
+constexpr int kMxGroups = kMxCols / 4;                      // 4-pixel groups per input row
+constexpr int kMxItems = kMxRows * kMxGroups;               // 960
+constexpr int kMxPer = (kMxItems + kMxThreads - 1) / kMxThreads;
+constexpr int kMxDWords = kMxTY * (kMxTX / 4) / kMxThreads; // depth words per thread: 2
+constexpr int kMxDBytes = kMxTY * kMxTX / kMxThreads;       // depth bytes per thread: 8
+
+struct MxTiles {
+  int32_t ntx, nty;         // tiles per row and column
+  int32_t ilo, icols;       // interior tile columns ilo .. ilo + icols - 1 (icols 0: none)
+  int32_t ecols, nedge;     // edge tile columns per row; edge tiles
+  int32_t ninner;           // interior tiles
+  __device__ __forceinline__ int edge_cx(int ec) const { return icols == 0 ? ec : (ec == 0 ? 0 : ilo + icols - 1 + ec); }
+};
+
+template <int C, bool kDWords>
+struct MxLoads {
+  mu32x3 gv[kMxPer];
+  uint32_t dv[kDWords ? kMxDWords : kMxDBytes];
+};
+
+// one interior tile's loads, the same for every lane and tile
+template <int C, bool kDWords>
+__device__ __forceinline__ void mx_issue(const uint8_t* img, const uint8_t* depth, int W, int H, int64_t pitch, int x0,
+                                         int y0, int tid, MxLoads<C, kDWords>& L) {
+#pragma unroll
+  for (int k = 0; k < kMxPer; ++k) {
+    const int ic = min(tid + k * kMxThreads, kMxItems - 1);   // past the last group: the last group again
+    const int r = ic / kMxGroups, q = ic - r * kMxGroups;
+    const int yy = min(max(y0 - kMxRad + r, 0), H - 1);
+    const uint8_t* src = img + (int64_t)yy * pitch + (int64_t)(x0 - kMxRad + 4 * q) * C;
+    if constexpr (C == 3) L.gv[k] = *(g_mu32x3*)src;
+    else L.gv[k] = (mu32x3){*(g_mu32*)src, 0u, 0u};
+  }
+  if constexpr (kDWords) {
+#pragma unroll
+    for (int k = 0; k < kMxDWords; ++k) {
+      const int i = tid + k * kMxThreads;
+      const int r = i / (kMxTX / 4), q = i - r * (kMxTX / 4);
+      L.dv[k] = *(g_mu32*)(depth + (int64_t)min(y0 + r, H - 1) * W + x0 + 4 * q);
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < kMxDBytes; ++k) {
+      const int i = tid + k * kMxThreads;
+      const int r = i / kMxTX, x = i - r * kMxTX;
+      L.dv[k] = depth[(int64_t)min(y0 + r, H - 1) * W + x0 + x];
+    }
+  }
+}
+
+// in-focus flags from an interior tile's depth loads (1 below the image);
+// returns whether this thread saw a pixel to blur
+template <bool kDWords>
+__device__ __forceinline__ bool mx_flags_loaded(const uint32_t* dv, int y0, int H, int tid, uint8_t* keep,
+                                                const BlurArgs& a) {
+  bool need = false;
+  const bool one = a.nranges == 1;
+  const uint32_t lo = (uint32_t)a.lo[0], span = (uint32_t)(a.hi[0] - a.lo[0]);
+  auto bit = [&](uint32_t d) -> uint32_t {
+    return (one ? d - lo <= span : in_focus((int)d, a)) ? 1u : 0u;
+  };
+  if constexpr (kDWords) {
+#pragma unroll
+    for (int k = 0; k < kMxDWords; ++k) {
+      const int i = tid + k * kMxThreads;
+      const int r = i / (kMxTX / 4), q = i - r * (kMxTX / 4);
+      uint32_t kw = 0u;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) kw |= bit((dv[k] >> (8 * j)) & 0xFFu) << (8 * j);
+      if (y0 + r >= H) kw = 0x01010101u;
+      *(uint32_t*)(keep + r * kMxTX + 4 * q) = kw;
+      need |= kw != 0x01010101u;
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < kMxDBytes; ++k) {
+      const int i = tid + k * kMxThreads;
+      const int r = i / kMxTX;
+      const uint32_t kb = y0 + r >= H ? 1u : bit(dv[k]);
+      keep[i] = (uint8_t)kb;
+      need |= kb == 0u;
+    }
+  }
+  return need;
+}
+
+// in-focus flags read byte by byte (edge tiles)
+__device__ __forceinline__ bool mx_flags_bytes(const uint8_t* depth, int W, int H, int x0, int y0, int tid,
+                                               uint8_t* keep, const BlurArgs& a) {
+  bool need = false;
+  for (int i = tid; i < kMxTY * kMxTX; i += kMxThreads) {
+    const int y = i / kMxTX, x = i - y * kMxTX;
+    bool k = true;
+    if (y0 + y < H && x0 + x < W) k = in_focus(depth[(int64_t)(y0 + y) * W + x0 + x], a);
+    keep[i] = k ? 1 : 0;
+    need |= !k;
+  }
+  return need;
+}
+
+// planar fp16 input tile from an interior tile's dword groups
+template <int C>
+__device__ __forceinline__ void mx_stage_loaded(const mu32x3* gv, int tid, _Float16* P) {
+  const uint32_t k64 = 0x64646464u;
+#pragma unroll
+  for (int k = 0; k < kMxPer; ++k) {
+    const int i = tid + k * kMxThreads;
+    if (i < kMxItems) {   // (the last wavefront's fourth group only)
+      const int r = i / kMxGroups, q = i - r * kMxGroups;
+      _Float16* dst = P + r * kMxCols + 4 * q;
+      if constexpr (C == 3) {
+        const uint32_t w0 = gv[k].x, w1 = gv[k].y, w2 = gv[k].z;
+        // w0 = R0 G0 B0 R1, w1 = G1 B1 R2 G2, w2 = B2 R3 G3 B3 (lowest byte first)
+        const uint32_t r01 = byte_pair_f16(__builtin_amdgcn_perm(w0, k64, 0x00070004u));
+        const uint32_t r23 = byte_pair_f16(__builtin_amdgcn_perm(w2, w1, 0x0c050c02u) | 0x64006400u);
+        const uint32_t g01 = byte_pair_f16(__builtin_amdgcn_perm(w1, w0, 0x0c040c01u) | 0x64006400u);
+        const uint32_t g23 = byte_pair_f16(__builtin_amdgcn_perm(w2, w1, 0x0c060c03u) | 0x64006400u);
+        const uint32_t b01 = byte_pair_f16(__builtin_amdgcn_perm(w1, w0, 0x0c050c02u) | 0x64006400u);
+        const uint32_t b23 = byte_pair_f16(__builtin_amdgcn_perm(w2, k64, 0x00070004u));
+        constexpr int plane = MxGeom<C>::plane;
+        *(mu32x2*)dst = (mu32x2){r01, r23};
+        *(mu32x2*)(dst + plane) = (mu32x2){g01, g23};
+        *(mu32x2*)(dst + 2 * plane) = (mu32x2){b01, b23};
+      } else {
+        const uint32_t w = gv[k].x;
+        *(mu32x2*)dst = (mu32x2){byte_pair_f16(__builtin_amdgcn_perm(w, k64, 0x00050004u)),
+                                 byte_pair_f16(__builtin_amdgcn_perm(w, k64, 0x00070006u))};
+      }
+    }
+  }
+}
+
+// planar fp16 input tile byte by byte with clamped rows and columns (edge tiles)
+template <int C>
+__device__ __forceinline__ void mx_stage_bytes(const uint8_t* img, int W, int H, int64_t pitch, int x0, int y0, int tid,
+                                               _Float16* P) {
+  for (int e = tid; e < kMxRows * kMxCols * C; e += kMxThreads) {
+    const int r = e / (kMxCols * C), jc = e - r * (kMxCols * C), j = jc / C, c = jc - j * C;
+    const int yy = min(max(y0 - kMxRad + r, 0), H - 1), xx = min(max(x0 - kMxRad + j, 0), W - 1);
+    P[c * MxGeom<C>::plane + r * kMxCols + j] = (_Float16)img[(int64_t)yy * pitch + (int64_t)xx * C + c];
+  }
+}
+
+// The banded tap matrix, as this lane's eight entries (column n, rows
+// 8g .. 8g + 7): taps[24 + t] holds 2^10 x tap t (zero outside [0, 2 radius]),
+// a lane reads t = 8g + e - n - 8 + radius, in [-22, 31].
+__device__ __forceinline__ void mx_weights(const float* taps, int rad, int n, int g, h16x8& whi, h16x8& wlo) {
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const float w = taps[24 + 8 * g + e - n - kMxRad + rad];
+    const _Float16 hi = (_Float16)w;
+    whi[e] = hi;
+    wlo[e] = (_Float16)(w - (float)hi);
+  }
+}
+
+// Both passes of one staged tile and its outputs (after the barrier that
+// follows the staging). kSink: lanes outside the image store to `sink`.
+template <int C, bool kSink>
+__device__ __forceinline__ void mx_sum_store(const unsigned char* lds, int tid, bool need, const h16x8& whi,
+                                             const h16x8& wlo, int x0, int y0, int W, int H, float* out, float* sink) {
+  using G = MxGeom<C>;
+  const _Float16* P = (const _Float16*)lds;
+  const uint8_t* keep = lds + G::planes;
+  const int wv = tid >> 6, l = tid & 63, n = l & 15, g = l >> 4;
+  // this lane's outputs: rows 16p + 4g + i (p < 2, i < 4) of column 16 wv + n
+  const int xx = 16 * wv + n;
+  f32x4 res[C][2];
+  if (need) {
+    _Float16* hs = (_Float16*)(lds + G::planes + G::keep + (size_t)wv * G::hsum);   // [16][kMxPT] hi
+    _Float16* hl = hs + 16 * kMxPT;                                                 // [16][kMxPT] lo
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const _Float16* pl = P + c * G::plane;
+#pragma unroll
+      for (int m = 0; m < kMxRows / 16; ++m) {
+        // rows 16m .. 16m + 15 of the input tile, columns 16 wv .. 16 wv + 31
+        const h16x8 A = *(const h16x8*)(pl + (16 * m + n) * kMxCols + 16 * wv + 8 * g);
+        const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
+        const f32x4 big = __builtin_amdgcn_mfma_f32_16x16x32_f16(A, whi, zero, 0, 0, 0);
+        const f32x4 small = __builtin_amdgcn_mfma_f32_16x16x32_f16(A, wlo, zero, 0, 0, 0);
+        // 2^10 x the horizontal sum of input row 16m + 4g + i at output column
+        // 16 wv + n (the low taps' products summed apart: their roundings stay small)
+        float h[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) h[i] = (big[i] + small[i]) * (1.f / kMxScale);
+        const fp16x2 p0 = __builtin_amdgcn_cvt_pkrtz(h[0], h[1]);
+        const fp16x2 p1 = __builtin_amdgcn_cvt_pkrtz(h[2], h[3]);
+        const fp16x2 q0 = __builtin_amdgcn_cvt_pkrtz(h[0] - (float)p0.x, h[1] - (float)p0.y);
+        const fp16x2 q1 = __builtin_amdgcn_cvt_pkrtz(h[2] - (float)p1.x, h[3] - (float)p1.y);
+        *(mu32x2*)(hs + n * kMxPT + 16 * m + 4 * g) =
+            (mu32x2){__builtin_bit_cast(uint32_t, p0), __builtin_bit_cast(uint32_t, p1)};
+        *(mu32x2*)(hl + n * kMxPT + 16 * m + 4 * g) =
+            (mu32x2){__builtin_bit_cast(uint32_t, q0), __builtin_bit_cast(uint32_t, q1)};
+      }
+      asm volatile("" ::: "memory");
+#pragma unroll
+      for (int p = 0; p < kMxTY / 16; ++p) {
+        // horizontal sums of rows 16p .. 16p + 31 at this lane's column
+        const h16x8 Bh = *(const h16x8*)(hs + n * kMxPT + 16 * p + 8 * g);
+        const h16x8 Bl = *(const h16x8*)(hl + n * kMxPT + 16 * p + 8 * g);
+        const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
+        const f32x4 big = __builtin_amdgcn_mfma_f32_16x16x32_f16(whi, Bh, zero, 0, 0, 0);
+        f32x4 small = __builtin_amdgcn_mfma_f32_16x16x32_f16(wlo, Bh, zero, 0, 0, 0);
+        small = __builtin_amdgcn_mfma_f32_16x16x32_f16(whi, Bl, small, 0, 0, 0);
+        res[c][p] = (big + small) * (1.f / kMxScale);   // the output at row 16p + 4g + i, column 16 wv + n
+      }
+      asm volatile("" ::: "memory");   // this channel's reads before the next channel's writes
+    }
+  } else {
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+#pragma unroll
+      for (int p = 0; p < 2; ++p) res[c][p] = (f32x4){0.f, 0.f, 0.f, 0.f};
+  }
+
+  // in-focus flags and input values of the lane's outputs, read at once
+  uint32_t kf[2][4];
+  float iv[C][2][4];
+#pragma unroll
+  for (int p = 0; p < 2; ++p)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int yy = 16 * p + 4 * g + i;
+      kf[p][i] = keep[yy * kMxTX + xx];
+#pragma unroll
+      for (int c = 0; c < C; ++c) iv[c][p][i] = (float)P[c * G::plane + (yy + kMxRad) * kMxCols + xx + kMxRad];
+    }
+  // outputs: in-focus pixels keep their input value
+  float* o = out + ((int64_t)(y0 + 4 * g) * W + x0 + xx) * C;
+#pragma unroll
+  for (int p = 0; p < 2; ++p)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int yy = 16 * p + 4 * g + i;
+      const bool inside = y0 + yy < H && x0 + xx < W;
+      if (!kSink && !inside) continue;
+      float v[C];
+#pragma unroll
+      for (int c = 0; c < C; ++c) v[c] = kf[p][i] ? iv[c][p][i] : res[c][p][i];
+      float* op = inside ? o + (int64_t)(16 * p + i) * W * C : sink;
+      if constexpr (C == 3) {
+        *(g_mu32x3_rw*)op = (mu32x3){__builtin_bit_cast(uint32_t, v[0]), __builtin_bit_cast(uint32_t, v[1]),
+                                     __builtin_bit_cast(uint32_t, v[2])};
+      } else {
+        *(__attribute__((address_space(1))) float*)op = v[0];
+      }
+    }
+}
+
+// flags bit 0: image rows start on 4-byte boundaries. Workgroups below
+// T.nedge take one edge tile each; the others walk the interior tiles.
+template <int C, bool kDWords>
+__global__ __launch_bounds__(kMxThreads) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_blur_mfma(
+    const uint8_t* img, const uint8_t* depth, int32_t W, int32_t H, int64_t pitch, BlurArgs a, float* out, float* sink,
+    MxTiles T) {
+  using G = MxGeom<C>;
+  extern __shared__ __attribute__((aligned(16))) unsigned char mx_lds[];
+  _Float16* P = (_Float16*)mx_lds;
+  uint8_t* keep = mx_lds + G::planes;
+  float* taps = (float*)(mx_lds + G::planes + G::keep + 4 * G::hsum);
+  const int tid = threadIdx.x;
+  const int n = tid & 15, g = (tid & 63) >> 4;
+  if (tid < 64) {
+    const int t = tid - 24;
+    taps[tid] = (t >= 0 && t <= 2 * a.rad) ? a.g[t] * kMxScale : 0.f;
+  }
+
+  if ((int)blockIdx.x < T.nedge) {
+    const int e = blockIdx.x;
+    const int x0 = T.edge_cx(e % T.ecols) * kMxTX, y0 = (e / T.ecols) * kMxTY;
+    bool need = mx_flags_bytes(depth, W, H, x0, y0, tid, keep, a);
+    mx_stage_bytes<C>(img, W, H, pitch, x0, y0, tid, P);
+    need = __syncthreads_or(need);
+    h16x8 whi, wlo;
+    mx_weights(taps, a.rad, n, g, whi, wlo);
+    mx_sum_store<C, false>(mx_lds, tid, need, whi, wlo, x0, y0, W, H, out, sink);
+    return;
+  }
+  // interior tiles
+  const int step = gridDim.x - T.nedge;
+  int t = blockIdx.x - T.nedge;
+  if (t >= T.ninner) return;
+  auto origin = [&](int tt, int& x0, int& y0) {
+    x0 = (T.ilo + tt % T.icols) * kMxTX;
+    y0 = (tt / T.icols) * kMxTY;
+  };
+  MxLoads<C, kDWords> L;
+  {
+    int x0, y0;
+    origin(t, x0, y0);
+    mx_issue<C, kDWords>(img, depth, W, H, pitch, x0, y0, tid, L);
+  }
+  h16x8 whi, wlo;
+  bool have_w = false;
+  for (; t < T.ninner; t += step) {
+    int x0, y0;
+    origin(t, x0, y0);
+    __syncthreads();   // the previous tile's reads of the LDS are done (and the taps are written)
+    if (!have_w) { mx_weights(taps, a.rad, n, g, whi, wlo); have_w = true; }
+    bool need = mx_flags_loaded<kDWords>(L.dv, y0, H, tid, keep, a);
+    mx_stage_loaded<C>(L.gv, tid, P);
+    if (t + step < T.ninner) {
+      int nx0, ny0;
+      origin(t + step, nx0, ny0);
+      mx_issue<C, kDWords>(img, depth, W, H, pitch, nx0, ny0, tid, L);   // in flight while this tile is finished
+    }
+    need = __syncthreads_or(need);
+    mx_sum_store<C, true>(mx_lds, tid, need, whi, wlo, x0, y0, W, H, out, sink);
+  }
+}
+
+template <int C>
+void launch_blur_mfma(hipStream_t s, const uint8_t* img, const uint8_t* depth, int32_t W, int32_t H, int64_t pitch,
+                      bool img_words, bool depth_words, const BlurArgs& a, float* out, float* sink) {
+  MxTiles T{};
+  T.ntx = (W + kMxTX - 1) / kMxTX;
+  T.nty = (H + kMxTY - 1) / kMxTY;
+  // interior columns: cx >= 1 and 64 cx + 72 <= W
+  const int ihi = W >= kMxTX + kMxRad ? (W - kMxTX - kMxRad) / kMxTX : 0;
+  T.ilo = 1;
+  T.icols = img_words && ihi >= 1 ? ihi : 0;
+  T.ecols = T.ntx - T.icols;
+  T.nedge = T.ecols * T.nty;
+  T.ninner = T.icols * T.nty;
+  int dev = 0, cus = 256;
+  if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  // four workgroups fit a CU's LDS
+  const int inner_groups = std::min(T.ninner, 4 * std::max(cus, 1));
+  const dim3 grid((unsigned)(T.nedge + inner_groups));
+  if (depth_words)
+    hipLaunchKernelGGL((k_blur_mfma<C, true>), grid, dim3(kMxThreads), MxGeom<C>::lds, s, img, depth, W, H, pitch, a,
+                       out, sink, T);
+  else
+    hipLaunchKernelGGL((k_blur_mfma<C, false>), grid, dim3(kMxThreads), MxGeom<C>::lds, s, img, depth, W, H, pitch,
+                       a, out, sink, T);
+}
+
 int fail(int st, const char* fmt, ...) {
   char buf[256];
   va_list ap;
@@ -571,7 +981,14 @@ int sbs_selective_blur(const uint8_t* img, int32_t W, int32_t H, int32_t C, int6
   a.nranges = nranges;
   for (int t = 0; t < nranges; ++t) { a.lo[t] = ranges[2 * t]; a.hi[t] = ranges[2 * t + 1]; }
   hipStream_t s = (hipStream_t)stream;
-  if (rad <= kBlurTileRad) {
+  const int64_t mx_tiles = (int64_t)((W + kMxTX - 1) / kMxTX) * ((H + kMxTY - 1) / kMxTY);
+  if (rad <= kMxRad && mx_tiles < (1LL << 30)) {
+    const bool img_words = (((uintptr_t)img | (uintptr_t)pitch) & 3) == 0;
+    const bool depth_words = (((uintptr_t)depth | (uintptr_t)W) & 3) == 0;
+    float* sink = (float*)workspace;   // stores of lanes outside the image (12 bytes)
+    if (C == 3) launch_blur_mfma<3>(s, img, depth, W, H, pitch, img_words, depth_words, a, out, sink);
+    else launch_blur_mfma<1>(s, img, depth, W, H, pitch, img_words, depth_words, a, out, sink);
+  } else if (rad <= kBlurTileRad && (H + kBlurTY - 1) / kBlurTY <= 65535) {
     const int64_t tx = (W + kBlurTX - 1) / kBlurTX;
     const dim3 grid((unsigned)tx, (unsigned)((H + kBlurTY - 1) / kBlurTY));
     const int32_t aligned = (((uintptr_t)img | (uintptr_t)pitch) & 3) == 0 ? 1 : 0;

@@ -99,14 +99,17 @@ def test_blur_matches_oracle(mods, C, sigma):
     torch.cuda.synchronize()
     np.testing.assert_allclose(got.cpu().numpy(), exp, atol=1e-3, rtol=0)
 
+@pytest.mark.parametrize("W", [300, 298])
 @pytest.mark.parametrize("sigma", [2.0, 4.6])
-def test_blur_pitched_rows_over_many_tiles(mods, sigma):
+def test_blur_pitched_rows_over_many_tiles(mods, sigma, W):
     """An RGB image inside wider rows (pitch > W * 3), several 64 x 32 tiles
     with partial ones at the right and bottom, the largest radius the tiled
-    kernel takes (14 at sigma 4.6) and a common one (6 at sigma 2)."""
+    kernel takes (14 at sigma 4.6) and a common one (6 at sigma 2); a width
+    that is not a multiple of 4 (depth rows not word-aligned) with aligned
+    image rows."""
     torch, sbs = mods
     rng = np.random.default_rng(11)
-    H, W = 150, 300
+    H = 150
     wide = rng.integers(0, 256, (H, 320, 3), dtype=np.uint8)
     img = np.ascontiguousarray(wide[:, :W])
     depth = rng.integers(0, 60, (H, W), dtype=np.uint8)
@@ -118,6 +121,49 @@ def test_blur_pitched_rows_over_many_tiles(mods, sigma):
     torch.cuda.synchronize()
     np.testing.assert_allclose(got.cpu().numpy(), exp, atol=1e-3, rtol=0)
 
+
+
+@pytest.mark.parametrize("C,sigma", [(3, 0.3), (1, 2.3), (3, 2.3), (3, 2.6), (1, 2.6)])
+@pytest.mark.parametrize("H,W", [(1, 70), (37, 131), (96, 256), (33, 65)])
+def test_blur_matrix_core_radii(mods, C, sigma, H, W):
+    """Radii 1, 7 and 8 (the largest the matrix-core path takes): one-row
+    images, partial tiles, odd widths (rows not 4-byte aligned: the clamped
+    byte staging) and aligned widths (the dword staging)."""
+    torch, sbs = mods
+    rng = np.random.default_rng(17)
+    shape = (H, W) if C == 1 else (H, W, C)
+    img = rng.integers(0, 256, shape, dtype=np.uint8)
+    depth = rng.integers(0, 40, (H, W), dtype=np.uint8)
+    ranges = [(3, 9), (30, 35)]
+    exp = oracle.blur(img, depth, ranges, sigma)
+    got = sbs.selective_blur(torch.from_numpy(img).cuda(), torch.from_numpy(depth).cuda(), ranges, sigma)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(got.cpu().numpy(), exp, atol=1e-3, rtol=0)
+
+
+def test_blur_full_frame_4096x2304(mods):
+    """Every output of a 4096x2304 RGB frame at sigma 2 (radius 6, the paper
+    chain's setting) against the oracle: random bytes (the worst case for the
+    fp16 splits: every tap sees a full-range value), a depth map of 64 x 32
+    blocks in focus, out of focus and mixed."""
+    torch, sbs = mods
+    rng = np.random.default_rng(19)
+    H, W = 2304, 4096
+    img = rng.integers(0, 256, (H, W, 3), dtype=np.uint8)
+    kinds = rng.integers(0, 3, (H // 32, W // 64))
+    depth = rng.integers(0, 128, (H, W), dtype=np.uint8)
+    full = np.repeat(np.repeat(kinds, 32, axis=0), 64, axis=1)
+    depth[full == 0] = 10
+    depth[full == 1] = 100
+    ranges = [(0, 42)]
+    exp = oracle.blur(img, depth, ranges, 2.0)
+    got = sbs.selective_blur(torch.from_numpy(img).cuda(), torch.from_numpy(depth).cuda(), ranges, 2.0)
+    torch.cuda.synchronize()
+    err = np.abs(got.cpu().numpy().astype(np.float64) - exp)
+    assert err.max() <= 1e-3, f"max |err| {err.max():.3g}"
+    # in-focus pixels are copied exactly
+    keep = (depth <= 42)
+    assert np.array_equal(got.cpu().numpy()[keep], img[keep].astype(np.float32))
 
 
 @pytest.mark.parametrize("C,sigma", [(3, 2.0), (1, 1.2), (3, 4.6)])
