@@ -520,6 +520,9 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned int mu32x2 __attribute__((ext_vector_type(2)));
 typedef unsigned int mu32x3 __attribute__((ext_vector_type(3)));
 typedef __attribute__((address_space(1))) const mu32x3 g_mu32x3;
+typedef __attribute__((address_space(1))) const mu32x2 g_mu32x2;
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(1))) const u32x4 g_u32x4;
 typedef __attribute__((address_space(1))) const uint32_t g_mu32;
 typedef __attribute__((address_space(1))) mu32x3 g_mu32x3_rw;
 
@@ -556,9 +559,8 @@ __device__ __forceinline__ uint32_t byte_pair_f16(uint32_t word_with_64) {
 }
 
 // The tiles: interior tiles (input columns x0 - 8 .. x0 + 71 inside the
-// image, 4-byte-aligned image rows) load their input as dword groups;
-// edge tiles (and every tile of images whose rows are not aligned) byte by
-// byte with clamped columns. Edge tiles take one workgroup each; interior
+// image) load their input as word groups; edge tiles byte by byte with
+// clamped columns. Edge tiles take one workgroup each; interior
 // tiles go to a persistent set of workgroups that load the next tile's
 // words into registers while they sum and write the current one. Every lane
 // of an interior tile issues the same loads and stores (rows clamped; the
@@ -568,7 +570,6 @@ constexpr int kMxGroups = kMxCols / 4;                      // 4-pixel groups pe
 constexpr int kMxItems = kMxRows * kMxGroups;               // 960
 constexpr int kMxPer = (kMxItems + kMxThreads - 1) / kMxThreads;
 constexpr int kMxDWords = kMxTY * (kMxTX / 4) / kMxThreads; // depth words per thread: 2
-constexpr int kMxDBytes = kMxTY * kMxTX / kMxThreads;       // depth bytes per thread: 8
 
 struct MxTiles {
   int32_t ntx, nty;         // tiles per row and column
@@ -578,38 +579,60 @@ struct MxTiles {
   __device__ __forceinline__ int edge_cx(int ec) const { return icols == 0 ? ec : (ec == 0 ? 0 : ilo + icols - 1 + ec); }
 };
 
-template <int C, bool kDWords>
+// Words of a 4-pixel group as loaded: from the group's first byte when image
+// rows are 4-byte aligned (3 words of RGB, 1 of grey), else from the word
+// boundary below it (one word more, shifted into place when staged).
+template <int C, bool kARows>
+constexpr int kMxGroupWords = (C == 3 ? 3 : 1) + (kARows ? 0 : 1);
+
+template <int C, bool kDWords, bool kARows>
 struct MxLoads {
-  mu32x3 gv[kMxPer];
-  uint32_t dv[kDWords ? kMxDWords : kMxDBytes];
+  uint32_t gw[kMxPer][kMxGroupWords<C, kARows>];
+  uint32_t dv[kMxDWords][kDWords ? 1 : 2];   // depth words (from the word boundary below where rows are unaligned)
 };
 
+// first byte of 4-pixel group q of input row r (row clamped)
+template <int C>
+__device__ __forceinline__ const uint8_t* mx_group(const uint8_t* img, int H, int64_t pitch, int x0, int y0, int r,
+                                                   int q) {
+  const int yy = min(max(y0 - kMxRad + r, 0), H - 1);
+  return img + (int64_t)yy * pitch + (int64_t)(x0 - kMxRad + 4 * q) * C;
+}
+
 // one interior tile's loads, the same for every lane and tile
-template <int C, bool kDWords>
+template <int C, bool kDWords, bool kARows>
 __device__ __forceinline__ void mx_issue(const uint8_t* img, const uint8_t* depth, int W, int H, int64_t pitch, int x0,
-                                         int y0, int tid, MxLoads<C, kDWords>& L) {
+                                         int y0, int tid, MxLoads<C, kDWords, kARows>& L) {
 #pragma unroll
   for (int k = 0; k < kMxPer; ++k) {
     const int ic = min(tid + k * kMxThreads, kMxItems - 1);   // past the last group: the last group again
     const int r = ic / kMxGroups, q = ic - r * kMxGroups;
-    const int yy = min(max(y0 - kMxRad + r, 0), H - 1);
-    const uint8_t* src = img + (int64_t)yy * pitch + (int64_t)(x0 - kMxRad + 4 * q) * C;
-    if constexpr (C == 3) L.gv[k] = *(g_mu32x3*)src;
-    else L.gv[k] = (mu32x3){*(g_mu32*)src, 0u, 0u};
-  }
-  if constexpr (kDWords) {
-#pragma unroll
-    for (int k = 0; k < kMxDWords; ++k) {
-      const int i = tid + k * kMxThreads;
-      const int r = i / (kMxTX / 4), q = i - r * (kMxTX / 4);
-      L.dv[k] = *(g_mu32*)(depth + (int64_t)min(y0 + r, H - 1) * W + x0 + 4 * q);
+    const uint8_t* src = mx_group<C>(img, H, pitch, x0, y0, r, q);
+    if constexpr (!kARows) src = (const uint8_t*)((uintptr_t)src & ~(uintptr_t)3);
+    constexpr int nw = kMxGroupWords<C, kARows>;
+    if constexpr (nw == 4) {
+      const u32x4 v = *(g_u32x4*)src;
+      L.gw[k][0] = v.x; L.gw[k][1] = v.y; L.gw[k][2] = v.z; L.gw[k][3] = v.w;
+    } else if constexpr (nw == 3) {
+      const mu32x3 v = *(g_mu32x3*)src;
+      L.gw[k][0] = v.x; L.gw[k][1] = v.y; L.gw[k][2] = v.z;
+    } else if constexpr (nw == 2) {
+      const mu32x2 v = *(g_mu32x2*)src;
+      L.gw[k][0] = v.x; L.gw[k][1] = v.y;
+    } else {
+      L.gw[k][0] = *(g_mu32*)src;
     }
-  } else {
+  }
 #pragma unroll
-    for (int k = 0; k < kMxDBytes; ++k) {
-      const int i = tid + k * kMxThreads;
-      const int r = i / kMxTX, x = i - r * kMxTX;
-      L.dv[k] = depth[(int64_t)min(y0 + r, H - 1) * W + x0 + x];
+  for (int k = 0; k < kMxDWords; ++k) {
+    const int i = tid + k * kMxThreads;
+    const int r = i / (kMxTX / 4), q = i - r * (kMxTX / 4);
+    const uint8_t* d = depth + (int64_t)min(y0 + r, H - 1) * W + x0 + 4 * q;
+    if constexpr (kDWords) {
+      L.dv[k][0] = *(g_mu32*)d;
+    } else {
+      const mu32x2 v = *(g_mu32x2*)((uintptr_t)d & ~(uintptr_t)3);
+      L.dv[k][0] = v.x; L.dv[k][1] = v.y;
     }
   }
 }
@@ -617,35 +640,29 @@ __device__ __forceinline__ void mx_issue(const uint8_t* img, const uint8_t* dept
 // in-focus flags from an interior tile's depth loads (1 below the image);
 // returns whether this thread saw a pixel to blur
 template <bool kDWords>
-__device__ __forceinline__ bool mx_flags_loaded(const uint32_t* dv, int y0, int H, int tid, uint8_t* keep,
-                                                const BlurArgs& a) {
+__device__ __forceinline__ bool mx_flags_loaded(const uint32_t (*dv)[kDWords ? 1 : 2], const uint8_t* depth, int W,
+                                                int H, int x0, int y0, int tid, uint8_t* keep, const BlurArgs& a) {
   bool need = false;
   const bool one = a.nranges == 1;
   const uint32_t lo = (uint32_t)a.lo[0], span = (uint32_t)(a.hi[0] - a.lo[0]);
   auto bit = [&](uint32_t d) -> uint32_t {
     return (one ? d - lo <= span : in_focus((int)d, a)) ? 1u : 0u;
   };
-  if constexpr (kDWords) {
 #pragma unroll
-    for (int k = 0; k < kMxDWords; ++k) {
-      const int i = tid + k * kMxThreads;
-      const int r = i / (kMxTX / 4), q = i - r * (kMxTX / 4);
-      uint32_t kw = 0u;
-#pragma unroll
-      for (int j = 0; j < 4; ++j) kw |= bit((dv[k] >> (8 * j)) & 0xFFu) << (8 * j);
-      if (y0 + r >= H) kw = 0x01010101u;
-      *(uint32_t*)(keep + r * kMxTX + 4 * q) = kw;
-      need |= kw != 0x01010101u;
+  for (int k = 0; k < kMxDWords; ++k) {
+    const int i = tid + k * kMxThreads;
+    const int r = i / (kMxTX / 4), q = i - r * (kMxTX / 4);
+    uint32_t w = dv[k][0];
+    if constexpr (!kDWords) {
+      const uint32_t sh = (uint32_t)(uintptr_t)(depth + (int64_t)min(y0 + r, H - 1) * W + x0 + 4 * q) & 3u;
+      w = __builtin_amdgcn_alignbyte(dv[k][1], dv[k][0], sh);
     }
-  } else {
+    uint32_t kw = 0u;
 #pragma unroll
-    for (int k = 0; k < kMxDBytes; ++k) {
-      const int i = tid + k * kMxThreads;
-      const int r = i / kMxTX;
-      const uint32_t kb = y0 + r >= H ? 1u : bit(dv[k]);
-      keep[i] = (uint8_t)kb;
-      need |= kb == 0u;
-    }
+    for (int j = 0; j < 4; ++j) kw |= bit((w >> (8 * j)) & 0xFFu) << (8 * j);
+    if (y0 + r >= H) kw = 0x01010101u;
+    *(uint32_t*)(keep + r * kMxTX + 4 * q) = kw;
+    need |= kw != 0x01010101u;
   }
   return need;
 }
@@ -664,9 +681,10 @@ __device__ __forceinline__ bool mx_flags_bytes(const uint8_t* depth, int W, int 
   return need;
 }
 
-// planar fp16 input tile from an interior tile's dword groups
-template <int C>
-__device__ __forceinline__ void mx_stage_loaded(const mu32x3* gv, int tid, _Float16* P) {
+// planar fp16 input tile from an interior tile's loaded groups
+template <int C, bool kDWords, bool kARows>
+__device__ __forceinline__ void mx_stage_loaded(const MxLoads<C, kDWords, kARows>& L, const uint8_t* img, int H,
+                                                int64_t pitch, int x0, int y0, int tid, _Float16* P) {
   const uint32_t k64 = 0x64646464u;
 #pragma unroll
   for (int k = 0; k < kMxPer; ++k) {
@@ -674,8 +692,18 @@ __device__ __forceinline__ void mx_stage_loaded(const mu32x3* gv, int tid, _Floa
     if (i < kMxItems) {   // (the last wavefront's fourth group only)
       const int r = i / kMxGroups, q = i - r * kMxGroups;
       _Float16* dst = P + r * kMxCols + 4 * q;
+      // the group's words, shifted into place when loaded from the word below
+      uint32_t gw[C == 3 ? 3 : 1];
+      if constexpr (kARows) {
+#pragma unroll
+        for (int j = 0; j < (C == 3 ? 3 : 1); ++j) gw[j] = L.gw[k][j];
+      } else {
+        const uint32_t sh = (uint32_t)(uintptr_t)mx_group<C>(img, H, pitch, x0, y0, r, q) & 3u;
+#pragma unroll
+        for (int j = 0; j < (C == 3 ? 3 : 1); ++j) gw[j] = __builtin_amdgcn_alignbyte(L.gw[k][j + 1], L.gw[k][j], sh);
+      }
       if constexpr (C == 3) {
-        const uint32_t w0 = gv[k].x, w1 = gv[k].y, w2 = gv[k].z;
+        const uint32_t w0 = gw[0], w1 = gw[1], w2 = gw[2];
         // w0 = R0 G0 B0 R1, w1 = G1 B1 R2 G2, w2 = B2 R3 G3 B3 (lowest byte first)
         const uint32_t r01 = byte_pair_f16(__builtin_amdgcn_perm(w0, k64, 0x00070004u));
         const uint32_t r23 = byte_pair_f16(__builtin_amdgcn_perm(w2, w1, 0x0c050c02u) | 0x64006400u);
@@ -688,7 +716,7 @@ __device__ __forceinline__ void mx_stage_loaded(const mu32x3* gv, int tid, _Floa
         *(mu32x2*)(dst + plane) = (mu32x2){g01, g23};
         *(mu32x2*)(dst + 2 * plane) = (mu32x2){b01, b23};
       } else {
-        const uint32_t w = gv[k].x;
+        const uint32_t w = gw[0];
         *(mu32x2*)dst = (mu32x2){byte_pair_f16(__builtin_amdgcn_perm(w, k64, 0x00050004u)),
                                  byte_pair_f16(__builtin_amdgcn_perm(w, k64, 0x00070006u))};
       }
@@ -816,7 +844,7 @@ __device__ __forceinline__ void mx_sum_store(const unsigned char* lds, int tid, 
 
 // flags bit 0: image rows start on 4-byte boundaries. Workgroups below
 // T.nedge take one edge tile each; the others walk the interior tiles.
-template <int C, bool kDWords>
+template <int C, bool kDWords, bool kARows>
 __global__ __launch_bounds__(kMxThreads) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_blur_mfma(
     const uint8_t* img, const uint8_t* depth, int32_t W, int32_t H, int64_t pitch, BlurArgs a, float* out, float* sink,
     MxTiles T) {
@@ -851,11 +879,11 @@ __global__ __launch_bounds__(kMxThreads) __attribute__((amdgpu_waves_per_eu(4, 8
     x0 = (T.ilo + tt % T.icols) * kMxTX;
     y0 = (tt / T.icols) * kMxTY;
   };
-  MxLoads<C, kDWords> L;
+  MxLoads<C, kDWords, kARows> L;
   {
     int x0, y0;
     origin(t, x0, y0);
-    mx_issue<C, kDWords>(img, depth, W, H, pitch, x0, y0, tid, L);
+    mx_issue<C, kDWords, kARows>(img, depth, W, H, pitch, x0, y0, tid, L);
   }
   h16x8 whi, wlo;
   bool have_w = false;
@@ -864,12 +892,12 @@ __global__ __launch_bounds__(kMxThreads) __attribute__((amdgpu_waves_per_eu(4, 8
     origin(t, x0, y0);
     __syncthreads();   // the previous tile's reads of the LDS are done (and the taps are written)
     if (!have_w) { mx_weights(taps, a.rad, n, g, whi, wlo); have_w = true; }
-    bool need = mx_flags_loaded<kDWords>(L.dv, y0, H, tid, keep, a);
-    mx_stage_loaded<C>(L.gv, tid, P);
+    bool need = mx_flags_loaded<kDWords>(L.dv, depth, W, H, x0, y0, tid, keep, a);
+    mx_stage_loaded<C, kDWords, kARows>(L, img, H, pitch, x0, y0, tid, P);
     if (t + step < T.ninner) {
       int nx0, ny0;
       origin(t + step, nx0, ny0);
-      mx_issue<C, kDWords>(img, depth, W, H, pitch, nx0, ny0, tid, L);   // in flight while this tile is finished
+      mx_issue<C, kDWords, kARows>(img, depth, W, H, pitch, nx0, ny0, tid, L);   // in flight while this tile is finished
     }
     need = __syncthreads_or(need);
     mx_sum_store<C, true>(mx_lds, tid, need, whi, wlo, x0, y0, W, H, out, sink);
@@ -882,10 +910,13 @@ void launch_blur_mfma(hipStream_t s, const uint8_t* img, const uint8_t* depth, i
   MxTiles T{};
   T.ntx = (W + kMxTX - 1) / kMxTX;
   T.nty = (H + kMxTY - 1) / kMxTY;
-  // interior columns: cx >= 1 and 64 cx + 72 <= W
-  const int ihi = W >= kMxTX + kMxRad ? (W - kMxTX - kMxRad) / kMxTX : 0;
+  // interior columns: cx >= 1 and 64 cx + 72 <= W (+ 4 where image rows are
+  // not word-aligned: a group's words are loaded from the word boundary below
+  // it, up to 4 bytes past the tile's last input byte)
+  const int reach = kMxTX + kMxRad + (img_words ? 0 : 4);
+  const int ihi = W >= reach ? (W - reach) / kMxTX : 0;
   T.ilo = 1;
-  T.icols = img_words && ihi >= 1 ? ihi : 0;
+  T.icols = ihi >= 1 ? ihi : 0;
   T.ecols = T.ntx - T.icols;
   T.nedge = T.ecols * T.nty;
   T.ninner = T.icols * T.nty;
@@ -894,12 +925,16 @@ void launch_blur_mfma(hipStream_t s, const uint8_t* img, const uint8_t* depth, i
   // four workgroups fit a CU's LDS
   const int inner_groups = std::min(T.ninner, 4 * std::max(cus, 1));
   const dim3 grid((unsigned)(T.nedge + inner_groups));
-  if (depth_words)
-    hipLaunchKernelGGL((k_blur_mfma<C, true>), grid, dim3(kMxThreads), MxGeom<C>::lds, s, img, depth, W, H, pitch, a,
-                       out, sink, T);
-  else
-    hipLaunchKernelGGL((k_blur_mfma<C, false>), grid, dim3(kMxThreads), MxGeom<C>::lds, s, img, depth, W, H, pitch,
-                       a, out, sink, T);
+  auto go = [&](auto kern) {
+    hipLaunchKernelGGL(kern, grid, dim3(kMxThreads), MxGeom<C>::lds, s, img, depth, W, H, pitch, a, out, sink, T);
+  };
+  if (img_words) {
+    if (depth_words) go(k_blur_mfma<C, true, true>);
+    else go(k_blur_mfma<C, false, true>);
+  } else {
+    if (depth_words) go(k_blur_mfma<C, true, false>);
+    else go(k_blur_mfma<C, false, false>);
+  }
 }
 
 int fail(int st, const char* fmt, ...) {

@@ -124,11 +124,12 @@ def test_blur_pitched_rows_over_many_tiles(mods, sigma, W):
 
 
 @pytest.mark.parametrize("C,sigma", [(3, 0.3), (1, 2.3), (3, 2.3), (3, 2.6), (1, 2.6)])
-@pytest.mark.parametrize("H,W", [(1, 70), (37, 131), (96, 256), (33, 65)])
+@pytest.mark.parametrize("H,W", [(1, 70), (37, 131), (96, 256), (33, 65), (70, 301)])
 def test_blur_matrix_core_radii(mods, C, sigma, H, W):
     """Radii 1, 7 and 8 (the largest the matrix-core path takes): one-row
-    images, partial tiles, odd widths (rows not 4-byte aligned: the clamped
-    byte staging) and aligned widths (the dword staging)."""
+    images, partial tiles, odd widths (rows not 4-byte aligned: word loads
+    from the boundary below, shifted into place, for interior tiles at 301
+    columns; clamped bytes for the edge tiles) and aligned widths."""
     torch, sbs = mods
     rng = np.random.default_rng(17)
     shape = (H, W) if C == 1 else (H, W, C)
