@@ -177,6 +177,7 @@ __global__ __launch_bounds__(kBlock) void k_hist(const uint8_t* __restrict__ L8,
 __global__ __launch_bounds__(256) void k_kmeans(const unsigned long long* __restrict__ hist, int32_t K,
                                                 uint8_t* __restrict__ lut, int32_t* __restrict__ passes_out) {
   __shared__ long long S[kMaxK], Nn[kMaxK];
+  __shared__ double M[kMaxK];   // S / N rounded to double
   __shared__ unsigned long long s2[kMaxK], n2[kMaxK];
   __shared__ int lo_s, hi_s, changed;
   __shared__ int rank[kMaxK];
@@ -197,15 +198,30 @@ __global__ __launch_bounds__(256) void k_kmeans(const unsigned long long* __rest
   int pass = 0;
   for (; pass < kMaxPasses; ++pass) {
     if (b == 0) changed = 0;
-    if (b < K) { s2[b] = 0; n2[b] = 0; }
+    if (b < K) {
+      s2[b] = 0;
+      n2[b] = 0;
+      M[b] = (double)S[b] / (double)Nn[b];   // S < 2^40 and N < 2^32: both exact, the quotient rounded once
+    }
     __syncthreads();
     if (hb > 0) {
+      // |b - S_k/N_k| < |b - S_best/N_best|, decided on the rounded means
+      // where they differ by more than their rounding (|error| < 2^-44 for
+      // means in [0, 255]), else exactly:
+      //   |b N_k - S_k| N_best < |b N_best - S_best| N_k
       int best = 0;
+      long long Sb = S[0], Nb = Nn[0];
+      double db = fabs((double)b - M[0]);
       for (int k = 1; k < K; ++k) {
-        // |b - S_k/N_k| < |b - S_best/N_best|  <=>  |b N_k - S_k| N_best < |b N_best - S_best| N_k
-        const long long dk = llabs((long long)b * Nn[k] - S[k]);
-        const long long db = llabs((long long)b * Nn[best] - S[best]);
-        if ((__int128)dk * Nn[best] < (__int128)db * Nn[k]) best = k;
+        const double dk = fabs((double)b - M[k]);
+        bool closer;
+        if (dk < db - 0x1p-40) closer = true;
+        else if (dk > db + 0x1p-40) closer = false;
+        else {
+          const long long Sk = S[k], Nk = Nn[k];
+          closer = (__int128)llabs((long long)b * Nk - Sk) * Nb < (__int128)llabs((long long)b * Nb - Sb) * Nk;
+        }
+        if (closer) { best = k; db = dk; Sb = S[k]; Nb = Nn[k]; }
       }
       if (assign != best) { assign = best; changed = 1; }
     }

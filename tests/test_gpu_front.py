@@ -161,3 +161,32 @@ def test_fraction_control_wide_rows_and_far_pixels(torch, sbs):
             got = sbs.boundaries(d, K=2, mode=0, min_cc=1, frac=frac, seed=5).cpu().numpy().view(np.uint32)
             exp = oracle.boundaries(img, K=2, mode=0, min_cc=1, frac=frac, seed=5)
             assert np.array_equal(got, exp), f"{H}x{W} frac {frac}"
+
+
+def test_kmeans_ties_on_few_grey_levels(torch, sbs):
+    """Histograms of a few evenly spaced grey levels with equal or small
+    counts: bins that lie exactly halfway between two centres (the tie goes
+    to the centre tried first) and means that round alike in floating point,
+    for K from 2 to 9, checked through the label image."""
+    rng = np.random.default_rng(23)
+    cases = []
+    for step in range(1, 21):   # symmetric three- and five-level images: ties in the first pass
+        for levels, K in ((3, 2), (5, 2), (5, 3), (5, 4)):
+            base = int(rng.integers(0, 256 - step * (levels - 1)))
+            cases.append((base + step * np.arange(levels), np.ones(levels, np.int64), K))
+    for trial in range(60):
+        levels = int(rng.integers(2, 7))
+        step = int(rng.integers(1, 40))
+        base = int(rng.integers(0, 256 - step * (levels - 1)))
+        cases.append((base + step * np.arange(levels), rng.integers(1, 4, levels) * (1 if trial % 2 else 5),
+                      int(rng.integers(2, 10))))
+    for trial, (vals, counts, K) in enumerate(cases):
+        pix = np.repeat(vals, counts).astype(np.uint8)
+        side = int(np.ceil(np.sqrt(pix.size)))
+        img = np.full(side * side, pix[-1], np.uint8)
+        img[:pix.size] = pix
+        img = img.reshape(side, side)
+        d = torch.from_numpy(img).cuda()
+        _, _, labels = sbs.boundaries(d, K=K, mode=1, min_cc=50, with_maps=True)
+        exp = oracle_labels(img, K, 1)
+        assert np.array_equal(labels.cpu().numpy(), exp), f"trial {trial}: levels {vals} counts {counts} K {K}"
