@@ -263,8 +263,13 @@ int sbs_reconstruct(const uint32_t* idx, const uint8_t* disp, int64_t n, int32_t
  *   depth       device, W*H u8
  *   ranges      HOST array of nranges (lo, hi) pairs, nranges <= 16
  *   out         device, W*H*C float32, HWC, not rounded
- *   workspace   device, >= sbs_selective_blur_workspace_bytes(W, H, C)
- * Computed in fp32 (separable passes); SBS_ERR_UNSUPPORTED if ceil(3 sigma) > 64.
+ *   workspace   device, >= sbs_selective_blur_workspace_bytes(W, H, C), 4-byte
+ *               aligned (radius <= 8 uses its first 12 bytes as a sink for
+ *               stores outside the image; larger radii hold a float image)
+ * Separable passes with fp32 sums. Radius ceil(3 sigma) <= 8: on the matrix
+ * cores, taps and horizontal sums carried as fp16 high/low pairs, within
+ * about 4e-4 of exact on outputs in [0, 255]; radius 9..64: fp32 taps on
+ * the vector units. SBS_ERR_UNSUPPORTED if ceil(3 sigma) > 64.
  */
 size_t sbs_selective_blur_workspace_bytes(int32_t W, int32_t H, int32_t C);
 int sbs_selective_blur(const uint8_t* img, int32_t W, int32_t H, int32_t C, int64_t pitch, const uint8_t* depth,
