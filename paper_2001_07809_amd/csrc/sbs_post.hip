@@ -1007,6 +1007,7 @@ int sbs_selective_blur(const uint8_t* img, int32_t W, int32_t H, int32_t C, int6
   const int rad = (int)std::ceil(3.0 * (double)sigma);
   if (rad > kMaxRadius) return fail(SBS_ERR_UNSUPPORTED, "sigma too large (radius %d > %d)", rad, kMaxRadius);
   if (workspace_bytes < sbs_selective_blur_workspace_bytes(W, H, C)) return fail(SBS_ERR_INVALID_ARG, "workspace too small");
+  if (((uintptr_t)workspace & 3) != 0) return fail(SBS_ERR_INVALID_ARG, "workspace not 4-byte aligned");
   BlurArgs a{};
   double gs = 0.0;
   double g[2 * kMaxRadius + 1];

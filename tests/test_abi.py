@@ -119,3 +119,21 @@ def test_probe_rejects_bad_arguments_on_host():
     assert lib.sbs_probe_sad_rate(0, 10, ctypes.byref(r), ctypes.byref(t)) == 1
     assert lib.sbs_probe_sad_rate(10, 0, ctypes.byref(r), ctypes.byref(t)) == 1
     assert lib.sbs_probe_sad_rate(10, 10, None, ctypes.byref(t)) == 1
+
+
+def test_blur_rejects_bad_arguments_on_host():
+    lib = sbs.lib()
+    p = ctypes.c_void_p(256)
+    rg = (ctypes.c_int32 * 2)(0, 10)
+    need = lib.sbs_selective_blur_workspace_bytes(64, 32, 3)
+    f = ctypes.c_float
+    # geometry, ranges, sigma, workspace size and alignment: refused before any device work
+    assert lib.sbs_selective_blur(p, 0, 32, 3, 192, p, rg, 1, f(2.0), p, p, need, None) == 1
+    assert lib.sbs_selective_blur(p, 64, 32, 2, 192, p, rg, 1, f(2.0), p, p, need, None) == 1
+    assert lib.sbs_selective_blur(p, 64, 32, 3, 100, p, rg, 1, f(2.0), p, p, need, None) == 1
+    assert lib.sbs_selective_blur(p, 64, 32, 3, 192, p, rg, 17, f(2.0), p, p, need, None) == 1
+    assert lib.sbs_selective_blur(p, 64, 32, 3, 192, p, rg, 1, f(0.0), p, p, need, None) == 1
+    assert lib.sbs_selective_blur(p, 64, 32, 3, 192, p, rg, 1, f(2.0), p, p, need - 1, None) == 1
+    assert lib.sbs_selective_blur(p, 64, 32, 3, 192, p, rg, 1, f(2.0), p, ctypes.c_void_p(258), need, None) == 1
+    assert "aligned" in lib.sbs_last_error().decode()
+    assert lib.sbs_selective_blur(p, 64, 32, 3, 192, p, rg, 1, f(30.0), p, p, need, None) == 2
