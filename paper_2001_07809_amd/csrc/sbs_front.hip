@@ -885,6 +885,10 @@ struct ScanCtx {
   int32_t* frank;         // kinds 2, 3 output: rank of a tie in raster order
   unsigned long long seed;
   const uint8_t* cls;     // fraction control: 0 border column, 1 kept, 2 other
+  // The flags of a scan, one bit per element (word i >> 6, bit i & 63):
+  // written by the counting pass, read by the applying pass instead of
+  // working the flags out again (nullptr: both passes work them out).
+  unsigned long long* bits;
 };
 
 // Kept: the pixel's component (root r, -1 for no boundary pixel) passes the filter.
@@ -990,9 +994,16 @@ __global__ __launch_bounds__(kBlock) void k_scan_count(ScanCtx c, uint32_t* bsum
   __syncthreads();
   const int64_t i0 = (int64_t)blockIdx.x * kScanPer;
   uint32_t m = 0;
-  for (int j = threadIdx.x; j < kScanPer; j += kBlock) {
-    const int64_t i = i0 + j;
-    if (i < c.N && flag<KIND>(c, i)) ++m;
+#pragma unroll
+  for (int j0 = 0; j0 < kScanPer; j0 += kBlock) {
+    const int64_t i = i0 + j0 + threadIdx.x;
+    const bool fl = i < c.N && flag<KIND>(c, i);
+    m += fl;
+    if (c.bits) {
+      // the wavefront's 64 consecutive elements as one word
+      const unsigned long long w = __builtin_amdgcn_ballot_w64(fl);
+      if ((threadIdx.x & 63) == 0) c.bits[(i0 + j0 + threadIdx.x) >> 6] = w;
+    }
   }
   m = wave_scan_incl(m);   // lane 63: the wavefront's count
   if ((threadIdx.x & 63) == 63) atomicAdd(&s, m);
@@ -1027,11 +1038,21 @@ __global__ __launch_bounds__(kBlock) void k_scan_apply(ScanCtx c, const uint32_t
   constexpr int per = kScanPer / kBlock;
   bool f[per];
   uint32_t m = 0;
+  if (c.bits) {
+    const int64_t e = i0 + (int64_t)threadIdx.x * per;   // per divides 64: one word holds the thread's flags
+    const unsigned long long w = c.bits[e >> 6] >> (e & 63);
 #pragma unroll
-  for (int j = 0; j < per; ++j) {
-    const int64_t i = i0 + (int64_t)threadIdx.x * per + j;
-    f[j] = i < c.N && flag<KIND>(c, i);
-    m += f[j];
+    for (int j = 0; j < per; ++j) {
+      f[j] = (w >> j) & 1ull;
+      m += f[j];
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < per; ++j) {
+      const int64_t i = i0 + (int64_t)threadIdx.x * per + j;
+      f[j] = i < c.N && flag<KIND>(c, i);
+      m += f[j];
+    }
   }
   uint32_t all;
   uint32_t pos = bsum[blockIdx.x] + block_scan_excl<kBlock / 64>(m, sc, all);
@@ -1564,7 +1585,7 @@ int fail(int st, const char* fmt, ...) {
 size_t a256(size_t v) { return (v + 255) / 256 * 256; }
 
 struct Layout {
-  size_t L8, lab, lab2, B, parent, size, cnt, bsum, hist, g, dist, frank, rhist, dhist, lut, misc, end;
+  size_t L8, lab, lab2, B, parent, size, cnt, bsum, bits, hist, g, dist, frank, rhist, dhist, lut, misc, end;
 };
 
 Layout layout(int32_t W, int32_t H) {
@@ -1582,6 +1603,7 @@ Layout layout(int32_t W, int32_t H) {
   o.size = take((size_t)N * 4);
   o.cnt = take(((size_t)N + 1) * 4);
   o.bsum = take(((size_t)(N + kScanPer - 1) / kScanPer + 1) * 4);
+  o.bits = take((size_t)(N + kScanPer - 1) / kScanPer * (kScanPer / 8));
   o.hist = take(256 * 8);
   o.g = take((size_t)N * 4);
   o.dist = take((size_t)std::max<int64_t>(N, seg_words) * 4);
@@ -1744,6 +1766,7 @@ int sbs_boundaries(const uint8_t* img, int32_t W, int32_t H, int32_t C, int64_t 
   c.B = B; c.parent = parent; c.size = size; c.rule = nullptr; c.min_cc = min_cc; c.W = W; c.N = N;
   c.rank = cnt;   // the rank array reuses cnt: ranks are written after k_drop_find has read the counts
   c.out = out_idx; c.refined = out_refined; c.count = (long long*)out_count;
+  c.bits = (unsigned long long*)(base + Lo.bits);
   if (mode == 1) {
     hipLaunchKernelGGL(k_fill, dim3(g), dim3(kBlock), 0, s, (uint8_t*)cnt, (int64_t)(N + 1) * 4, (uint8_t)0);
     // at most 512 blocks: each block's closing adds (its total and its small
@@ -1822,6 +1845,9 @@ int sbs_boundaries(const uint8_t* img, int32_t W, int32_t H, int32_t C, int64_t 
     hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, bsum, nb, (long long*)nullptr);
     hipLaunchKernelGGL(k_scan_apply<3>, dim3((unsigned)nb), dim3(kBlock), 0, s, c, bsum);
   }
+  // the kept map, when asked for, is worked out per element in the applying
+  // pass anyway: the flags are then worked out there too
+  if (out_refined) c.bits = nullptr;
   hipLaunchKernelGGL(k_scan_count<1>, dim3((unsigned)nb), dim3(kBlock), 0, s, c, bsum);
   hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, bsum, nb, (long long*)out_count);
   hipLaunchKernelGGL(k_scan_apply<1>, dim3((unsigned)nb), dim3(kBlock), 0, s, c, bsum);
