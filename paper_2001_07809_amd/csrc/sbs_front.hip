@@ -1032,10 +1032,11 @@ __global__ __launch_bounds__(1024) void k_scan_top(uint32_t* bsum, int64_t nb, l
 
 template <int KIND>
 __global__ __launch_bounds__(kBlock) void k_scan_apply(ScanCtx c, const uint32_t* bsum) {
-  // thread t owns elements i0 + 4t .. i0 + 4t + 3 (in order)
+  // thread t owns elements i0 + per t .. i0 + per t + per - 1 (in order)
   __shared__ uint32_t sc[kBlock / 64];
   const int64_t i0 = (int64_t)blockIdx.x * kScanPer;
   constexpr int per = kScanPer / kBlock;
+  static_assert(64 % per == 0, "a thread's flags lie in one word");
   bool f[per];
   uint32_t m = 0;
   if (c.bits) {
