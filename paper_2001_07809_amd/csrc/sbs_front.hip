@@ -36,6 +36,7 @@ namespace sbs_front {
 
 constexpr int kBlock = 256;
 constexpr int kScanPer = 1024;     // elements per block in the device-wide scans
+constexpr int kRsPasses = 8;       // most counting passes of one radix select (a 64-bit key)
 constexpr int kMaxK = 64;
 constexpr int kMaxPasses = 1000;
 constexpr int kN1Parts = 64;        // partial counts of kept pixels (fraction control)
@@ -1173,13 +1174,48 @@ __device__ __forceinline__ bool rs_key(const ScanCtx& c, int64_t i, unsigned lon
 // keys whose higher digits match the prefix so far, in 16 bank-staggered LDS
 // copies (lane l adds to copy l % 16; see k_hist), then one global add per
 // digit and block.
+// The state of a select after the pick of a finished pass: the digit d at
+// `shift` whose count range holds the wanted rank (counts of smaller digits
+// before it), taken by every block of the next pass from that pass's counts
+// (256 threads, one digit each), so that no launch is needed for the pick.
+// Block 0 writes the state to `out` for the passes after.
+__device__ __forceinline__ RadixSel rs_after_pick(const RadixSel* in, const uint32_t* hist, int shift, RadixSel* out) {
+  __shared__ uint32_t wtot[kBlock / 64];
+  __shared__ int sel_d;
+  __shared__ long long sel_below;
+  const RadixSel r = *in;
+  if (threadIdx.x == 0) sel_d = -1;
+  const int d = threadIdx.x;
+  const uint32_t v = hist[d];
+  uint32_t total = 0u;
+  const long long before = r.below + (long long)block_scan_excl<kBlock / 64>(v, wtot, total);   // (its barriers order sel_d)
+  if (r.need > 0 && before < r.need && r.need <= before + (long long)v) { sel_d = d; sel_below = before; }
+  __syncthreads();
+  RadixSel o = r;
+  if (sel_d >= 0) {
+    o.prefix |= (unsigned long long)sel_d << shift;
+    o.below = sel_below;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) *out = o;
+  return o;
+}
+
+// The select's state for a counting pass: `in` itself for the first pass
+// (in_hist null), else `in` after the pick of the previous pass's counts.
+__device__ __forceinline__ RadixSel rs_state(const RadixSel* in, const uint32_t* in_hist, int in_shift,
+                                             RadixSel* out) {
+  return in_hist ? rs_after_pick(in, in_hist, in_shift, out) : *in;
+}
+
 template <int SEL>
-__global__ __launch_bounds__(kBlock) void k_rs_hist(ScanCtx c, const RadixSel* rs, int shift, uint32_t* hist) {
+__global__ __launch_bounds__(kBlock) void k_rs_hist(ScanCtx c, const RadixSel* in, const uint32_t* in_hist,
+                                                    int in_shift, RadixSel* out, int shift, uint32_t* hist) {
   __shared__ uint32_t h[kHistCopies][257];
+  const RadixSel rs = rs_state(in, in_hist, in_shift, out);
   for (int i = threadIdx.x; i < kHistCopies * 257; i += blockDim.x) (&h[0][0])[i] = 0u;
   __syncthreads();
   uint32_t* mine = h[threadIdx.x & (kHistCopies - 1)];
-  const unsigned long long pre = rs->prefix;
+  const unsigned long long pre = rs.prefix;
   const int hi = shift + 8;   // digits above this one must match the prefix
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   auto count = [&](int64_t i) {
@@ -1222,19 +1258,9 @@ __global__ __launch_bounds__(kBlock) void k_rs_hist(ScanCtx c, const RadixSel* r
   if (t) atomicAdd(&hist[threadIdx.x], t);
 }
 
-__global__ __launch_bounds__(256) void k_rs_pick(RadixSel* rs, int shift, uint32_t* hist) {
-  __shared__ uint32_t wtot[4];
-  const int d = threadIdx.x;
-  const uint32_t v = hist[d];
-  const long long need = rs->need, below = rs->below;
-  // the scan's barriers also order every thread's reads of rs before the write below
-  uint32_t total = 0u;   // counts add up to at most N < 2^31
-  const long long before = below + (long long)block_scan_excl<4>(v, wtot, total);   // smaller digits
-  if (need > 0 && before < need && need <= before + (long long)v) {
-    rs->prefix |= (unsigned long long)d << shift;
-    rs->below = before;
-  }
-  hist[d] = 0;   // ready for the next pass
+// The pick of a select's last pass: the final state to `out` (may be `in`).
+__global__ __launch_bounds__(256) void k_rs_pick(const RadixSel* in, const uint32_t* hist, int shift, RadixSel* out) {
+  rs_after_pick(in, hist, shift, out);
 }
 
 // The candidates of the hash select (other pixels at the selected distance),
@@ -1292,13 +1318,15 @@ __global__ __launch_bounds__(kBlock) void k_fc_cands(ScanCtx c, int32_t* cand, u
 
 // One hash-select pass over the compacted candidates (as k_rs_hist).
 __global__ __launch_bounds__(kBlock) void k_rs_hist_cands(const int32_t* cand, const unsigned long long* ncand,
-                                                          unsigned long long seed, const RadixSel* rs, int shift,
-                                                          uint32_t* hist) {
+                                                          unsigned long long seed, const RadixSel* in,
+                                                          const uint32_t* in_hist, int in_shift, RadixSel* out,
+                                                          int shift, uint32_t* hist) {
   __shared__ uint32_t h[kHistCopies][257];
+  const RadixSel rs = rs_state(in, in_hist, in_shift, out);
   for (int i = threadIdx.x; i < kHistCopies * 257; i += blockDim.x) (&h[0][0])[i] = 0u;
   __syncthreads();
   uint32_t* mine = h[threadIdx.x & (kHistCopies - 1)];
-  const unsigned long long pre = rs->prefix;
+  const unsigned long long pre = rs.prefix;
   const int hi = shift + 8;
   const int64_t n = (int64_t)*ncand;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -1609,7 +1637,7 @@ Layout layout(int32_t W, int32_t H) {
   o.g = take((size_t)N * 4);
   o.dist = take((size_t)std::max<int64_t>(N, seg_words) * 4);
   o.frank = take((size_t)N * 4);
-  o.rhist = take(256 * 4);
+  o.rhist = take(256 * 4 * kRsPasses * 3);   // one zeroed count array per pass of each of the three selects
   o.dhist = take(kStW * 4);
   o.lut = take(256);
   o.misc = take(kMiscBytes);
@@ -1723,6 +1751,8 @@ int sbs_boundaries(const uint8_t* img, int32_t W, int32_t H, int32_t C, int64_t 
   DropRule* rule = (DropRule*)(misc + 192);
   FracState* fs = (FracState*)(misc + 256);
   unsigned long long* n1 = (unsigned long long*)(misc + 1024);   // kN1Parts partial counts
+  RadixSel* rsv = (RadixSel*)(misc + 704);   // a select's state after each pass's pick (kRsPasses)
+  static_assert(704 + kRsPasses * sizeof(RadixSel) <= 1024, "misc layout");
   int32_t* gcol = (int32_t*)(base + Lo.g);
   int32_t* dist = (int32_t*)(base + Lo.dist);
   int32_t* frank = (int32_t*)(base + Lo.frank);
@@ -1783,7 +1813,6 @@ int sbs_boundaries(const uint8_t* img, int32_t W, int32_t H, int32_t C, int64_t 
   if (frac >= 0.0) {
     const long long want = std::min<long long>((long long)N, std::llround(frac * (double)N));
     const long long n0 = W == 1 ? H : 2LL * H;
-    hipLaunchKernelGGL(k_fill, dim3(1), dim3(kBlock), 0, s, (uint8_t*)rhist, (int64_t)(256 * 4), (uint8_t)0);
     uint8_t* cls = lab2;   // free once the refinement is done
     hipLaunchKernelGGL(k_fc_class, dim3(g), dim3(kBlock), 0, s, c, cls, n1);
     // Component sizes are at most N: with N below 2^24 the top digit of ~size is
@@ -1791,12 +1820,30 @@ int sbs_boundaries(const uint8_t* img, int32_t W, int32_t H, int32_t C, int64_t 
     const bool small = N < (1LL << 24);
     hipLaunchKernelGGL(k_fc_plan, dim3(1), dim3(1), 0, s, fs, n1, want, n0, small ? 0xFF000000ull : 0ull);
     c.fc = fs; c.dist = dist; c.frank = frank; c.seed = (unsigned long long)seed; c.cls = cls;
-    // radix-select histograms: at most 512 blocks (each ends with up to 256 global adds)
+    // radix-select histograms: at most 512 blocks (each ends with up to 256
+    // global adds). Pass p counts into its own zeroed array and starts from
+    // the state after the pick of pass p - 1's counts (rsv[p - 1], written by
+    // its block 0); one pick launch after the last pass sets the final state.
     const int gr = std::min(g, 512);
-    for (int sh = small ? 16 : 24; sh >= 0; sh -= 8) {      // kept pixels: size descending
-      hipLaunchKernelGGL(k_rs_hist<1>, dim3(gr), dim3(kBlock), 0, s, c, &fs->s1, sh, rhist);
-      hipLaunchKernelGGL(k_rs_pick, dim3(1), dim3(256), 0, s, &fs->s1, sh, rhist);
-    }
+    hipLaunchKernelGGL(k_fill, dim3(1), dim3(kBlock), 0, s, (uint8_t*)rhist, (int64_t)(256 * 4 * kRsPasses * 3),
+                       (uint8_t)0);
+    int nsel = 0;
+    auto select = [&](RadixSel* st, int first_shift, int last_shift, auto launch_pass) {
+      uint32_t* const hs = rhist + 256 * kRsPasses * nsel++;   // this select's count arrays
+      int p = 0, prev_shift = 0;
+      for (int sh = first_shift; sh >= last_shift; sh -= 8, ++p) {
+        const RadixSel* in = p <= 1 ? st : &rsv[p - 1];
+        const uint32_t* in_hist = p == 0 ? nullptr : hs + 256 * (p - 1);
+        launch_pass(in, in_hist, prev_shift, &rsv[p], sh, hs + 256 * p);
+        prev_shift = sh;
+      }
+      hipLaunchKernelGGL(k_rs_pick, dim3(1), dim3(256), 0, s, p <= 1 ? (const RadixSel*)st : &rsv[p - 1],
+                         hs + 256 * (p - 1), prev_shift, st);
+    };
+    select(&fs->s1, small ? 16 : 24, 0,   // kept pixels: size descending
+           [&](const RadixSel* in, const uint32_t* ih, int ish, RadixSel* out, int sh, uint32_t* h) {
+             hipLaunchKernelGGL(k_rs_hist<1>, dim3(gr), dim3(kBlock), 0, s, c, in, ih, ish, out, sh, h);
+           });
     hipLaunchKernelGGL(k_scan_count<2>, dim3((unsigned)nb), dim3(kBlock), 0, s, c, bsum);
     hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, bsum, nb, (long long*)nullptr);
     hipLaunchKernelGGL(k_scan_apply<2>, dim3((unsigned)nb), dim3(kBlock), 0, s, c, bsum);
@@ -1821,14 +1868,15 @@ int sbs_boundaries(const uint8_t* img, int32_t W, int32_t H, int32_t C, int64_t 
       hipLaunchKernelGGL(k_fc_dist_pick, dim3(1), dim3(kStBlock), 0, s, fs, dhist, W);
     } else {
       hipLaunchKernelGGL(k_dt_row, dim3(H < 16384 ? H : 16384), dim3(kBlock), 0, s, c, H, gcol, dist);
-      for (int sh = 24; sh >= 0; sh -= 8) {      // other pixels: distance
-        // Distances are below W (the border columns are selected), so digits at
-        // and above a power of two >= W are 0 for every candidate: the pick
-        // would add 0 to the prefix and to the count below, so the pass is skipped.
-        if (sh >= 8 && (int64_t)W <= (1LL << sh)) continue;
-        hipLaunchKernelGGL(k_rs_hist<2>, dim3(gr), dim3(kBlock), 0, s, c, &fs->s2, sh, rhist);
-        hipLaunchKernelGGL(k_rs_pick, dim3(1), dim3(256), 0, s, &fs->s2, sh, rhist);
-      }
+      // Distances are below W (the border columns are selected), so digits at
+      // and above a power of two >= W are 0 for every candidate: the pick
+      // would add 0 to the prefix and to the count below, so those passes are skipped.
+      int top = 24;
+      while (top >= 8 && (int64_t)W <= (1LL << top)) top -= 8;
+      select(&fs->s2, top, 0,   // other pixels: distance
+             [&](const RadixSel* in, const uint32_t* ih, int ish, RadixSel* out, int sh, uint32_t* h) {
+               hipLaunchKernelGGL(k_rs_hist<2>, dim3(gr), dim3(kBlock), 0, s, c, in, ih, ish, out, sh, h);
+             });
     }
     hipLaunchKernelGGL(k_fc_after_dist, dim3(1), dim3(1), 0, s, fs);
     // other pixels at that distance: hash, over their compacted list (in the
@@ -1837,11 +1885,11 @@ int sbs_boundaries(const uint8_t* img, int32_t W, int32_t H, int32_t C, int64_t 
     unsigned long long* ncand = (unsigned long long*)(misc + 640);
     hipLaunchKernelGGL(k_fc_cands, dim3((unsigned)std::min<int64_t>((N + kCandPer - 1) / kCandPer, 8192)),
                        dim3(kBlock), 0, s, c, cand, ncand);
-    for (int sh = 56; sh >= 0; sh -= 8) {
-      hipLaunchKernelGGL(k_rs_hist_cands, dim3(std::min(gr, 64)), dim3(kBlock), 0, s, cand, ncand,
-                         (unsigned long long)seed, &fs->s3, sh, rhist);
-      hipLaunchKernelGGL(k_rs_pick, dim3(1), dim3(256), 0, s, &fs->s3, sh, rhist);
-    }
+    select(&fs->s3, 56, 0,   // the hash
+           [&](const RadixSel* in, const uint32_t* ih, int ish, RadixSel* out, int sh, uint32_t* h) {
+             hipLaunchKernelGGL(k_rs_hist_cands, dim3(std::min(gr, 64)), dim3(kBlock), 0, s, cand, ncand,
+                                (unsigned long long)seed, in, ih, ish, out, sh, h);
+           });
     hipLaunchKernelGGL(k_scan_count<3>, dim3((unsigned)nb), dim3(kBlock), 0, s, c, bsum);
     hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, bsum, nb, (long long*)nullptr);
     hipLaunchKernelGGL(k_scan_apply<3>, dim3((unsigned)nb), dim3(kBlock), 0, s, c, bsum);
