@@ -97,13 +97,31 @@ __global__ __launch_bounds__(kBlock) void k_gray(const uint8_t* __restrict__ img
 
 // RGB rows whose width is a multiple of 4 at word-aligned addresses: four
 // pixels per thread from three aligned words, one word written.
+// Four pixels per thread from three aligned words. The step search starts
+// from a table over Y in 1/4096 buckets: coarse[b] is the last step at or
+// below b/4096, and since consecutive steps lie more than 1/4096 apart (the
+// host checks it before it takes this kernel) a bucket holds at most one
+// step, so one comparison finishes the search (instead of eight dependent
+// LDS reads). Built per block from the steps, for a grid of a few blocks per CU.
+constexpr int kLightBuckets = 4096;
 __global__ __launch_bounds__(kBlock) void k_light4(const uint8_t* __restrict__ img, int32_t W, int32_t H,
                                                    int64_t pitch, uint8_t* __restrict__ L8, LightSteps steps) {
 #pragma clang fp contract(off)
   __shared__ double lin[256];
   __shared__ double t[256];
+  __shared__ uint8_t coarse[kLightBuckets + 1];
   lin[threadIdx.x] = srgb_linear((int)threadIdx.x);
   t[threadIdx.x] = steps.t[threadIdx.x];
+  __syncthreads();
+  {
+    // step k covers buckets ceil(t[k] 4096) .. ceil(t[k + 1] 4096) - 1 (step 0 from bucket 0)
+    const int k = threadIdx.x;
+    auto first_bucket = [&](int j) -> int {
+      return j > 255 ? kLightBuckets + 1 : (int)fmin(ceil(t[j] * (double)kLightBuckets), (double)(kLightBuckets + 1));
+    };
+    const int b0 = k == 0 ? 0 : first_bucket(k), b1 = first_bucket(k + 1);
+    for (int b = b0; b < b1; ++b) coarse[b] = (uint8_t)k;
+  }
   __syncthreads();
   const int64_t Q = (int64_t)W * H / 4;   // groups of four pixels (W % 4 == 0)
   for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < Q; g += (int64_t)gridDim.x * blockDim.x) {
@@ -119,10 +137,8 @@ __global__ __launch_bounds__(kBlock) void k_light4(const uint8_t* __restrict__ i
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const double Y = 0.2126 * lin[px[k][0]] + 0.7152 * lin[px[k][1]] + 0.0722 * lin[px[k][2]];
-      int v = 0;
-#pragma unroll
-      for (int st = 128; st; st >>= 1)
-        if (Y >= t[v + st]) v += st;
+      int v = coarse[min((int)(Y * (double)kLightBuckets), kLightBuckets)];   // Y >= 0
+      if (v < 255 && Y >= t[v + 1]) ++v;
       out |= (uint32_t)v << (8 * k);
     }
     *(uint32_t*)(L8 + i) = out;
@@ -599,19 +615,12 @@ __device__ __forceinline__ void uf_union(int32_t* parent, int32_t a, int32_t b) 
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_cc_init(const uint8_t* __restrict__ B, int64_t N, int32_t* parent,
-                                                    int32_t* size) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
-    parent[i] = B[i] ? (int32_t)i : -1;
-    size[i] = 0;
-  }
-}
-
 // Two-level merge. k_cc_tile: one block per tile of kTileW x kTileH pixels
 // runs the same union-find on the tile's pixels in LDS (links from larger to
 // smaller local raster index, which is the global raster order within the
-// tile), then writes for every boundary pixel the global index of its tile
-// root. k_cc_edges then unions, through the global forest, only the
+// tile), then writes for every pixel of the tile the global index of its
+// tile root (-1 off the boundary map) and the tile roots' local sizes (0
+// elsewhere), which initialises the whole forest. k_cc_edges then unions, through the global forest, only the
 // neighbour pairs that cross a tile edge. The forest's roots stay the
 // smallest raster index of their component.
 constexpr int kTileW = 64, kTileH = 16;
@@ -671,21 +680,27 @@ __global__ __launch_bounds__(kBlock) void k_cc_tile(const uint8_t* __restrict__ 
     }
   }
   __syncthreads();
+  // every pixel of the tile gets its parent (-1 off the boundary map), so no
+  // separate pass initialises the forest
 #pragma unroll
   for (int j = 0; j < kTileH / kRowsPerPass; ++j) {
-    if (!on[j]) continue;
     const int ly = (int)(threadIdx.x / kTileW) + kRowsPerPass * j;
-    const int32_t r = lds_find(lp, ly * kTileW + lx);
-    parent[(int64_t)(y0 + ly) * W + x0 + lx] = (y0 + r / kTileW) * W + x0 + (r % kTileW);
-    atomicAdd(&lsz[r], 1);
+    if (x0 + lx >= W || y0 + ly >= H) continue;
+    int32_t gp = -1;
+    if (on[j]) {
+      const int32_t r = lds_find(lp, ly * kTileW + lx);
+      gp = (y0 + r / kTileW) * W + x0 + (r % kTileW);
+      atomicAdd(&lsz[r], 1);
+    }
+    parent[(int64_t)(y0 + ly) * W + x0 + lx] = gp;
   }
   __syncthreads();
-  // each tile root's local component size, at the root (the rest stay 0)
+  // each tile root's local component size, at the root (0 everywhere else)
 #pragma unroll
   for (int j = 0; j < kTileH / kRowsPerPass; ++j) {
     const int ly = (int)(threadIdx.x / kTileW) + kRowsPerPass * j;
     const int l = ly * kTileW + lx;
-    if (on[j] && lsz[l] > 0) size[(int64_t)(y0 + ly) * W + x0 + lx] = lsz[l];
+    if (x0 + lx < W && y0 + ly < H) size[(int64_t)(y0 + ly) * W + x0 + lx] = on[j] ? lsz[l] : 0;
   }
 }
 
@@ -1683,10 +1698,18 @@ const LightSteps& light_steps() {
 
 void launch_light(const uint8_t* img, int32_t W, int32_t H, int32_t C, int64_t pitch, uint8_t* L8, int grid,
                   hipStream_t s) {
+  // the bucket table of k_light4 needs consecutive steps more than a bucket apart
+  static const bool coarse_ok = [] {
+    const LightSteps& st = light_steps();
+    for (int k = 1; k < 255; ++k)
+      if (std::isfinite(st.t[k + 1]) && !(st.t[k + 1] - st.t[k] > 1.0 / kLightBuckets)) return false;
+    return true;
+  }();
   if (C == 1)
     hipLaunchKernelGGL(k_gray, dim3(grid), dim3(kBlock), 0, s, img, W, H, pitch, L8);
-  else if ((W & 3) == 0 && (pitch & 3) == 0 && ((uintptr_t)img & 3) == 0 && ((uintptr_t)L8 & 3) == 0)
-    hipLaunchKernelGGL(k_light4, dim3(grid), dim3(kBlock), 0, s, img, W, H, pitch, L8, light_steps());
+  else if (coarse_ok && (W & 3) == 0 && (pitch & 3) == 0 && ((uintptr_t)img & 3) == 0 && ((uintptr_t)L8 & 3) == 0)
+    hipLaunchKernelGGL(k_light4, dim3(std::min(grid, 1024)), dim3(kBlock), 0, s, img, W, H, pitch, L8,
+                       light_steps());
   else
     hipLaunchKernelGGL(k_light, dim3(grid), dim3(kBlock), 0, s, img, W, H, C, pitch, L8, light_steps());
 }
@@ -1763,11 +1786,14 @@ int sbs_boundaries(const uint8_t* img, int32_t W, int32_t H, int32_t C, int64_t 
   // Clear the small counters with kernels (no memset nodes if the caller captures the stream).
   hipLaunchKernelGGL(k_fill, dim3(1), dim3(kBlock), 0, s, (uint8_t*)hist, (int64_t)(256 * 8), (uint8_t)0);
   hipLaunchKernelGGL(k_fill, dim3(1), dim3(kBlock), 0, s, (uint8_t*)misc, (int64_t)kMiscBytes, (uint8_t)0);
-  launch_light(img, W, H, C, pitch, L8, g, s);
+  // grey rows without gaps are the lightness image itself (no copy)
+  const uint8_t* lum = L8;
+  if (C == 1 && pitch == W) lum = img;
+  else launch_light(img, W, H, C, pitch, L8, g, s);
   // at most 512 blocks: each ends with up to 256 global adds
-  hipLaunchKernelGGL(k_hist, dim3(std::min(grid_for((N + 15) / 16), 512)), dim3(kBlock), 0, s, L8, N, hist);
+  hipLaunchKernelGGL(k_hist, dim3(std::min(grid_for((N + 15) / 16), 512)), dim3(kBlock), 0, s, lum, N, hist);
   hipLaunchKernelGGL(k_kmeans, dim3(1), dim3(256), 0, s, hist, K, lut, passes);
-  hipLaunchKernelGGL(k_label, dim3(g), dim3(kBlock), 0, s, L8, N, lut, lab);
+  hipLaunchKernelGGL(k_label, dim3(g), dim3(kBlock), 0, s, lum, N, lut, lab);
   const uint8_t* labels = lab;
   if (mode == 0) {
     // open, close and boundary in one pass; the closed labels go straight to
@@ -1786,7 +1812,6 @@ int sbs_boundaries(const uint8_t* img, int32_t W, int32_t H, int32_t C, int64_t 
     const hipError_t ce = hipMemcpyAsync(out_labels, labels, (size_t)N, hipMemcpyDeviceToDevice, s);
     if (ce != hipSuccess) return fail(SBS_ERR_HIP, "boundaries: %s", hipGetErrorString(ce));
   }
-  hipLaunchKernelGGL(k_cc_init, dim3(g), dim3(kBlock), 0, s, B, N, parent, size);
   const dim3 gt((W + kTileW - 1) / kTileW, (H + kTileH - 1) / kTileH);
   hipLaunchKernelGGL(k_cc_tile, gt, dim3(kBlock), 0, s, B, W, H, parent, size);
   hipLaunchKernelGGL(k_cc_edges, gt, dim3(128), 0, s, B, W, H, parent);
