@@ -1027,21 +1027,34 @@ __global__ __launch_bounds__(kBlock) void k_scan_count(ScanCtx c, uint32_t* bsum
   if (threadIdx.x == 0) bsum[blockIdx.x] = s;
 }
 
-// exclusive scan of nb block counts in place (one block of 1024 threads; each
-// thread sums a contiguous run of counts, the runs are scanned across the
-// block, then each thread writes its run's prefixes)
+// exclusive scan of nb block counts in place (one block of 1024 threads):
+// the counts are read into LDS with coalesced loads (up to kTopLds of them;
+// beyond that straight from global memory), each thread sums a contiguous
+// run of them, the runs are scanned across the block, then each thread
+// writes its run's prefixes back to LDS and the block stores them coalesced.
+constexpr int kTopLds = 12288;   // 48 KB: 4096x3072 pixels at 1024 per count
 __global__ __launch_bounds__(1024) void k_scan_top(uint32_t* bsum, int64_t nb, long long* total) {
   __shared__ uint32_t wtot[16];
+  __shared__ uint32_t v[kTopLds];
+  const bool in_lds = nb <= kTopLds;
+  if (in_lds)
+    for (int64_t b = threadIdx.x; b < nb; b += 1024) v[b] = bsum[b];
+  __syncthreads();
+  uint32_t* src = in_lds ? v : bsum;
   const int64_t per = (nb + 1023) / 1024;
   const int64_t b0 = (int64_t)threadIdx.x * per, b1 = min(b0 + per, nb);
   uint32_t run = 0;
-  for (int64_t b = b0; b < b1; ++b) run += bsum[b];
+  for (int64_t b = b0; b < b1; ++b) run += src[b];
   uint32_t all;
-  uint32_t pos = block_scan_excl<16>(run, wtot, all);
+  uint32_t pos = block_scan_excl<16>(run, wtot, all);   // (its barriers order the reads above before the writes below)
   for (int64_t b = b0; b < b1; ++b) {
-    const uint32_t v = bsum[b];
-    bsum[b] = pos;
-    pos += v;
+    const uint32_t c = src[b];
+    src[b] = pos;
+    pos += c;
+  }
+  if (in_lds) {
+    __syncthreads();
+    for (int64_t b = threadIdx.x; b < nb; b += 1024) bsum[b] = v[b];
   }
   if (threadIdx.x == 0 && total) *total = (long long)all;
 }
