@@ -623,7 +623,8 @@ __device__ __forceinline__ void uf_union(int32_t* parent, int32_t a, int32_t b) 
 // elsewhere), which initialises the whole forest. k_cc_edges then unions, through the global forest, only the
 // neighbour pairs that cross a tile edge. The forest's roots stay the
 // smallest raster index of their component.
-constexpr int kTileW = 64, kTileH = 16;
+constexpr int kTileW = 64, kTileH = 32;
+static_assert(kTileW + 2 * (kTileH - 1) <= 128, "k_cc_edges: one thread per tile edge pixel");
 
 __device__ __forceinline__ int32_t lds_find(int32_t* lp, int32_t a) {
   for (;;) {
