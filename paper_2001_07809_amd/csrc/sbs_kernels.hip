@@ -1186,9 +1186,14 @@ hipError_t launch_put_desc(FrameDev* table, const FrameDev* host, int nframes, h
   return hipGetLastError();
 }
 
+// Blocks per frame of the list kernels (grid-stride over the list): 64 fill
+// the chip when a launch covers many frames; fewer frames per launch take
+// more each, so that a single frame's list is not walked by 64 blocks alone.
+int list_blocks(int nf) { return nf >= 32 ? 64 : 2048 / nf; }
+
 hipError_t launch_prologue(const FrameDev* table, int f0, int nf, int max_rows, WsHeader* hdr,
                            hipStream_t s) {
-  hipLaunchKernelGGL(k_check, dim3(64, nf), dim3(256), 0, s, table, f0, hdr);
+  hipLaunchKernelGGL(k_check, dim3(list_blocks(nf), nf), dim3(256), 0, s, table, f0, hdr);
   int gx = max_rows < 2048 ? max_rows : 2048;
   if (gx < 1) gx = 1;
   hipLaunchKernelGGL(k_prep, dim3(gx, nf), dim3(256), 0, s, table, f0);
@@ -1197,7 +1202,7 @@ hipError_t launch_prologue(const FrameDev* table, int f0, int nf, int max_rows, 
 }
 
 hipError_t launch_finalize(const FrameDev* table, int f0, int nf, hipStream_t s) {
-  hipLaunchKernelGGL(k_finalize, dim3(64, nf), dim3(256), 0, s, table, f0);
+  hipLaunchKernelGGL(k_finalize, dim3(list_blocks(nf), nf), dim3(256), 0, s, table, f0);
   return hipGetLastError();
 }
 
