@@ -188,36 +188,99 @@ __global__ __launch_bounds__(256) void k_rc_colseg(const int16_t* f, int32_t W, 
 
 // In place: seg_last[sg] becomes the nearest determined value above segment
 // sg (the last one of the segments before it), seg_first[sg] the nearest
-// below it (the first one of the segments after it); -1 where none. The
-// records are read kScanBatch at a time before any of them is written, so a
-// thread has that many loads in flight instead of one round trip per segment.
+// below it (the first one of the segments after it); -1 where none. Three
+// launches over chunks of kScanBatch segments: k_rc_chunks sums up each
+// chunk (its last and first determined value; one thread per column and
+// chunk), k_rc_colscan turns the summaries into the same nearest values per
+// chunk (one thread per column, a pass down and one up, kScanBatch records
+// in flight), and k_rc_segscan rewrites each chunk's records from its
+// chunk's carries (one thread per column and chunk). A column's sequential
+// work is its chunk count, a sixteenth of its segment count.
 constexpr int kScanBatch = 16;
-__global__ __launch_bounds__(256) void k_rc_segscan(int32_t W, int32_t nseg, int16_t* seg_first, int16_t* seg_last) {
+__global__ __launch_bounds__(256) void k_rc_chunks(int32_t W, int32_t nseg, const int16_t* seg_first,
+                                                   const int16_t* seg_last, int16_t* ch_first, int16_t* ch_last) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;
+  if (x >= W) return;
+  const int s0 = c * kScanBatch;
+  int16_t vl[kScanBatch], vf[kScanBatch];
+#pragma unroll
+  for (int k = 0; k < kScanBatch; ++k) {
+    const bool in = s0 + k < nseg;
+    vl[k] = in ? seg_last[(int64_t)(s0 + k) * W + x] : (int16_t)-1;
+    vf[k] = in ? seg_first[(int64_t)(s0 + k) * W + x] : (int16_t)-1;
+  }
+  int16_t last = -1, first = -1;
+#pragma unroll
+  for (int k = 0; k < kScanBatch; ++k) {
+    if (vl[k] >= 0) last = vl[k];
+    if (first < 0 && vf[k] >= 0) first = vf[k];
+  }
+  ch_last[(int64_t)c * W + x] = last;
+  ch_first[(int64_t)c * W + x] = first;
+}
+
+// In place over n records of each column: last[i] becomes the last
+// non-negative value of records 0 .. i - 1, first[i] the first of records
+// i + 1 .. n - 1 (-1 where none). Records are read kScanBatch at a time
+// before any of them is written.
+__global__ __launch_bounds__(256) void k_rc_colscan(int32_t W, int32_t n, int16_t* first, int16_t* last) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   if (x >= W) return;
   int16_t carry = -1;
-  for (int s0 = 0; s0 < nseg; s0 += kScanBatch) {
+  for (int s0 = 0; s0 < n; s0 += kScanBatch) {
     int16_t v[kScanBatch];
 #pragma unroll
-    for (int k = 0; k < kScanBatch; ++k) v[k] = s0 + k < nseg ? seg_last[(int64_t)(s0 + k) * W + x] : (int16_t)-1;
+    for (int k = 0; k < kScanBatch; ++k) v[k] = s0 + k < n ? last[(int64_t)(s0 + k) * W + x] : (int16_t)-1;
 #pragma unroll
     for (int k = 0; k < kScanBatch; ++k) {
-      if (s0 + k >= nseg) break;
-      seg_last[(int64_t)(s0 + k) * W + x] = carry;
+      if (s0 + k >= n) break;
+      last[(int64_t)(s0 + k) * W + x] = carry;
       if (v[k] >= 0) carry = v[k];
     }
   }
   carry = -1;
-  for (int s1 = nseg - 1; s1 >= 0; s1 -= kScanBatch) {   // segments s1, s1 - 1, ...
+  for (int s1 = n - 1; s1 >= 0; s1 -= kScanBatch) {   // records s1, s1 - 1, ...
     int16_t v[kScanBatch];
 #pragma unroll
-    for (int k = 0; k < kScanBatch; ++k) v[k] = s1 - k >= 0 ? seg_first[(int64_t)(s1 - k) * W + x] : (int16_t)-1;
+    for (int k = 0; k < kScanBatch; ++k) v[k] = s1 - k >= 0 ? first[(int64_t)(s1 - k) * W + x] : (int16_t)-1;
 #pragma unroll
     for (int k = 0; k < kScanBatch; ++k) {
       if (s1 - k < 0) break;
-      seg_first[(int64_t)(s1 - k) * W + x] = carry;
+      first[(int64_t)(s1 - k) * W + x] = carry;
       if (v[k] >= 0) carry = v[k];
     }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_rc_segscan(int32_t W, int32_t nseg, int16_t* seg_first, int16_t* seg_last,
+                                                    const int16_t* ch_first, const int16_t* ch_last) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;
+  if (x >= W) return;
+  const int s0 = c * kScanBatch;
+  int16_t vl[kScanBatch], vf[kScanBatch];
+#pragma unroll
+  for (int k = 0; k < kScanBatch; ++k) {
+    const bool in = s0 + k < nseg;
+    vl[k] = in ? seg_last[(int64_t)(s0 + k) * W + x] : (int16_t)-1;
+    vf[k] = in ? seg_first[(int64_t)(s0 + k) * W + x] : (int16_t)-1;
+  }
+  // the last determined value of the chunks before this one, the first of
+  // those after it (one chunk: none)
+  int16_t above = gridDim.y > 1 ? ch_last[(int64_t)c * W + x] : (int16_t)-1;
+  int16_t below = gridDim.y > 1 ? ch_first[(int64_t)c * W + x] : (int16_t)-1;
+#pragma unroll
+  for (int k = 0; k < kScanBatch; ++k) {
+    if (s0 + k >= nseg) break;
+    seg_last[(int64_t)(s0 + k) * W + x] = above;
+    if (vl[k] >= 0) above = vl[k];
+  }
+#pragma unroll
+  for (int k = kScanBatch - 1; k >= 0; --k) {
+    if (s0 + k >= nseg) continue;
+    seg_first[(int64_t)(s0 + k) * W + x] = below;
+    if (vf[k] >= 0) below = vf[k];
   }
 }
 
@@ -976,15 +1039,27 @@ int sbs_reconstruct(const uint32_t* idx, const uint8_t* disp, int64_t n, int32_t
   hipLaunchKernelGGL(k_rc_clear, dim3(1024), dim3(256), 0, s, slot, N);
   if (n > 0) hipLaunchKernelGGL(k_rc_scatter, dim3(256), dim3(256), 0, s, idx, n, N, slot);
   hipLaunchKernelGGL(k_rc_fill, dim3(H < 65536 ? H : 65536), dim3(kRowThreads), 0, s, slot, disp, W, H, f);
-  // The column pass's segment records reuse the slot array (no longer read
-  // after k_rc_fill): 2 x nseg x W int16 <= 4 x W x H bytes.
+  // The column pass's segment records and their chunk summaries reuse the
+  // slot array (no longer read after k_rc_fill): 2 x (nseg + nch) x W int16,
+  // within its 4 x W x H bytes (summaries only when nch > 1, i.e. H > 256:
+  // then nseg + nch <= H / 16 + H / 256 + 2 < H).
   const int seglen = std::max(kColSeg, (H + 65534) / 65535);
   const int nseg = (H + seglen - 1) / seglen;
   int16_t* seg_first = (int16_t*)slot;
   int16_t* seg_last = seg_first + (int64_t)nseg * W;
   const dim3 cg((W + 255) / 256, nseg);
   hipLaunchKernelGGL(k_rc_colseg, cg, dim3(256), 0, s, f, W, H, seglen, seg_first, seg_last);
-  hipLaunchKernelGGL(k_rc_segscan, dim3((W + 255) / 256), dim3(256), 0, s, W, nseg, seg_first, seg_last);
+  // chunk summaries after the segment records, still inside the slot array
+  const int nch = (nseg + kScanBatch - 1) / kScanBatch;
+  int16_t* ch_first = seg_last + (int64_t)nseg * W;
+  int16_t* ch_last = ch_first + (int64_t)nch * W;
+  const dim3 chg((W + 255) / 256, nch);
+  // (one chunk: no carries to take, and no room needed for summaries)
+  if (nch > 1) {
+    hipLaunchKernelGGL(k_rc_chunks, chg, dim3(256), 0, s, W, nseg, seg_first, seg_last, ch_first, ch_last);
+    hipLaunchKernelGGL(k_rc_colscan, dim3((W + 255) / 256), dim3(256), 0, s, W, nch, ch_first, ch_last);
+  }
+  hipLaunchKernelGGL(k_rc_segscan, chg, dim3(256), 0, s, W, nseg, seg_first, seg_last, ch_first, ch_last);
   hipLaunchKernelGGL(k_rc_peek, cg, dim3(256), 0, s, f, W, H, threshold, seglen, seg_last, seg_first, up, out_map);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(SBS_ERR_HIP, "reconstruct: %s", hipGetErrorString(e));
