@@ -28,10 +28,21 @@ __global__ __launch_bounds__(256) void k_rc_clear(int32_t* slot, int64_t N) {
     slot[i] = -1;
 }
 
+// In two passes without an atomic per entry: every entry stores its
+// position (an entry followed by one of the same index leaves it to that
+// one), so a pixel holds one of its positions; then every entry whose
+// position is above what its pixel holds raises it with an atomic maximum,
+// which leaves the largest (only repeats that are not adjacent need one).
 __global__ __launch_bounds__(256) void k_rc_scatter(const uint32_t* idx, int64_t n, int64_t N, int32_t* slot) {
   for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
     const uint32_t p = idx[k];
-    if ((int64_t)p < N) atomicMax(&slot[p], (int32_t)k);
+    if ((int64_t)p < N && (k + 1 == n || idx[k + 1] != p)) slot[p] = (int32_t)k;
+  }
+}
+__global__ __launch_bounds__(256) void k_rc_scatter_max(const uint32_t* idx, int64_t n, int64_t N, int32_t* slot) {
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t p = idx[k];
+    if ((int64_t)p < N && slot[p] < (int32_t)k) atomicMax(&slot[p], (int32_t)k);
   }
 }
 
@@ -1037,7 +1048,11 @@ int sbs_reconstruct(const uint32_t* idx, const uint8_t* disp, int64_t n, int32_t
   int16_t* f = (int16_t*)(base + align256(N * 4));
   int16_t* up = (int16_t*)(base + align256(N * 4) + align256(N * 2));
   hipLaunchKernelGGL(k_rc_clear, dim3(1024), dim3(256), 0, s, slot, N);
-  if (n > 0) hipLaunchKernelGGL(k_rc_scatter, dim3(256), dim3(256), 0, s, idx, n, N, slot);
+  if (n > 0) {
+    const unsigned sg = (unsigned)std::min<int64_t>((n + 1023) / 1024, 2048);
+    hipLaunchKernelGGL(k_rc_scatter, dim3(sg), dim3(256), 0, s, idx, n, N, slot);
+    hipLaunchKernelGGL(k_rc_scatter_max, dim3(sg), dim3(256), 0, s, idx, n, N, slot);
+  }
   hipLaunchKernelGGL(k_rc_fill, dim3(H < 65536 ? H : 65536), dim3(kRowThreads), 0, s, slot, disp, W, H, f);
   // The column pass's segment records and their chunk summaries reuse the
   // slot array (no longer read after k_rc_fill): 2 x (nseg + nch) x W int16,
