@@ -186,11 +186,24 @@ __global__ __launch_bounds__(256) void k_rc_colseg(const int16_t* f, int32_t W, 
   if (x >= W) return;
   const int y0 = sg * seglen, y1 = min(y0 + seglen, H);
   int16_t first = -1, last = -1;
-  for (int y = y0; y < y1; ++y) {
-    const int16_t v = f[(int64_t)y * W + x];
-    if (v >= 0) {
-      if (first < 0) first = v;
-      last = v;
+  if (seglen == kColSeg) {
+    // the segment's values read at once
+    int16_t v[kColSeg];
+#pragma unroll
+    for (int k = 0; k < kColSeg; ++k) v[k] = y0 + k < y1 ? f[(int64_t)(y0 + k) * W + x] : (int16_t)-1;
+#pragma unroll
+    for (int k = 0; k < kColSeg; ++k)
+      if (v[k] >= 0) {
+        if (first < 0) first = v[k];
+        last = v[k];
+      }
+  } else {
+    for (int y = y0; y < y1; ++y) {
+      const int16_t v = f[(int64_t)y * W + x];
+      if (v >= 0) {
+        if (first < 0) first = v;
+        last = v;
+      }
     }
   }
   seg_first[(int64_t)sg * W + x] = first;
