@@ -171,10 +171,11 @@ __global__ __launch_bounds__(kRowThreads) void k_rc_fill(const int32_t* slot, co
 // short walks fill the chip better than fewer long ones; more for images
 // over 1M rows so the segments fit the grid), one thread per
 // (column, segment): k_rc_colseg records each segment's topmost and
-// bottommost determined value, k_rc_segscan turns those records into the
-// nearest determined value above and below each segment (one pass down and
-// one up each column, so a column with few determined pixels costs O(nseg),
-// not O(nseg^2)), and k_rc_peek resolves the segment's rows in two passes
+// bottommost determined value, k_rc_chunks / k_rc_colscan / k_rc_segscan
+// turn those records into the nearest determined value above and below each
+// segment (scans down and up each column over chunk summaries, so a column
+// with few determined pixels costs O(nseg), not O(nseg^2)), and k_rc_peek
+// resolves the segment's rows in two passes
 // (threads of a block cover adjacent columns, so every row access is
 // coalesced).
 constexpr int kColSeg = 16;
