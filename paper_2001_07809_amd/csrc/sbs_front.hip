@@ -771,8 +771,7 @@ struct DropRule {
 };
 
 // cnt[s] += 1 for every component of size s; total = all boundary pixels.
-__global__ __launch_bounds__(kBlock) void k_drop_count(const int32_t* __restrict__ parent,
-                                                       const int32_t* __restrict__ size, int64_t N,
+__global__ __launch_bounds__(kBlock) void k_drop_count(const int32_t* __restrict__ size, int64_t N,
                                                        unsigned long long* total, int32_t* cnt) {
   constexpr int kSmall = 1024;   // sizes below this are counted per block in LDS first
   __shared__ unsigned long long part;
@@ -781,27 +780,27 @@ __global__ __launch_bounds__(kBlock) void k_drop_count(const int32_t* __restrict
   if (threadIdx.x == 0) part = 0;
   __syncthreads();
   unsigned long long mine = 0;
-  auto count_root = [&](int64_t i) {
-    const int32_t s = size[i];
+  // After k_cc_flatten a pixel's size is non-zero exactly at the roots
+  // (tile roots that are not roots handed their counts on and hold 0).
+  auto count_root = [&](int32_t s) {
+    if (s <= 0) return;
     mine += (unsigned long long)s;
     if (s < kSmall) atomicAdd(&small[s], 1);
     else atomicAdd(&cnt[s], 1);
   };
-  // four pixels per thread and step (one 16-byte load of parents: the grid
-  // is small, so each thread needs several loads in flight), then the tail
+  // four pixels per thread and step (one 16-byte load of sizes: the grid is
+  // small, so each thread needs several loads in flight), then the tail
   const int64_t nq = N >> 2;
-  const int4* pq = (const int4*)parent;   // 16-byte aligned: in the 256-byte aligned workspace
+  const int4* sq = (const int4*)size;   // 16-byte aligned: in the 256-byte aligned workspace
   for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nq; q += (int64_t)gridDim.x * blockDim.x) {
-    const int4 p = pq[q];
-    const int64_t i = q << 2;
-    if (p.x == (int32_t)i) count_root(i);   // roots only
-    if (p.y == (int32_t)(i + 1)) count_root(i + 1);
-    if (p.z == (int32_t)(i + 2)) count_root(i + 2);
-    if (p.w == (int32_t)(i + 3)) count_root(i + 3);
+    const int4 v = sq[q];
+    count_root(v.x);
+    count_root(v.y);
+    count_root(v.z);
+    count_root(v.w);
   }
   if (blockIdx.x == 0)
-    for (int64_t i = (nq << 2) + threadIdx.x; i < N; i += blockDim.x)
-      if (parent[i] == (int32_t)i) count_root(i);
+    for (int64_t i = (nq << 2) + threadIdx.x; i < N; i += blockDim.x) count_root(size[i]);
   // one LDS add per wavefront (adds to one word from every lane serialise)
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) mine += __shfl_xor(mine, off, 64);
@@ -1841,7 +1840,7 @@ int sbs_boundaries(const uint8_t* img, int32_t W, int32_t H, int32_t C, int64_t 
     hipLaunchKernelGGL(k_fill, dim3(g), dim3(kBlock), 0, s, (uint8_t*)cnt, (int64_t)(N + 1) * 4, (uint8_t)0);
     // at most 512 blocks: each block's closing adds (its total and its small
     // sizes' counts) go to the same few global words, so fewer blocks wait less
-    hipLaunchKernelGGL(k_drop_count, dim3(std::min(g, 512)), dim3(kBlock), 0, s, parent, size, N, total, cnt);
+    hipLaunchKernelGGL(k_drop_count, dim3(std::min(g, 512)), dim3(kBlock), 0, s, size, N, total, cnt);
     hipLaunchKernelGGL(k_drop_find, dim3(1), dim3(1024), 0, s, cnt, total, 0.04, rule);
     c.rule = rule;
     // rank of each root of size s* among those roots, in raster order

@@ -195,3 +195,22 @@ def test_blur_tiles_in_focus_and_aligned_rows(mods, C, sigma):
     got = sbs.selective_blur(torch.from_numpy(img).cuda(), torch.from_numpy(depth).cuda(), ranges, sigma)
     torch.cuda.synchronize()
     np.testing.assert_allclose(got.cpu().numpy(), exp, atol=1e-3, rtol=0)
+
+
+@pytest.mark.parametrize("sigma", [2.0, 4.6])
+def test_blur_no_ranges_and_all_in_focus(mods, sigma):
+    """No range of interest (every pixel blurred), several ranges at once,
+    and one range that covers every depth (every tile copied through), on
+    the matrix-core path (sigma 2) and the fp32 tile path (sigma 4.6)."""
+    torch, sbs = mods
+    rng = np.random.default_rng(29)
+    H, W = 100, 333
+    img = rng.integers(0, 256, (H, W, 3), dtype=np.uint8)
+    depth = rng.integers(0, 64, (H, W), dtype=np.uint8)
+    for ranges in ([], [(0, 3), (10, 12), (20, 20), (40, 63)], [(0, 255)]):
+        exp = oracle.blur(img, depth, ranges, sigma)
+        got = sbs.selective_blur(torch.from_numpy(img).cuda(), torch.from_numpy(depth).cuda(), ranges, sigma)
+        torch.cuda.synchronize()
+        np.testing.assert_allclose(got.cpu().numpy(), exp, atol=1e-3, rtol=0, err_msg=f"ranges {ranges}")
+        if ranges == [(0, 255)]:
+            assert np.array_equal(got.cpu().numpy(), img.astype(np.float32))
