@@ -624,6 +624,7 @@ __device__ __forceinline__ void uf_union(int32_t* parent, int32_t a, int32_t b) 
 // neighbour pairs that cross a tile edge. The forest's roots stay the
 // smallest raster index of their component.
 constexpr int kTileW = 64, kTileH = 32;
+static_assert(kTileW == 64, "k_cc_tile: one wavefront per tile row");
 static_assert(kTileW + 2 * (kTileH - 1) <= 128, "k_cc_edges: one thread per tile edge pixel");
 
 __device__ __forceinline__ int32_t lds_find(int32_t* lp, int32_t a) {
@@ -662,7 +663,14 @@ __global__ __launch_bounds__(kBlock) void k_cc_tile(const uint8_t* __restrict__ 
     const int ly = (int)(threadIdx.x / kTileW) + kRowsPerPass * j;
     const int x = x0 + lx, y = y0 + ly;
     on[j] = x < W && y < H && B[(int64_t)y * W + x] != 0;
-    lp[ly * kTileW + lx] = on[j] ? ly * kTileW + lx : -1;
+    // a wavefront holds one tile row (kTileW == 64): each pixel links
+    // straight to the first pixel of its horizontal run, so left neighbours
+    // need no union below
+    const uint64_t row = __builtin_amdgcn_ballot_w64(on[j]);
+    const uint64_t upto = lx == 63 ? ~0ull : ((2ull << lx) - 1ull);   // bits 0 .. lx
+    const uint64_t gaps = ~row & upto;
+    const int start = gaps ? 64 - __builtin_clzll(gaps) : 0;   // just past the last gap at or before lx
+    lp[ly * kTileW + lx] = on[j] ? ly * kTileW + start : -1;
     lsz[ly * kTileW + lx] = 0;
   }
   __syncthreads();
@@ -671,8 +679,8 @@ __global__ __launch_bounds__(kBlock) void k_cc_tile(const uint8_t* __restrict__ 
     if (!on[j]) continue;
     const int ly = (int)(threadIdx.x / kTileW) + kRowsPerPass * j;
     const int l = ly * kTileW + lx;
-    // the tile's neighbours before this pixel in raster order (8-connectivity)
-    if (lx > 0 && lp[l - 1] >= 0) lds_union(lp, l, l - 1);
+    // the tile's neighbours before this pixel in raster order (8-connectivity;
+    // the left one is in its run already)
     if (ly > 0) {
       const int u = l - kTileW;
       if (lx > 0 && lp[u - 1] >= 0) lds_union(lp, l, u - 1);
