@@ -657,7 +657,7 @@ __global__ __launch_bounds__(kBlock) void k_cc_tile(const uint8_t* __restrict__ 
   const int x0 = blockIdx.x * kTileW, y0 = blockIdx.y * kTileH;
   const int lx = threadIdx.x & (kTileW - 1);
   constexpr int kRowsPerPass = kBlock / kTileW;
-  bool on[kTileH / kRowsPerPass];
+  bool on[kTileH / kRowsPerPass], first[kTileH / kRowsPerPass];
 #pragma unroll
   for (int j = 0; j < kTileH / kRowsPerPass; ++j) {
     const int ly = (int)(threadIdx.x / kTileW) + kRowsPerPass * j;
@@ -670,6 +670,7 @@ __global__ __launch_bounds__(kBlock) void k_cc_tile(const uint8_t* __restrict__ 
     const uint64_t upto = lx == 63 ? ~0ull : ((2ull << lx) - 1ull);   // bits 0 .. lx
     const uint64_t gaps = ~row & upto;
     const int start = gaps ? 64 - __builtin_clzll(gaps) : 0;   // just past the last gap at or before lx
+    first[j] = start == lx;
     lp[ly * kTileW + lx] = on[j] ? ly * kTileW + start : -1;
     lsz[ly * kTileW + lx] = 0;
   }
@@ -680,12 +681,19 @@ __global__ __launch_bounds__(kBlock) void k_cc_tile(const uint8_t* __restrict__ 
     const int ly = (int)(threadIdx.x / kTileW) + kRowsPerPass * j;
     const int l = ly * kTileW + lx;
     // the tile's neighbours before this pixel in raster order (8-connectivity;
-    // the left one is in its run already)
+    // the left one is in its run already). Above: one union per horizontal
+    // run of the row above that touches the pixel and not the pixel before
+    // it in its own run (those are joined through that pixel already), so
+    // a run's first pixel takes the first pixel of each run among its three
+    // upper neighbours, every later pixel only a run starting up-right.
     if (ly > 0) {
       const int u = l - kTileW;
-      if (lx > 0 && lp[u - 1] >= 0) lds_union(lp, l, u - 1);
-      if (lp[u] >= 0) lds_union(lp, l, u);
-      if (lx + 1 < kTileW && lp[u + 1] >= 0) lds_union(lp, l, u + 1);
+      const bool ul = lx > 0 && lp[u - 1] >= 0, uc = lp[u] >= 0, ur = lx + 1 < kTileW && lp[u + 1] >= 0;
+      if (first[j]) {
+        if (ul) lds_union(lp, l, u - 1);
+        if (uc && !ul) lds_union(lp, l, u);
+      }
+      if (ur && !uc) lds_union(lp, l, u + 1);
     }
   }
   __syncthreads();
