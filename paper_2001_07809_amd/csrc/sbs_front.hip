@@ -723,26 +723,44 @@ __global__ __launch_bounds__(kBlock) void k_cc_tile(const uint8_t* __restrict__ 
 
 // Neighbour pairs across tile edges: thread t of a tile's block takes edge
 // pixel t (its top row, then its left and right columns below the top row).
+// Along the top row the rule of k_cc_tile applies: the row's runs are joined
+// inside the tile already and so are the runs of the row above (inside its
+// tiles, or by the left-column unions of the tile holding their right part),
+// so a run's first pixel takes up-left, and up when up-left is off, and every
+// pixel takes up-right only when up is off.
 __global__ __launch_bounds__(128) void k_cc_edges(const uint8_t* __restrict__ B, int32_t W, int32_t H,
                                                   int32_t* parent) {
   const int x0 = blockIdx.x * kTileW, y0 = blockIdx.y * kTileH;
   const int t = threadIdx.x;
-  int lx, ly;
+  int lx = 0, ly = 0;
   if (t < kTileW) { lx = t; ly = 0; }
   else if (t < kTileW + kTileH - 1) { lx = 0; ly = t - kTileW + 1; }
   else if (t < kTileW + 2 * (kTileH - 1)) { lx = kTileW - 1; ly = t - kTileW - kTileH + 2; }
-  else return;
   const int x = x0 + lx, y = y0 + ly;
-  if (x >= W || y >= H) return;
+  const bool in = t < kTileW + 2 * (kTileH - 1) && x < W && y < H;
   const int32_t i = y * W + x;
-  if (!B[i]) return;
+  const bool on = in && B[i] != 0;
+  bool first = true;
+  if (t < kTileW) {   // wavefront 0 holds the top row (kTileW == 64)
+    const uint64_t row = __builtin_amdgcn_ballot_w64(on);
+    first = lx == 0 || ((row >> (lx - 1)) & 1ull) == 0;
+  }
+  if (!on) return;
   // raster-earlier neighbours that lie in another tile
   if (x > 0 && lx == 0 && B[i - 1]) uf_union(parent, i, i - 1);
   if (y > 0) {
     const int32_t u = i - W;
-    if (x > 0 && (lx == 0 || ly == 0) && B[u - 1]) uf_union(parent, i, u - 1);
-    if (ly == 0 && B[u]) uf_union(parent, i, u);
-    if (x + 1 < W && (ly == 0 || lx == kTileW - 1) && B[u + 1]) uf_union(parent, i, u + 1);
+    if (ly == 0) {
+      const bool ul = x > 0 && B[u - 1], uc = B[u] != 0, ur = x + 1 < W && B[u + 1];
+      if (first) {
+        if (ul) uf_union(parent, i, u - 1);
+        if (uc && !ul) uf_union(parent, i, u);
+      }
+      if (ur && !uc) uf_union(parent, i, u + 1);
+    } else {
+      if (lx == 0 && x > 0 && B[u - 1]) uf_union(parent, i, u - 1);
+      if (lx == kTileW - 1 && x + 1 < W && B[u + 1]) uf_union(parent, i, u + 1);
+    }
   }
 }
 
@@ -1374,11 +1392,21 @@ __global__ __launch_bounds__(kBlock) void k_rs_hist_cands(const int32_t* cand, c
   const int hi = shift + 8;
   const int64_t n = (int64_t)*ncand;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride) {
-    const unsigned long long key = mix64((unsigned long long)cand[k] ^ seed);
-    if (hi < 64 && (key >> hi) != (pre >> hi)) continue;
+  auto count = [&](int32_t px) {
+    const unsigned long long key = mix64((unsigned long long)px ^ seed);
+    if (hi < 64 && (key >> hi) != (pre >> hi)) return;
     atomicAdd(&mine[(uint32_t)((key >> shift) & 0xFF)], 1u);
+  };
+  // four candidates per 16-byte load (the list starts 256-byte aligned in
+  // the workspace), so few threads still keep several loads in flight
+  const int64_t nq = n >> 2;
+  const int4* cq = (const int4*)cand;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nq; q += stride) {
+    const int4 v = cq[q];
+    count(v.x); count(v.y); count(v.z); count(v.w);
   }
+  if (blockIdx.x == 0)
+    for (int64_t k = (nq << 2) + threadIdx.x; k < n; k += blockDim.x) count(cand[k]);
   __syncthreads();
   uint32_t t = 0;
   for (int k = 0; k < kHistCopies; ++k) t += h[k][threadIdx.x];
