@@ -657,10 +657,14 @@ __global__ __launch_bounds__(kBlock) void k_cc_tile(const uint8_t* __restrict__ 
   const int x0 = blockIdx.x * kTileW, y0 = blockIdx.y * kTileH;
   const int lx = threadIdx.x & (kTileW - 1);
   constexpr int kRowsPerPass = kBlock / kTileW;
+  // wavefront w takes the band of rows w kBand .. w kBand + kBand - 1, one
+  // row per pass, so a row's upward unions meet a row its own wavefront
+  // linked one pass before (short paths to the roots)
+  constexpr int kBand = kTileH / kRowsPerPass;
   bool on[kTileH / kRowsPerPass], first[kTileH / kRowsPerPass];
 #pragma unroll
   for (int j = 0; j < kTileH / kRowsPerPass; ++j) {
-    const int ly = (int)(threadIdx.x / kTileW) + kRowsPerPass * j;
+    const int ly = (int)(threadIdx.x / kTileW) * kBand + j;
     const int x = x0 + lx, y = y0 + ly;
     on[j] = x < W && y < H && B[(int64_t)y * W + x] != 0;
     // a wavefront holds one tile row (kTileW == 64): each pixel links
@@ -678,7 +682,7 @@ __global__ __launch_bounds__(kBlock) void k_cc_tile(const uint8_t* __restrict__ 
 #pragma unroll
   for (int j = 0; j < kTileH / kRowsPerPass; ++j) {
     if (!on[j]) continue;
-    const int ly = (int)(threadIdx.x / kTileW) + kRowsPerPass * j;
+    const int ly = (int)(threadIdx.x / kTileW) * kBand + j;
     const int l = ly * kTileW + lx;
     // the tile's neighbours before this pixel in raster order (8-connectivity;
     // the left one is in its run already). Above: one union per horizontal
@@ -701,7 +705,7 @@ __global__ __launch_bounds__(kBlock) void k_cc_tile(const uint8_t* __restrict__ 
   // separate pass initialises the forest
 #pragma unroll
   for (int j = 0; j < kTileH / kRowsPerPass; ++j) {
-    const int ly = (int)(threadIdx.x / kTileW) + kRowsPerPass * j;
+    const int ly = (int)(threadIdx.x / kTileW) * kBand + j;
     if (x0 + lx >= W || y0 + ly >= H) continue;
     int32_t gp = -1;
     if (on[j]) {
@@ -715,7 +719,7 @@ __global__ __launch_bounds__(kBlock) void k_cc_tile(const uint8_t* __restrict__ 
   // each tile root's local component size, at the root (0 everywhere else)
 #pragma unroll
   for (int j = 0; j < kTileH / kRowsPerPass; ++j) {
-    const int ly = (int)(threadIdx.x / kTileW) + kRowsPerPass * j;
+    const int ly = (int)(threadIdx.x / kTileW) * kBand + j;
     const int l = ly * kTileW + lx;
     if (x0 + lx < W && y0 + ly < H) size[(int64_t)(y0 + ly) * W + x0 + lx] = on[j] ? lsz[l] : 0;
   }
